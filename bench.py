@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP64 matrix-free action on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--all] [--no-cpu-baseline]
+
+A step is one full action y = A(u) (gather, geometry, evaluation, pointwise form,
+quadrature, colour-ordered scatter) over the whole mesh, inputs resident in HBM.  The
+default workload is the 2D P4 compressible neo-Hookean residual on the 512x512 unit
+square (524288 triangles, 8,396,802 DoFs, quadrature degree 8).  Prints ONE JSON line.
+
+Roofline: the kernel is bound by FP64 vector arithmetic (its arithmetic intensity is far
+above the 9.8 flop/byte ridge), so `roofline` reports achieved FP64 flop/s of the
+algorithmic flop count (the plain per-cell quadrature loop, counted per cell below)
+against the 78.6 TFLOP/s FP64 vector peak.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+# ----------------------------------------------------------------------- cost model
+def flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
+    """Algorithmic FP64 flops of one cell of the plain quadrature loop (FMA = 2)."""
+    d = dim
+    if d == 2:
+        geo = 4 + 3 + 1 + 4 + 1          # J (4 sub), det (3), 1/det, K (4 mul), |det|
+    else:
+        geo = 9 + 17 + 1 + 9 * 5 + 1     # J, det by cofactors, 1/det, adjugate*inv, |det|
+    if form == 0:                        # mass: eval 2n, weight 2, contraction 2n
+        per_q = 2 * nloc + 2 + 2 * nloc
+        return geo + nq * per_q
+    ev = 2 * d * d * nloc                # reference gradients of the d components
+    ct = 2 * d * d * nloc                # contraction against the test gradients
+    geo_q = 2 * d ** 3 + (2 * d ** 3 + d * d) + 1   # G = gref K, T = W S K^T, W
+    if form == 1:
+        pw = d + 3 * d * d + d           # trace, mu (G + G^T), lam tr on diagonal
+    else:
+        inv = 3 + 1 + 4 if d == 2 else 17 + 1 + 45
+        pw = d + inv + 1 + 2 + 2 * d * d  # F = I + G, inverse, log, lam ln J - mu, P
+    return geo + nq * (ev + ct + geo_q + pw)
+
+
+def vjp_flops_per_cell(dim: int, nloc: int, nq: int) -> float:
+    d = dim
+    geo = 4 + 3 + 1 + 4 + 1 if d == 2 else 9 + 17 + 1 + 45 + 1
+    ev = 2 * (2 * d * d * nloc)          # gradients of u and v
+    ct = 2 * d * d * nloc
+    geo_q = 2 * (2 * d ** 3) + (2 * d ** 3 + d * d) + 1
+    inv = 3 + 1 + 4 if d == 2 else 17 + 1 + 45
+    pw = d + inv + 1 + 2 + 2 * d ** 3 + d + 2 * d ** 3 + 4 * d * d
+    return geo + nq * (ev + ct + geo_q + pw)
+
+
+def footprint_bytes(dim, n_vert, n_cell, nloc, n_dof, vectors=2) -> float:
+    """Each DoF, coordinate and map entry counted once."""
+    return 8.0 * n_dof * vectors + 8.0 * dim * n_vert + 4.0 * nloc * n_cell + 4.0 * (dim + 1) * n_cell
+
+
+# ----------------------------------------------------------------------- timing
+def time_steps(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    return ms, wall
+
+
+def cold_flush(buf):
+    """Stream a buffer larger than the 256 MB MALL so that the next step starts cold."""
+    buf.add_(1.0)
+
+
+def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bool = False):
+    import torch
+    import meshgen
+    import paper_2506_17471_amd as fx
+
+    w = meshgen.workload(name)
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    u = torch.as_tensor(w.u, device="cuda")
+    y = torch.empty_like(u)
+    if vjp:
+        v = torch.as_tensor(w.v if w.v is not None else np.random.default_rng(9).uniform(-1, 1, w.n_dof),
+                            device="cuda")
+        fn = lambda: plan.vjp(u, v, out=y)  # noqa: E731
+    else:
+        fn = lambda: plan.action(u, out=y)  # noqa: E731
+    if cold:
+        flush = torch.zeros(160 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 1.25 GiB
+
+        def fn_cold(f=fn):
+            cold_flush(flush)
+            f()
+        # time only the action: events around fn, flush outside
+        import torch as _t
+        for _ in range(warmup):
+            fn()
+        _t.cuda.synchronize()
+        ms = []
+        st = _t.cuda.current_stream()
+        for _ in range(steps):
+            cold_flush(flush)
+            a, b = _t.cuda.Event(enable_timing=True), _t.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            _t.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        ms = np.array(ms)
+        wall = float(ms.sum()) / 1e3
+    else:
+        ms, wall = time_steps(fn, steps, warmup)
+    nv = w.mesh.n_vert
+    if vjp and w.form == 2:
+        fl = vjp_flops_per_cell(w.mesh.dim, plan.n_loc, plan.n_quad)
+    else:
+        fl = flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad)
+    info = dict(workload=name, n_cell=w.mesh.n_cell, n_dof=w.n_dof, n_loc=plan.n_loc,
+                n_quad=plan.n_quad, n_colours=plan.n_colours,
+                flops_per_cell=fl, flops=fl * w.mesh.n_cell,
+                bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
+                                      3 if vjp and w.form == 2 else 2),
+                ms_mean=float(ms.mean()), ms_median=float(np.median(ms)), ms_min=float(ms.min()),
+                wall_s=wall)
+    t = info["ms_mean"] / 1e3
+    info["dof_per_s"] = w.n_dof / t
+    info["tflops"] = info["flops"] / t / 1e12
+    info["hbm_gbs_footprint"] = info["bytes"] / t / 1e9
+    return info, w, plan
+
+
+def cpu_baseline(w, max_cells: int = 65536):
+    """The oracle (single thread) on the first `max_cells` cells of the same mesh."""
+    import oracle
+    import meshgen
+    m = w.mesh
+    nc = min(max_cells, m.n_cell)
+    sub = meshgen.Mesh(m.dim, m.n, m.k, m.coords, m.cell_verts[:nc], m.cell_nodes[:nc], m.n_node, m.h)
+    oracle.action(w.form, sub, w.u, w.quad_degree, w.params)     # warm (tables, library)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.action(w.form, sub, w.u, w.quad_degree, w.params)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    dofs_per_cell = w.n_dof / m.n_cell
+    return {"value": nc * dofs_per_cell / dt, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nc} of {m.n_cell} cells of the same mesh, {reps} runs, "
+                      f"{dt * 1e3:.1f} ms each; DoF/s scaled by DoFs per cell of the full mesh"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="nh_p4_2d")
+    ap.add_argument("--all", action="store_true", help="also time the other workloads")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the action "
+              f"shards by cells across GPUs, which this build does not run)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    main_info, w, plan = run_workload(args.workload, args.steps, args.warmup)
+    print(f"# {args.workload}: {main_info['ms_mean']:.4f} ms/step", file=sys.stderr, flush=True)
+    extras = {}
+    if w.form == 2:
+        vinfo, _, _ = run_workload(args.workload, args.steps, args.warmup, vjp=True)
+        extras["vjp"] = vinfo
+        extras["adjoint_forward_time_ratio"] = vinfo["ms_mean"] / main_info["ms_mean"]
+        print(f"# vjp: {vinfo['ms_mean']:.4f} ms/step", file=sys.stderr, flush=True)
+    if args.all:
+        for name in ("mass_p2_2d", "mass_p2_2d_1024", "elast_p2_3d"):
+            info, _, _ = run_workload(name, args.steps, args.warmup)
+            extras[name] = info
+            print(f"# {name}: {info['ms_mean']:.4f} ms/step", file=sys.stderr, flush=True)
+        info, _, _ = run_workload("mass_p2_2d_1024", args.steps, args.warmup, cold=True)
+        extras["mass_p2_2d_1024_cold"] = info
+
+    t = main_info["ms_mean"] / 1e3
+    achieved = main_info["tflops"]
+    n_launch = plan.n_colours
+    out = {
+        "metric": "FP64 FE action DoF/s",
+        "value": main_info["dof_per_s"],
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_info["ms_mean"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_cell": main_info["n_cell"],
+                   "n_dof": main_info["n_dof"], "n_quad": main_info["n_quad"],
+                   "n_colours": main_info["n_colours"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "vector_kernel (neo-Hookean, 2D, P4)",
+                     "launches_per_step": n_launch,
+                     "avg_launch_ms": main_info["ms_mean"] / n_launch,
+                     "footprint_gbs": main_info["hbm_gbs_footprint"]},
+        "extras": extras,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,153 @@
+/*
+ * femx -- matrix-free finite element actions on AMD Instinct MI355X (gfx950), FP64.
+ *
+ * C ABI of the library.  The operation is the matrix-free action of a finite element
+ * operator on affine simplex meshes (paper Sec. 2.2, the action written as a sum of cell
+ * integrals through the local-to-global maps and the reference-cell substitution, then
+ * replaced by quadrature; Sec. 2.3, the generic action kernel: gather, Jacobian and
+ * determinant, evaluation at quadrature points, pointwise form, quadrature contraction,
+ * scatter-add).  Forms follow App. A: mass, linear elasticity, and the hyperelastic
+ * residual with a compressible neo-Hookean energy.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Reference simplex {xi >= 0, sum xi <= 1}; P_k Lagrange basis with equispaced nodes
+ *   xi = alpha/k, |alpha| <= k.  Local node order (the columns of cell_nodes): first
+ *   coordinate fastest, i.e. 2D  for j in 0..k: for i in 0..k-j: (i, j);
+ *   3D  for l: for j: for i (i + j + l <= k).  n_loc = C(k + d, d).
+ * - Geometry is affine: J = [x_1 - x_0 | ... | x_d - x_0] from the cell's vertices in
+ *   cell_verts order; integrals use |det J| (cells with det J < 0 in 3D are valid).
+ * - Quadrature: the conical-product (collapsed Gauss-Jacobi) rule with
+ *   ceil((quad_degree + 1)/2) points per direction, exact to quad_degree.
+ * - Vectors are node-major interleaved: component c of node n at index n * ncomp + c,
+ *   ncomp = 1 for the mass form and d for the vector forms.
+ * - Host arrays are read during the call only.  Device arrays (u, v, y, g) are caller-
+ *   owned device memory (e.g. PyTorch CUDA tensors); the library never frees them.
+ * - Kernels are enqueued on the caller's HIP stream (hipStream_t passed as void*, NULL =
+ *   the default stream); fem_action and fem_action_vjp do not synchronise.
+ * - Every function returns FEM_OK (0) or a negative status; fem_last_error() returns a
+ *   thread-local message for the last failure.  No C++ exception crosses the ABI.
+ * - Results are deterministic: the scatter-add runs in colour order (a greedy colouring
+ *   of cells sharing a node), never by atomics.
+ */
+#ifndef FEM_ACTION_H
+#define FEM_ACTION_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* form ids */
+#define FEM_MASS 0        /* a(u, v) = int u v                                        */
+#define FEM_ELASTICITY 1  /* a(u, v) = int sigma(u) : eps(v),
+                             sigma = lambda tr(eps) I + 2 mu eps,  params {lambda, mu} */
+#define FEM_NEOHOOKEAN 2  /* r(u; v) = int P(F) : grad v,  F = I + grad u,
+                             P = mu (F - F^{-T}) + lambda ln(det F) F^{-T}
+                             (energy mu/2 (tr F^T F - d) - mu ln J + lambda/2 ln^2 J),
+                             params {lambda, mu}                                     */
+
+/* status codes */
+#define FEM_OK 0
+#define FEM_E_ARG (-1)          /* null pointer, negative size, bad layout argument     */
+#define FEM_E_UNSUPPORTED (-2)  /* form / dimension / degree / quadrature not built     */
+#define FEM_E_INDEX (-3)        /* a map entry is outside [0, n_vert) or [0, n_node)     */
+#define FEM_E_INVERTED (-4)     /* det J == 0, or det J < 0 for a 2D cell               */
+#define FEM_E_HIP (-5)          /* a HIP runtime call failed (message has the HIP error) */
+#define FEM_E_NOMEM (-6)        /* device or host allocation failed                     */
+
+typedef struct fem_plan fem_plan;
+
+/*
+ * Build a plan: validates the mesh, tabulates the reference basis at the quadrature
+ * points (paper Sec. 2.2, tabulated-values equation), colours the cells (greedy first-
+ * fit in ascending cell id; two cells conflict when they share a node of cell_nodes),
+ * and uploads colour-sorted copies of the maps and the coordinates to the current HIP
+ * device.  Synchronous; allocates device memory owned by the plan.
+ *
+ *   form         FEM_MASS, FEM_ELASTICITY or FEM_NEOHOOKEAN
+ *   dim          2 (triangles) or 3 (tetrahedra)
+ *   degree       polynomial degree k: 1..6 in 2D, 1..4 in 3D
+ *   quad_degree  degree the rule integrates exactly: 0..20
+ *   coords       HOST f64 [n_vert][dim]
+ *   cell_verts   HOST i32 [n_cell][dim+1]   vertex ids, the affine map's vertex order
+ *   cell_nodes   HOST i32 [n_cell][n_loc]   node ids in the local order above
+ *   n_node       number of nodes; vectors have n_node * ncomp entries
+ *   params       HOST f64 [n_params]: {lambda, mu} for the vector forms, unused for mass
+ * Errors: FEM_E_ARG, FEM_E_UNSUPPORTED, FEM_E_INDEX, FEM_E_INVERTED, FEM_E_HIP,
+ * FEM_E_NOMEM.  On error *out is set to NULL and nothing is leaked.
+ */
+int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degree,
+                    int64_t n_vert, const double *coords, int64_t n_cell,
+                    const int32_t *cell_verts, const int32_t *cell_nodes, int64_t n_node,
+                    const double *params, int n_params);
+
+/* Release a plan and its device memory (NULL is a no-op).  Synchronises the device
+ * before freeing so that no enqueued launch still reads the plan's arrays. */
+void fem_plan_destroy(fem_plan *plan);
+
+/*
+ * y = A(u): the operator action (paper Sec. 2.3, generic action kernel; App. A forms).
+ * For FEM_NEOHOOKEAN this is the nonlinear residual r(u).
+ *   u  DEVICE f64 [n_node * ncomp]  input
+ *   y  DEVICE f64 [n_node * ncomp]  output, overwritten (not accumulated); must not alias u
+ * Asynchronous on `stream`.  Errors: FEM_E_ARG (null plan/pointer), FEM_E_HIP (launch).
+ * Non-finite output for FEM_NEOHOOKEAN if det F <= 0 at a quadrature point.
+ */
+int fem_action(const fem_plan *plan, const double *u, double *y, void *stream);
+
+/*
+ * g = (dA/du)^T v: vector-Jacobian product of the action at u.  For FEM_NEOHOOKEAN the
+ * tangent of the residual is contracted with grad v at every quadrature point, F being
+ * recomputed from u (nothing is stored between the forward and this call).  For the
+ * linear forms A is symmetric and independent of u, so g = A v and u is ignored.
+ *   u, v  DEVICE f64 [n_node * ncomp] inputs;  g DEVICE f64 [n_node * ncomp] output,
+ *   overwritten; g must alias neither u nor v.  Asynchronous.  Errors as fem_action.
+ */
+int fem_action_vjp(const fem_plan *plan, const double *u, const double *v, double *g,
+                   void *stream);
+
+/* Plan properties (all outputs optional, pass NULL to skip). */
+int fem_plan_info(const fem_plan *plan, int *n_loc, int *ncomp, int *n_quad, int *n_colours,
+                  int64_t *n_dof);
+
+/* Colour of every cell in the caller's cell order: HOST i32 [n_cell] out. */
+int fem_plan_colouring(const fem_plan *plan, int32_t *colour);
+
+/*
+ * The plan's colouring on the host alone (no device needed): greedy first-fit over cells
+ * in ascending id, a cell taking the smallest colour not held by an earlier cell that
+ * shares one of its nodes.  The paper scatters with atomic adds (Sec. 4.1, single cell
+ * per work-item; Sec. 4.2, tiled kernel); the colouring replaces them so that the sum
+ * into each node runs in a fixed order.
+ *   cell_nodes HOST i32 [n_cell][n_loc] (n_loc <= 64);  colour HOST i32 [n_cell] out;
+ *   n_colours  HOST out (may be NULL).
+ * Errors: FEM_E_ARG (sizes, nulls), FEM_E_INDEX, FEM_E_UNSUPPORTED (> 1024 colours).
+ */
+int fem_colouring(int64_t n_cell, int n_loc, const int32_t *cell_nodes, int64_t n_node,
+                  int32_t *colour, int32_t *n_colours);
+
+/*
+ * Reference tables as used by the kernels (for testing the tabulation): HOST outputs
+ *   points [n_quad][dim], weights [n_quad], phi [n_quad][n_loc],
+ *   dphi [n_quad][n_loc][dim] (derivatives in the reference coordinates xi).
+ * Call with points == NULL to get n_quad and n_loc only.
+ */
+int fem_reference_tables(int dim, int degree, int quad_degree, int *n_quad, int *n_loc,
+                         double *points, double *weights, double *phi, double *dphi);
+
+/* Launch tuning: cells per workgroup (64, 128 or 256).  0 restores the default.
+ * Errors: FEM_E_ARG for any other value. */
+int fem_plan_set_block(fem_plan *plan, int cells_per_block);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *fem_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int fem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEM_ACTION_H */

@@ -1,0 +1,244 @@
+"""femx: matrix-free FP64 finite element actions on MI355X (gfx950).
+
+A thin ctypes binding over the C ABI in ``include/fem_action.h`` (``libfemx.so``).
+PyTorch supplies device memory and the current HIP stream; every step of the action runs
+in the library's HIP kernels.  There is no CPU fallback: if the library is missing the
+import of :func:`lib` raises.
+
+    plan = Plan(FORM_NEOHOOKEAN, dim=2, degree=4, quad_degree=8, coords=..., cell_verts=...,
+                cell_nodes=..., n_node=..., params=(lam, mu))
+    y = plan.action(u)                 # u: float64 CUDA tensor [n_node * ncomp]
+    g = plan.vjp(u, v)                 # (dA/du)^T v
+    y = FemAction.apply(u, plan)       # autograd: backward calls the VJP kernel
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+__all__ = ["FORM_MASS", "FORM_ELASTICITY", "FORM_NEOHOOKEAN", "FemError", "Plan", "FemAction",
+           "lib", "reference_tables", "colouring", "LIB_PATH"]
+
+FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN = 0, 1, 2
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfemx.so")
+
+_STATUS = {0: "FEM_OK", -1: "FEM_E_ARG", -2: "FEM_E_UNSUPPORTED", -3: "FEM_E_INDEX",
+           -4: "FEM_E_INVERTED", -5: "FEM_E_HIP", -6: "FEM_E_NOMEM"}
+
+_lib = None
+
+
+class FemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfemx.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2506_17471_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    L.fem_plan_create.argtypes = [ctypes.POINTER(P), i32, i32, i32, i32, i64, P, i64, P, P, i64, P, i32]
+    L.fem_plan_create.restype = i32
+    L.fem_plan_destroy.argtypes = [P]
+    L.fem_plan_destroy.restype = None
+    L.fem_action.argtypes = [P, P, P, P]
+    L.fem_action.restype = i32
+    L.fem_action_vjp.argtypes = [P, P, P, P, P]
+    L.fem_action_vjp.restype = i32
+    L.fem_plan_info.argtypes = [P, P, P, P, P, P]
+    L.fem_plan_info.restype = i32
+    L.fem_plan_colouring.argtypes = [P, P]
+    L.fem_plan_colouring.restype = i32
+    L.fem_reference_tables.argtypes = [i32, i32, i32, P, P, P, P, P, P]
+    L.fem_reference_tables.restype = i32
+    L.fem_plan_set_block.argtypes = [P, i32]
+    L.fem_plan_set_block.restype = i32
+    L.fem_colouring.argtypes = [i64, i32, P, i64, P, P]
+    L.fem_colouring.restype = i32
+    L.fem_last_error.argtypes = []
+    L.fem_last_error.restype = ctypes.c_char_p
+    L.fem_version.argtypes = []
+    L.fem_version.restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise FemError(status, lib().fem_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def reference_tables(dim: int, degree: int, quad_degree: int):
+    """The library's quadrature rule and tabulation: (points, weights, phi, dphi)."""
+    L = lib()
+    nq, nl = ctypes.c_int(), ctypes.c_int()
+    _check(L.fem_reference_tables(dim, degree, quad_degree, ctypes.byref(nq), ctypes.byref(nl),
+                                  None, None, None, None))
+    pts = np.empty((nq.value, dim))
+    w = np.empty(nq.value)
+    phi = np.empty((nq.value, nl.value))
+    dphi = np.empty((nq.value, nl.value, dim))
+    _check(L.fem_reference_tables(dim, degree, quad_degree, None, None, _np_ptr(pts), _np_ptr(w),
+                                  _np_ptr(phi), _np_ptr(dphi)))
+    return pts, w, phi, dphi
+
+
+def colouring(cell_nodes, n_node: int):
+    """The library's host colouring: (colour [n_cell] int32, n_colours)."""
+    L = lib()
+    cn = np.ascontiguousarray(cell_nodes, dtype=np.int32)
+    out = np.empty(cn.shape[0], dtype=np.int32)
+    nc = ctypes.c_int32()
+    _check(L.fem_colouring(cn.shape[0], cn.shape[1], _np_ptr(cn), int(n_node), _np_ptr(out),
+                           ctypes.byref(nc)))
+    return out, nc.value
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_ptr(t, n: int, name: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} entries")
+    return t.data_ptr()
+
+
+class Plan:
+    """A mesh + form + quadrature, validated, coloured and resident on the current device."""
+
+    def __init__(self, form: int, dim: int, degree: int, quad_degree: int, coords, cell_verts,
+                 cell_nodes, n_node: int, params=()):
+        L = lib()
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        cell_verts = np.ascontiguousarray(cell_verts, dtype=np.int32)
+        cell_nodes = np.ascontiguousarray(cell_nodes, dtype=np.int32)
+        prm = np.ascontiguousarray(params, dtype=np.float64)
+        if coords.ndim != 2 or coords.shape[1] != dim:
+            raise ValueError("coords must be [n_vert, dim]")
+        if cell_verts.ndim != 2 or cell_verts.shape[1] != dim + 1:
+            raise ValueError("cell_verts must be [n_cell, dim+1]")
+        n_loc = math.comb(degree + dim, dim) if degree >= 0 and dim >= 0 else -1
+        if cell_nodes.ndim != 2 or cell_nodes.shape != (cell_verts.shape[0], n_loc):
+            raise ValueError(f"cell_nodes must be [n_cell, {n_loc}] for degree {degree}")
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(L.fem_plan_create(ctypes.byref(h), form, dim, degree, quad_degree,
+                                 coords.shape[0], _np_ptr(coords), cell_verts.shape[0],
+                                 _np_ptr(cell_verts), _np_ptr(cell_nodes), int(n_node),
+                                 _np_ptr(prm) if prm.size else None, int(prm.size)))
+        self._h = h
+        self.form, self.dim, self.degree, self.quad_degree = form, dim, degree, quad_degree
+        self.n_cell = cell_verts.shape[0]
+        nl, nc, nq, ncol, nd = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(),
+                                ctypes.c_int64())
+        _check(L.fem_plan_info(h, ctypes.byref(nl), ctypes.byref(nc), ctypes.byref(nq),
+                               ctypes.byref(ncol), ctypes.byref(nd)))
+        self.n_loc, self.ncomp, self.n_quad, self.n_colours, self.n_dof = (
+            nl.value, nc.value, nq.value, ncol.value, nd.value)
+
+    @classmethod
+    def from_mesh(cls, form: int, mesh, quad_degree: int, params=()):
+        return cls(form, mesh.dim, mesh.k, quad_degree, mesh.coords, mesh.cell_verts,
+                   mesh.cell_nodes, mesh.n_node, params)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fem_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_block(self, cells_per_block: int):
+        _check(lib().fem_plan_set_block(self.handle, cells_per_block))
+
+    def colouring(self) -> np.ndarray:
+        out = np.empty(self.n_cell, dtype=np.int32)
+        _check(lib().fem_plan_colouring(self.handle, _np_ptr(out)))
+        return out
+
+    def action(self, u, out=None, stream=None):
+        """y = A(u) on the current stream (asynchronous)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(u)
+        _check(lib().fem_action(self.handle, _dev_ptr(u, self.n_dof, "u"),
+                                _dev_ptr(out, self.n_dof, "y"), _stream_handle(stream)))
+        return out
+
+    def vjp(self, u, v, out=None, stream=None):
+        """g = (dA/du)^T v on the current stream (asynchronous)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(v)
+        _check(lib().fem_action_vjp(self.handle, _dev_ptr(u, self.n_dof, "u"),
+                                    _dev_ptr(v, self.n_dof, "v"),
+                                    _dev_ptr(out, self.n_dof, "g"), _stream_handle(stream)))
+        return out
+
+
+def _autograd_function():
+    import torch
+
+    class _FemAction(torch.autograd.Function):
+        """y = A(u); backward g = (dA/du)^T grad_y, recomputing quadrature states from u."""
+
+        @staticmethod
+        def forward(ctx, u, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(u)
+            return plan.action(u.contiguous())
+
+        @staticmethod
+        def backward(ctx, gy):
+            (u,) = ctx.saved_tensors
+            return ctx.plan.vjp(u.contiguous(), gy.contiguous()), None
+
+    return _FemAction
+
+
+class _LazyFemAction:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _LazyFemAction._fn is None:
+            _LazyFemAction._fn = _autograd_function()
+        return getattr(_LazyFemAction._fn, name)
+
+
+FemAction = _LazyFemAction()

@@ -1,0 +1,118 @@
+"""C-ABI checks that need no GPU: exported symbols, the host-side steps of the plan
+(reference tabulation and quadrature, colouring) against the oracle, and error paths."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+import paper_2506_17471_amd as fx
+from oracle import basis, quadrature
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "fem_action.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(fem_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert {"fem_action", "fem_action_vjp", "fem_plan_create"} <= set(names)
+    L = fx.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert fx.lib().fem_version() >= 100
+
+
+@pytest.mark.parametrize("dim,k,qd", [(2, 1, 2), (2, 2, 4), (2, 3, 6), (2, 4, 8), (2, 6, 12),
+                                      (3, 1, 2), (3, 2, 2), (3, 2, 4), (3, 4, 6)])
+def test_reference_tables_match_oracle(dim, k, qd):
+    pts, w, phi, dphi = fx.reference_tables(dim, k, qd)
+    opts, ow = quadrature.stroud(dim, qd)
+    ophi, odphi = basis.tabulate(dim, k, opts)
+    assert pts.shape == opts.shape
+    assert np.max(np.abs(pts - opts)) < 1e-15
+    assert np.max(np.abs(w - ow) / ow) < 1e-14
+    assert np.max(np.abs(phi - ophi)) < 1e-13
+    assert np.max(np.abs(dphi - odphi)) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n,k", [(2, 16, 2), (2, 7, 4), (3, 4, 2), (3, 3, 3)])
+def test_colouring_bit_exact_with_oracle(dim, n, k):
+    m = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(0))
+    col, nc = fx.colouring(m.cell_nodes, m.n_node)
+    ocol, onc = oracle.colouring(m.cell_nodes, m.n_node)
+    assert nc == onc
+    assert np.array_equal(col, ocol)
+
+
+def test_colouring_full_size_valid():
+    # at full size: the property (no two cells of one colour share a node), checked
+    # vectorised per colour, plus the colour count of the oracle on the same mesh
+    w = meshgen.workload("nh_p4_2d", n=128)
+    col, nc = fx.colouring(w.mesh.cell_nodes, w.mesh.n_node)
+    for c in range(nc):
+        nodes = w.mesh.cell_nodes[col == c].ravel()
+        assert len(np.unique(nodes)) == len(nodes)
+    _, onc = oracle.colouring(w.mesh.cell_nodes, w.mesh.n_node)
+    assert nc == onc
+
+
+def _create(form=0, dim=2, degree=2, qd=4, mesh=None, params=(), **over):
+    L = fx.lib()
+    m = mesh or meshgen.unit_square(2, degree)
+    coords = np.ascontiguousarray(over.get("coords", m.coords), dtype=np.float64)
+    cv = np.ascontiguousarray(over.get("cell_verts", m.cell_verts), dtype=np.int32)
+    cn = np.ascontiguousarray(over.get("cell_nodes", m.cell_nodes), dtype=np.int32)
+    prm = np.asarray(params, dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = L.fem_plan_create(ctypes.byref(h), form, dim, degree, qd, coords.shape[0],
+                           coords.ctypes.data if over.get("null_coords") is None else None,
+                           cv.shape[0], cv.ctypes.data, cn.ctypes.data,
+                           over.get("n_node", m.n_node),
+                           prm.ctypes.data if prm.size else None, prm.size)
+    if st == 0:
+        L.fem_plan_destroy(h)
+    return st, L.fem_last_error().decode()
+
+
+def test_error_paths_from_host():
+    assert _create(form=7)[0] == -2
+    assert _create(dim=4)[0] == -2
+    assert _create(degree=9)[0] == -2
+    assert _create(qd=50)[0] == -2
+    assert _create(null_coords=True)[0] == -1
+    assert _create(form=1, params=())[0] == -1                     # vector form, no params
+    m = meshgen.unit_square(2, 2)
+    bad = m.cell_nodes.copy()
+    bad[3, 2] = m.n_node
+    assert _create(cell_nodes=bad)[0] == -3
+    badv = m.cell_verts.copy()
+    badv[0, 0] = -1
+    assert _create(cell_verts=badv)[0] == -3
+    inv = m.cell_verts.copy()
+    inv[1, [1, 2]] = inv[1, [2, 1]]                                 # clockwise triangle
+    st, msg = _create(cell_verts=inv)
+    assert st == -4 and "cell 1" in msg
+    L = fx.lib()
+    assert L.fem_action(None, None, None, None) == -1
+    assert L.fem_action_vjp(None, None, None, None, None) == -1
+    assert L.fem_plan_info(None, None, None, None, None, None) == -1
+
+
+def test_plan_without_device_reports_hip_error():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a device is present")
+    except ImportError:
+        pass
+    st, msg = _create()
+    assert st == -5 and "hipGetDevice" in msg

@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle (FP64).
+
+Bar: relative max error and relative L2 error <= 1e-12 against the oracle on the same
+seeded inputs (the forms are evaluated in FP64 on both sides, only the summation order
+differs), bit-exact for the colouring, bitwise-identical repeated runs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_17471_amd as fx  # noqa: E402
+
+TOL = 1e-12
+DEV = torch.device("cuda:0")
+NH = (10.0, 1.0)
+LAME = meshgen.lame_from_young(1.0, 0.3)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_err(y, ref):
+    y = np.asarray(y)
+    ref = np.asarray(ref)
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    return np.max(np.abs(y - ref)) / scale, np.linalg.norm(y - ref) / max(np.linalg.norm(ref), 1e-300)
+
+
+def gpu(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def params_for(form):
+    return () if form == fx.FORM_MASS else (LAME if form == fx.FORM_ELASTICITY else NH)
+
+
+def inputs(form, mesh, seed):
+    rng = np.random.default_rng(seed)
+    ncomp = 1 if form == fx.FORM_MASS else mesh.dim
+    if form == fx.FORM_NEOHOOKEAN:
+        u = meshgen.nh_displacement(rng, mesh, 0.01)
+        # an admissible state: det F > 0 at every quadrature point of the rule used
+        assert oracle.min_det_f(mesh, u, 2 * mesh.k) > 0.5
+    else:
+        u = rng.uniform(-1, 1, mesh.n_node * ncomp)
+    v = rng.uniform(-1, 1, mesh.n_node * ncomp)
+    return u, v
+
+
+def qdeg(form, k):
+    return 2 * (k - 1) if form == fx.FORM_ELASTICITY else 2 * k
+
+
+CASES = [(f, 2, k) for f in (0, 1, 2) for k in range(1, 7)] + \
+        [(f, 3, k) for f in (0, 1, 2) for k in range(1, 5)]
+
+
+@pytest.mark.parametrize("form,dim,k", CASES)
+def test_action_small_meshes(form, dim, k):
+    # 2D n=9: 162 cells; 3D n=3: 162 cells -- several wavefronts per colour plus a tail
+    n = 9 if dim == 2 else 3
+    mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(100 + k))
+    u, _ = inputs(form, mesh, k)
+    qd = qdeg(form, k)
+    say(f"[action] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd}")
+    plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    y = plan.action(gpu(u)).cpu().numpy()
+    ref = oracle.action(form, mesh, u, qd, params_for(form))
+    emax, el2 = rel_err(y, ref)
+    assert emax < TOL and el2 < TOL, (emax, el2)
+
+
+@pytest.mark.parametrize("form,dim,k", CASES)
+def test_vjp_small_meshes(form, dim, k):
+    n = 7 if dim == 2 else 2
+    mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(200 + k))
+    u, v = inputs(form, mesh, 50 + k)
+    qd = qdeg(form, k)
+    say(f"[vjp] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd}")
+    plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
+    ref = oracle.vjp(form, mesh, u, v, qd, params_for(form))
+    emax, el2 = rel_err(g, ref)
+    assert emax < TOL and el2 < TOL, (emax, el2)
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_block_sizes_bitwise_identical(block):
+    w = meshgen.workload("nh_p4_2d", n=24)
+    say(f"[block] nh_p4_2d n=24 block={block}")
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    u = gpu(w.u)
+    y0 = plan.action(u).cpu().numpy()
+    plan.set_block(block)
+    y1 = plan.action(u).cpu().numpy()
+    assert np.array_equal(y0, y1)
+
+
+def test_determinism_and_stream():
+    w = meshgen.workload("elast_p2_3d", n=6)
+    say("[determinism] elast_p2_3d n=6")
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    u = gpu(w.u)
+    y0 = plan.action(u)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        y1 = plan.action(u)
+    s.synchronize()
+    assert torch.equal(y0, y1)
+
+
+def test_colouring_matches_host_and_oracle():
+    w = meshgen.workload("nh_p4_2d", n=20)
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    col = plan.colouring()
+    ocol, nc = oracle.colouring(w.mesh.cell_nodes, w.mesh.n_node)
+    assert np.array_equal(col, ocol) and plan.n_colours == nc
+
+
+def test_empty_mesh_and_unused_nodes():
+    mesh = meshgen.unit_square(3, 2)
+    say("[edge] empty mesh")
+    empty = fx.Plan(fx.FORM_MASS, 2, 2, 4, mesh.coords, mesh.cell_verts[:0], mesh.cell_nodes[:0],
+                    mesh.n_node)
+    y = empty.action(gpu(np.ones(mesh.n_node)))
+    assert torch.count_nonzero(y).item() == 0
+    say("[edge] unused nodes")
+    extra = 5
+    plan = fx.Plan(fx.FORM_ELASTICITY, 2, 2, 2, mesh.coords, mesh.cell_verts, mesh.cell_nodes,
+                   mesh.n_node + extra, LAME)
+    u = np.random.default_rng(0).uniform(-1, 1, (mesh.n_node + extra) * 2)
+    out = gpu(np.full(len(u), 7.0))
+    plan.action(gpu(u), out=out)
+    y = out.cpu().numpy()
+    assert np.all(y[-2 * extra:] == 0)
+    ref = oracle.action(1, mesh, u[:-2 * extra], 2, LAME)
+    assert rel_err(y[:-2 * extra], ref)[0] < TOL
+
+
+def test_single_cell_and_ragged_counts():
+    for n in (1, 2, 5, 33):
+        mesh = meshgen.unit_square(n, 3, 0.1, np.random.default_rng(n))
+        if n == 1:
+            mesh.cell_verts = mesh.cell_verts[:1]
+            mesh.cell_nodes = mesh.cell_nodes[:1]
+        u, _ = inputs(0, mesh, n)
+        say(f"[ragged] mass P3 n={n} cells={mesh.n_cell}")
+        plan = fx.Plan.from_mesh(0, mesh, 6)
+        y = plan.action(gpu(u)).cpu().numpy()
+        ref = oracle.action(0, mesh, u, 6)
+        assert rel_err(y, ref)[0] < TOL
+
+
+FULL = ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d", "nh_vjp_p4_2d", "mass_p2_2d_1024"]
+
+
+@pytest.mark.parametrize("name", FULL)
+def test_full_size_against_oracle(name):
+    """Every output of the full-size workloads against the oracle (seconds on the host)."""
+    w = meshgen.workload(name)
+    say(f"[full] {name} cells={w.mesh.n_cell} dofs={w.n_dof}")
+    if w.form == fx.FORM_NEOHOOKEAN:
+        assert oracle.min_det_f(w.mesh, w.u, w.quad_degree) > 0.5
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    if w.v is not None:
+        out = plan.vjp(gpu(w.u), gpu(w.v)).cpu().numpy()
+        ref = oracle.vjp(w.form, w.mesh, w.u, w.v, w.quad_degree, w.params)
+    else:
+        out = plan.action(gpu(w.u)).cpu().numpy()
+        ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
+    emax, el2 = rel_err(out, ref)
+    say(f"[full] {name} rel_max={emax:.3e} rel_l2={el2:.3e}")
+    assert emax < TOL and el2 < TOL
+
+
+def test_autograd_function_matches_oracle_vjp():
+    w = meshgen.workload("nh_p4_2d", n=16)
+    say("[autograd] nh_p4_2d n=16")
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    u = gpu(w.u).requires_grad_(True)
+    rng = np.random.default_rng(3)
+    v = rng.uniform(-1, 1, w.n_dof)
+    y = fx.FemAction.apply(u, plan)
+    (y * gpu(v)).sum().backward()
+    ref = oracle.vjp(w.form, w.mesh, w.u, v, w.quad_degree, w.params)
+    assert rel_err(u.grad.cpu().numpy(), ref)[0] < TOL
+    assert rel_err(y.detach().cpu().numpy(),
+                   oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params))[0] < TOL
+
+
+def test_autograd_gradcheck_tiny():
+    mesh = meshgen.unit_square(2, 2, 0.1, np.random.default_rng(4))
+    u, _ = inputs(2, mesh, 4)
+    plan = fx.Plan.from_mesh(2, mesh, 4, NH)
+    say("[gradcheck] nh P2 2x2")
+    ut = gpu(u).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x: fx.FemAction.apply(x, plan), (ut,), eps=1e-6,
+                                    atol=1e-7, rtol=1e-6)
+
+
+@pytest.mark.parametrize("n,ncols", [(4, None), (16, 64)])
+def test_vjp_against_assembled_jacobian_transpose(n, ncols):
+    """J by central differences (h = 1e-6) of the GPU residual, column by column (all
+    columns at 4x4, a seeded sample of 64 at 16x16); (J^T v)_i = v . J[:, i] against the
+    VJP kernel."""
+    w = meshgen.workload("nh_p4_2d", n=n)
+    say(f"[jacobian] nh_p4_2d n={n}")
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    rng = np.random.default_rng(5)
+    v = rng.uniform(-1, 1, w.n_dof)
+    cols = np.arange(w.n_dof) if ncols is None else rng.choice(w.n_dof, ncols, replace=False)
+    h = 1e-6
+    ut, vt = gpu(w.u), gpu(v)
+    jtv = np.zeros(len(cols))
+    for j, i in enumerate(cols):
+        e = torch.zeros(w.n_dof, dtype=torch.float64, device=DEV)
+        e[i] = h
+        jtv[j] = torch.dot(vt, (plan.action(ut + e) - plan.action(ut - e)) / (2 * h)).item()
+    g = plan.vjp(ut, vt).cpu().numpy()[cols]
+    assert np.max(np.abs(jtv - g)) < 1e-6 * np.max(np.abs(g))
