@@ -27,8 +27,8 @@
  *   the default stream); fem_action and fem_action_vjp do not synchronise.
  * - Every function returns FEM_OK (0) or a negative status; fem_last_error() returns a
  *   thread-local message for the last failure.  No C++ exception crosses the ABI.
- * - Results are deterministic: the scatter-add runs in colour order (a greedy colouring
- *   of cells sharing a node), never by atomics.
+ * - Results are deterministic: the scatter-add never uses atomics; it runs in colour order
+ *   or in a fixed per-patch order (fem_plan_set_strategy).
  */
 #ifndef FEM_ACTION_H
 #define FEM_ACTION_H
@@ -137,9 +137,45 @@ int fem_colouring(int64_t n_cell, int n_loc, const int32_t *cell_nodes, int64_t 
 int fem_reference_tables(int dim, int degree, int quad_degree, int *n_quad, int *n_loc,
                          double *points, double *weights, double *phi, double *dphi);
 
-/* Launch tuning: cells per workgroup (64, 128 or 256).  0 restores the default.
- * Errors: FEM_E_ARG for any other value. */
+/* Launch tuning of the colour strategy: cells per workgroup (64, 128 or 256); 0 restores
+ * the default.  Errors: FEM_E_ARG for any other value. */
 int fem_plan_set_block(fem_plan *plan, int cells_per_block);
+
+/*
+ * Scatter strategy (both are deterministic; they sum in different fixed orders, so their
+ * results agree to rounding, and each is bitwise reproducible run to run):
+ *   FEM_SCATTER_COLOUR  one launch per colour of the greedy colouring; a lane owning a
+ *                       cell read-add-writes its nodes (no two cells of a launch share one).
+ *   FEM_SCATTER_PATCH   one launch over patches of `patch_cells` consecutive cells along a
+ *                       Morton curve of the cell centroids (64, 128 or 256; 0 = the largest
+ *                       whose element buffer fits 64 KB of LDS).  A workgroup stages its
+ *                       patch's nodal values in LDS, keeps the cell vectors in an LDS
+ *                       element buffer and sums every node in a fixed order; nodes that
+ *                       several patches hold are summed in patch order by a second, small
+ *                       kernel.  The default.
+ * Rebuilding patches synchronises the device.  Errors: FEM_E_ARG, FEM_E_UNSUPPORTED (the
+ * patch needs more than 160 KB of LDS), FEM_E_HIP, FEM_E_NOMEM.
+ */
+#define FEM_SCATTER_COLOUR 0
+#define FEM_SCATTER_PATCH 1
+int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells);
+int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells);
+
+/*
+ * Host-only check of the patch layout the library would build for this mesh (no device
+ * needed): every (cell, local node) contribution is summed exactly once into the node the
+ * map names, every index the kernels follow lies inside its buffer, and every shared node's
+ * partial slots are written once.  The same check runs inside fem_plan_create when the
+ * environment variable FEM_CHECK=1 is set.
+ *   stats HOST i64 [7] out (may be NULL): cells per patch, patches, most distinct nodes in a
+ *         patch, (patch, node) pairs, shared nodes, partial slots, LDS bytes per workgroup
+ *         for the forward kernel.
+ * Errors: FEM_E_ARG (including a layout violation), FEM_E_INDEX, FEM_E_INVERTED,
+ * FEM_E_UNSUPPORTED.
+ */
+int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const double *coords,
+                           int64_t n_cell, const int32_t *cell_verts, const int32_t *cell_nodes,
+                           int64_t n_node, int patch_cells, int64_t *stats);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *fem_last_error(void);

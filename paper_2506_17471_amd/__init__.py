@@ -20,9 +20,11 @@ import os
 import numpy as np
 
 __all__ = ["FORM_MASS", "FORM_ELASTICITY", "FORM_NEOHOOKEAN", "FemError", "Plan", "FemAction",
-           "lib", "reference_tables", "colouring", "LIB_PATH"]
+           "lib", "reference_tables", "colouring", "check_patch_layout", "LIB_PATH",
+           "SCATTER_COLOUR", "SCATTER_PATCH"]
 
 FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN = 0, 1, 2
+SCATTER_COLOUR, SCATTER_PATCH = 0, 1
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfemx.so")
 
 _STATUS = {0: "FEM_OK", -1: "FEM_E_ARG", -2: "FEM_E_UNSUPPORTED", -3: "FEM_E_INDEX",
@@ -66,6 +68,12 @@ def lib() -> ctypes.CDLL:
     L.fem_reference_tables.restype = i32
     L.fem_plan_set_block.argtypes = [P, i32]
     L.fem_plan_set_block.restype = i32
+    L.fem_plan_set_strategy.argtypes = [P, i32, i32]
+    L.fem_plan_set_strategy.restype = i32
+    L.fem_plan_get_strategy.argtypes = [P, P, P]
+    L.fem_plan_get_strategy.restype = i32
+    L.fem_check_patch_layout.argtypes = [i32, i32, i32, i64, P, i64, P, P, i64, i32, P]
+    L.fem_check_patch_layout.restype = i32
     L.fem_colouring.argtypes = [i64, i32, P, i64, P, P]
     L.fem_colouring.restype = i32
     L.fem_last_error.argtypes = []
@@ -109,6 +117,21 @@ def colouring(cell_nodes, n_node: int):
     _check(L.fem_colouring(cn.shape[0], cn.shape[1], _np_ptr(cn), int(n_node), _np_ptr(out),
                            ctypes.byref(nc)))
     return out, nc.value
+
+
+def check_patch_layout(form: int, mesh, patch_cells: int = 0) -> dict:
+    """Host-only validation of the patch layout for `mesh` (raises FemError on a violation)."""
+    L = lib()
+    xy = np.ascontiguousarray(mesh.coords, dtype=np.float64)
+    cv = np.ascontiguousarray(mesh.cell_verts, dtype=np.int32)
+    cn = np.ascontiguousarray(mesh.cell_nodes, dtype=np.int32)
+    st = np.zeros(7, dtype=np.int64)
+    _check(L.fem_check_patch_layout(form, mesh.dim, mesh.k, xy.shape[0], _np_ptr(xy), cv.shape[0],
+                                    _np_ptr(cv), _np_ptr(cn), int(mesh.n_node), patch_cells,
+                                    _np_ptr(st)))
+    keys = ["patch_cells", "n_patch", "max_patch_nodes", "patch_node_pairs", "shared_nodes",
+            "partial_slots", "lds_bytes"]
+    return dict(zip(keys, (int(x) for x in st)))
 
 
 def _stream_handle(stream) -> int:
@@ -186,6 +209,14 @@ class Plan:
 
     def set_block(self, cells_per_block: int):
         _check(lib().fem_plan_set_block(self.handle, cells_per_block))
+
+    def set_strategy(self, strategy: int, patch_cells: int = 0):
+        _check(lib().fem_plan_set_strategy(self.handle, strategy, patch_cells))
+
+    def strategy(self):
+        st, pc = ctypes.c_int(), ctypes.c_int()
+        _check(lib().fem_plan_get_strategy(self.handle, ctypes.byref(st), ctypes.byref(pc)))
+        return st.value, pc.value
 
     def colouring(self) -> np.ndarray:
         out = np.empty(self.n_cell, dtype=np.int32)

@@ -1,0 +1,276 @@
+// Device-side pieces of the per-cell computation shared by the launch strategies:
+// affine geometry, the pointwise forms, and the evaluation -> pointwise -> quadrature loop
+// over the quadrature points of one cell (paper Sec. 2.3: the generic action kernel's
+// per-cell body; App. A: the forms).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/fem_action.h"
+
+#define FEMX_CONSTANT __attribute__((address_space(4)))
+
+namespace femx {
+
+__host__ __device__ constexpr int nloc_of(int dim, int k)
+{
+    return dim == 2 ? (k + 1) * (k + 2) / 2 : (k + 1) * (k + 2) * (k + 3) / 6;
+}
+
+// doubles per quadrature-point record of the kernel table (see table_record())
+__host__ __device__ constexpr int record_of(int form, int dim, int nloc)
+{
+    return (((form == FEM_MASS ? nloc : dim * nloc) + 1) + 1) & ~1;
+}
+
+// K = J^{-1} and |det J| from the vertex coordinates (J[i][r] = x_{r+1,i} - x_{0,i}).
+template <int DIM>
+__device__ __forceinline__ double affine_geometry(const double (&x)[DIM + 1][DIM],
+                                                  double (&K)[DIM][DIM])
+{
+    double J[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) J[i][r] = x[r + 1][i] - x[0][i];
+    if constexpr (DIM == 2) {
+        const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double inv = 1.0 / det;
+        K[0][0] = J[1][1] * inv;
+        K[0][1] = -J[0][1] * inv;
+        K[1][0] = -J[1][0] * inv;
+        K[1][1] = J[0][0] * inv;
+        return fabs(det);
+    } else {
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        const double inv = 1.0 / det;
+        K[0][0] = c00 * inv;
+        K[1][0] = c01 * inv;
+        K[2][0] = c02 * inv;
+        K[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * inv;
+        K[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * inv;
+        K[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * inv;
+        K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * inv;
+        K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * inv;
+        K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * inv;
+        return fabs(det);
+    }
+}
+
+// A^{-1} and det A for a small matrix.
+template <int DIM>
+__device__ __forceinline__ double invert(const double (&A)[DIM][DIM], double (&B)[DIM][DIM])
+{
+    if constexpr (DIM == 2) {
+        const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        const double inv = 1.0 / det;
+        B[0][0] = A[1][1] * inv;
+        B[0][1] = -A[0][1] * inv;
+        B[1][0] = -A[1][0] * inv;
+        B[1][1] = A[0][0] * inv;
+        return det;
+    } else {
+        const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+        const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+        const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+        const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+        const double inv = 1.0 / det;
+        B[0][0] = c00 * inv;
+        B[1][0] = c01 * inv;
+        B[2][0] = c02 * inv;
+        B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * inv;
+        B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * inv;
+        B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * inv;
+        B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * inv;
+        B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * inv;
+        B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * inv;
+        return det;
+    }
+}
+
+// physical gradient G[c][j] = sum_r gref[c][r] K[r][j]
+template <int DIM>
+__device__ __forceinline__ void to_physical(const double (&gref)[DIM][DIM],
+                                            const double (&K)[DIM][DIM], double (&G)[DIM][DIM])
+{
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) s = fma(gref[c][r], K[r][j], s);
+            G[c][j] = s;
+        }
+}
+
+// T[c][r] = W sum_j S[c][j] K[r][j]: the stress paired with reference test derivatives
+template <int DIM>
+__device__ __forceinline__ void pull_back(const double (&S)[DIM][DIM], const double (&K)[DIM][DIM],
+                                          double W, double (&T)[DIM][DIM])
+{
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) s = fma(S[c][j], K[r][j], s);
+            T[c][r] = W * s;
+        }
+}
+
+// sigma = lam tr(G) I + mu (G + G^T)
+template <int DIM>
+__device__ __forceinline__ void stress_elasticity(const double (&G)[DIM][DIM], double lam,
+                                                  double mu, double (&S)[DIM][DIM])
+{
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) tr += G[i][i];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) S[i][j] = mu * (G[i][j] + G[j][i]) + (i == j ? lam * tr : 0.0);
+}
+
+// P = mu (F - F^{-T}) + lam ln(det F) F^{-T},  F = I + G
+template <int DIM>
+__device__ __forceinline__ void stress_neohookean(const double (&G)[DIM][DIM], double lam,
+                                                  double mu, double (&S)[DIM][DIM])
+{
+    double F[DIM][DIM], Fi[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) F[i][j] = G[i][j] + (i == j ? 1.0 : 0.0);
+    const double detF = invert<DIM>(F, Fi);
+    const double c = lam * log(detF) - mu;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) S[i][j] = fma(mu, F[i][j], c * Fi[j][i]);
+}
+
+// dP[H] = mu H + (mu - lam ln J) F^{-T} H^T F^{-T} + lam tr(F^{-1} H) F^{-T}: the tangent
+// contracted with H; it equals the transposed contraction because the tangent of a
+// hyperelastic stress has major symmetry.
+template <int DIM>
+__device__ __forceinline__ void tangent_neohookean(const double (&G)[DIM][DIM],
+                                                   const double (&H)[DIM][DIM], double lam,
+                                                   double mu, double (&S)[DIM][DIM])
+{
+    double F[DIM][DIM], Fi[DIM][DIM], FiH[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) F[i][j] = G[i][j] + (i == j ? 1.0 : 0.0);
+    const double detF = invert<DIM>(F, Fi);
+    const double b = mu - lam * log(detF);
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) s = fma(Fi[i][k], H[k][j], s);
+            FiH[i][j] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) tr += FiH[i][i];
+    const double ct = lam * tr;
+    // (F^{-T} H^T F^{-T})[k][l] = (F^{-1} H F^{-1})[l][k] = sum_m FiH[l][m] Fi[m][k]
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int l = 0; l < DIM; ++l) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) s = fma(FiH[l][m], Fi[m][k], s);
+            S[k][l] = fma(mu, H[k][l], fma(b, s, ct * Fi[l][k]));
+        }
+}
+
+// The quadrature loop of one cell: evaluation of u (and v) at each point from the
+// tabulation, the pointwise form, and accumulation into yl against the test functions.
+// The tabulation address is uniform across the wavefront (constant address space), so its
+// values arrive through scalar loads.
+template <int FORM, int DIM, int K, bool VJP>
+__device__ __forceinline__ void cell_quadrature(
+    const double (&ul)[nloc_of(DIM, K)][FORM == FEM_MASS ? 1 : DIM],
+    const double (&vl)[VJP ? nloc_of(DIM, K) : 1][FORM == FEM_MASS ? 1 : DIM],
+    const double (&Kinv)[DIM][DIM], double adet, const double *table, int nq, double lam,
+    double mu, double (&yl)[nloc_of(DIM, K)][FORM == FEM_MASS ? 1 : DIM])
+{
+    constexpr int NLOC = nloc_of(DIM, K);
+    constexpr int REC = record_of(FORM, DIM, NLOC);
+    const FEMX_CONSTANT double *tab = (const FEMX_CONSTANT double *)table;
+    if constexpr (FORM == FEM_MASS) {
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n) yl[n][0] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < nq; ++q) {
+            const FEMX_CONSTANT double *t = tab + q * REC;
+            double uq = 0.0;
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) uq = fma(t[n], ul[n][0], uq);
+            const double e = t[NLOC] * adet * uq;
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) yl[n][0] = fma(t[n], e, yl[n][0]);
+        }
+    } else {
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) yl[n][c] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < nq; ++q) {
+            const FEMX_CONSTANT double *t = tab + q * REC;
+            double gu[DIM][DIM], gv[DIM][DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    gu[c][r] = 0.0;
+                    gv[c][r] = 0.0;
+                }
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n)
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    const double tr = t[r * NLOC + n];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        gu[c][r] = fma(tr, ul[n][c], gu[c][r]);
+                        if constexpr (VJP) gv[c][r] = fma(tr, vl[n][c], gv[c][r]);
+                    }
+                }
+            double G[DIM][DIM], S[DIM][DIM], T[DIM][DIM];
+            to_physical<DIM>(gu, Kinv, G);
+            if constexpr (VJP) {
+                double H[DIM][DIM];
+                to_physical<DIM>(gv, Kinv, H);
+                tangent_neohookean<DIM>(G, H, lam, mu, S);
+            } else if constexpr (FORM == FEM_ELASTICITY) {
+                stress_elasticity<DIM>(G, lam, mu, S);
+            } else {
+                stress_neohookean<DIM>(G, lam, mu, S);
+            }
+            pull_back<DIM>(S, Kinv, t[DIM * NLOC] * adet, T);
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n)
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    const double tr = t[r * NLOC + n];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) yl[n][c] = fma(tr, T[c][r], yl[n][c]);
+                }
+        }
+    }
+}
+
+}  // namespace femx

@@ -59,6 +59,29 @@ struct LaunchArgs {
     double lam, mu;
 };
 
+// Launch parameters of the patch strategy (one workgroup per patch of cells).
+struct PatchArgs {
+    const int32_t *verts;       // SoA [(dim+1)][stride] vertex ids, patch-sorted cells
+    const uint16_t *lidx;       // SoA [nloc][stride] patch-local node index of (cell, a)
+    const int32_t *patch_off;   // [n_patch + 1] into the (patch, node) list
+    const int32_t *patch_nodes; // global node id of each (patch, node)
+    const int32_t *patch_dest;  // -1: node held by this patch only, else partial slot
+    const int32_t *csr_off;     // [n_pn + 1] element-buffer slots summed into (patch, node)
+    const uint16_t *csr_slots;  // slot = a * P + local cell, in ascending (cell, a)
+    const double *coords;
+    const double *tab;
+    const double *u;
+    const double *v;
+    double *y;
+    double *partial;            // [n_partial][ncomp]
+    int64_t stride;
+    int64_t n_cell;
+    int nq;
+    double lam, mu;
+};
+
+enum Strategy { STRAT_COLOUR = 0, STRAT_PATCH = 1 };
+
 }  // namespace femx
 
 struct fem_plan {
@@ -78,6 +101,21 @@ struct fem_plan {
     double *d_tab = nullptr;
     int32_t *d_untouched = nullptr;      // nodes no cell holds (zeroed separately)
     int64_t n_untouched = 0;
+    // patch strategy
+    int strategy = femx::STRAT_PATCH;
+    int patch = 0;                       // cells per patch (0: not built)
+    int64_t n_patch = 0, n_pn = 0, n_partial = 0, n_shared = 0;
+    int max_patch_nodes = 0;
+    int32_t *d_pverts = nullptr;
+    uint16_t *d_lidx = nullptr;
+    int32_t *d_patch_off = nullptr, *d_patch_nodes = nullptr, *d_patch_dest = nullptr;
+    int32_t *d_csr_off = nullptr;
+    uint16_t *d_csr_slots = nullptr;
+    int32_t *d_fix_node = nullptr, *d_fix_off = nullptr;
+    double *d_partial = nullptr;
+    int64_t pstride = 0;
+    std::vector<double> h_coords;        // host copies, to rebuild patches on request
+    std::vector<int32_t> h_cell_verts, h_cell_nodes;
 };
 
 namespace femx {
@@ -87,4 +125,10 @@ hipError_t launch_action(const fem_plan &p, const LaunchArgs &a, int block, bool
                          hipStream_t s);
 hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double *y,
                              hipStream_t s);
+// LDS bytes the patch kernel needs for a patch of `patch` cells with at most
+// `max_nodes` distinct nodes.
+size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes);
+hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
+hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t n_shared,
+                        const double *partial, int ncomp, double *y, hipStream_t s);
 }  // namespace femx

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -65,6 +66,27 @@ T *device_upload(const std::vector<T> &h, const char *what)
     return d;
 }
 
+void free_patch_memory(fem_plan *p)
+{
+    (void)hipFree(p->d_pverts);
+    (void)hipFree(p->d_lidx);
+    (void)hipFree(p->d_patch_off);
+    (void)hipFree(p->d_patch_nodes);
+    (void)hipFree(p->d_patch_dest);
+    (void)hipFree(p->d_csr_off);
+    (void)hipFree(p->d_csr_slots);
+    (void)hipFree(p->d_fix_node);
+    (void)hipFree(p->d_fix_off);
+    (void)hipFree(p->d_partial);
+    p->d_pverts = nullptr;
+    p->d_lidx = nullptr;
+    p->d_patch_off = p->d_patch_nodes = p->d_patch_dest = p->d_csr_off = nullptr;
+    p->d_csr_slots = nullptr;
+    p->d_fix_node = p->d_fix_off = nullptr;
+    p->d_partial = nullptr;
+    p->patch = 0;
+}
+
 void free_plan_memory(fem_plan *p)
 {
     if (!p) return;
@@ -74,6 +96,7 @@ void free_plan_memory(fem_plan *p)
     (void)hipFree(p->d_first);
     (void)hipFree(p->d_tab);
     (void)hipFree(p->d_untouched);
+    free_patch_memory(p);
 }
 
 // Greedy first-fit colouring, cells in ascending id; conflict = a shared node.
@@ -110,6 +133,10 @@ int greedy_colouring(int64_t n_cell, int nloc, const int32_t *cell_nodes, int64_
     }
     throw femx::Error(FEM_E_UNSUPPORTED, "colouring needs more than 1024 colours");
 }
+
+void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
+                   const int32_t *cell_nodes, int P);
+int default_patch(const fem_plan *p);
 
 // Host-side validation of the mesh; runs before any HIP call.
 void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
@@ -195,6 +222,239 @@ void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
     p->d_first = device_upload(first, "first-touch masks");
     p->d_tab = device_upload(tab, "tables");
     p->d_untouched = device_upload(untouched, "untouched nodes");
+    if (p->n_cell > 0) build_patches(p, coords, cell_verts, cell_nodes, default_patch(p));
+    else p->strategy = femx::STRAT_COLOUR;
+}
+
+
+// Morton key of a cell's centroid on a 2^21 (3D) or 2^31 (2D) lattice over the bounding box.
+uint64_t spread2(uint64_t v)
+{
+    v &= 0x7fffffffULL;
+    v = (v | (v << 16)) & 0x0000ffff0000ffffULL;
+    v = (v | (v << 8)) & 0x00ff00ff00ff00ffULL;
+    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0fULL;
+    v = (v | (v << 2)) & 0x3333333333333333ULL;
+    v = (v | (v << 1)) & 0x5555555555555555ULL;
+    return v;
+}
+
+uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffULL;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+std::vector<int64_t> morton_order(const fem_plan *p, const double *coords, const int32_t *cell_verts)
+{
+    const int d = p->dim, nv = d + 1;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < p->n_vert; ++v)
+        for (int i = 0; i < d; ++i) {
+            lo[i] = std::min(lo[i], coords[v * d + i]);
+            hi[i] = std::max(hi[i], coords[v * d + i]);
+        }
+    const double levels = d == 2 ? 2147483647.0 : 2097151.0;
+    std::vector<std::pair<uint64_t, int64_t>> key((size_t)p->n_cell);
+    for (int64_t c = 0; c < p->n_cell; ++c) {
+        uint64_t k = 0;
+        for (int i = 0; i < d; ++i) {
+            double x = 0.0;
+            for (int j = 0; j < nv; ++j) x += coords[(int64_t)cell_verts[c * nv + j] * d + i];
+            x /= nv;
+            const double span = hi[i] - lo[i];
+            const double t = span > 0 ? (x - lo[i]) / span : 0.0;
+            const uint64_t q = (uint64_t)std::min(levels, std::max(0.0, t * levels));
+            k |= d == 2 ? spread2(q) << i : spread3(q) << i;
+        }
+        key[c] = {k, c};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int64_t> order((size_t)p->n_cell);
+    for (int64_t c = 0; c < p->n_cell; ++c) order[c] = key[c].second;
+    return order;
+}
+
+// Patch strategy data: cells along the Morton curve cut into patches of P cells; per patch
+// its distinct nodes (ascending id), the local index of every (cell, a), and for every
+// distinct node the element-buffer slots it sums, in ascending (local cell, a).
+struct PatchLayout {
+    int P = 0, max_nodes = 0;
+    int64_t n_patch = 0, stride = 0;
+    std::vector<int64_t> order;
+    std::vector<int32_t> pverts, patch_off, patch_nodes, patch_dest, csr_off, fix_node, fix_off;
+    std::vector<uint16_t> lidx, csr_slots;
+};
+
+PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int32_t *cell_verts,
+                              const int32_t *cell_nodes, int P)
+{
+    using femx::Error;
+    const int nv = p->dim + 1, nloc = p->nloc;
+    if (P != 64 && P != 128 && P != 256) throw Error(FEM_E_ARG, "patch size must be 64, 128 or 256");
+    if ((int64_t)P * nloc > 65536) throw Error(FEM_E_UNSUPPORTED, "patch slots exceed 16 bits");
+    PatchLayout L;
+    L.P = P;
+    L.order = morton_order(p, coords, cell_verts);
+    L.n_patch = (p->n_cell + P - 1) / P;
+    L.stride = std::max<int64_t>(P, L.n_patch * P);
+    L.pverts.assign((size_t)nv * L.stride, 0);
+    L.lidx.assign((size_t)nloc * L.stride, 0);
+    L.patch_off.assign((size_t)L.n_patch + 1, 0);
+    L.csr_off.assign(1, 0);
+    L.patch_nodes.reserve((size_t)(p->n_cell * nloc / 2 + 16));
+    L.csr_slots.reserve((size_t)(p->n_cell * nloc));
+    std::vector<int32_t> node_count((size_t)p->n_node, 0);
+    std::vector<std::pair<int64_t, int32_t>> pairs;   // ((node*P + cl)*nloc + a, slot)
+    for (int64_t pt = 0; pt < L.n_patch; ++pt) {
+        const int64_t c0 = pt * P, c1 = std::min<int64_t>(p->n_cell, c0 + P);
+        pairs.clear();
+        for (int64_t s = c0; s < c1; ++s) {
+            const int64_t c = L.order[s];
+            const int cl = (int)(s - c0);
+            for (int j = 0; j < nv; ++j) L.pverts[(size_t)j * L.stride + s] = cell_verts[c * nv + j];
+            for (int a = 0; a < nloc; ++a) {
+                const int64_t nd = cell_nodes[c * nloc + a];
+                pairs.push_back({(nd * P + cl) * nloc + a, a * P + cl});
+            }
+        }
+        std::sort(pairs.begin(), pairs.end());
+        int U = 0;
+        int64_t prev = -1;
+        for (const auto &pr : pairs) {
+            const int64_t nd = pr.first / ((int64_t)P * nloc);
+            const int rem = (int)(pr.first % ((int64_t)P * nloc));
+            const int cl = rem / nloc, a = rem % nloc;
+            if (nd != prev) {
+                if (prev >= 0) L.csr_off.push_back((int32_t)L.csr_slots.size());
+                L.patch_nodes.push_back((int32_t)nd);
+                node_count[nd]++;
+                prev = nd;
+                ++U;
+            }
+            L.lidx[(size_t)a * L.stride + c0 + cl] = (uint16_t)(U - 1);
+            L.csr_slots.push_back((uint16_t)pr.second);
+        }
+        if (prev >= 0) L.csr_off.push_back((int32_t)L.csr_slots.size());
+        L.patch_off[pt + 1] = (int32_t)L.patch_nodes.size();
+        L.max_nodes = std::max(L.max_nodes, U);
+    }
+    // nodes held by several patches sum through partial slots, in patch order
+    std::vector<int32_t> fix_base((size_t)p->n_node, -1), rank((size_t)p->n_node, 0);
+    L.fix_off.assign(1, 0);
+    for (int64_t n = 0; n < p->n_node; ++n)
+        if (node_count[n] > 1) {
+            fix_base[n] = L.fix_off.back();
+            L.fix_node.push_back((int32_t)n);
+            L.fix_off.push_back(L.fix_off.back() + node_count[n]);
+        }
+    L.patch_dest.assign(L.patch_nodes.size(), -1);
+    for (size_t j = 0; j < L.patch_nodes.size(); ++j) {
+        const int32_t nd = L.patch_nodes[j];
+        if (fix_base[nd] >= 0) L.patch_dest[j] = fix_base[nd] + rank[nd]++;
+    }
+    return L;
+}
+
+// Check every index the patch and fixup kernels will follow, on the host: each (cell, a)
+// slot is summed exactly once, into the node the map gives it; every local index points at
+// its node; every partial slot is written once and read by its node's fixup; all indices
+// fall inside their buffers.  Throws on the first violation.
+void validate_patch_layout(const fem_plan *p, const PatchLayout &L, const int32_t *cell_nodes)
+{
+    using femx::Error;
+    const int P = L.P, nloc = p->nloc;
+    auto bad = [](const std::string &m) { throw Error(FEM_E_ARG, "patch layout: " + m); };
+    if ((int64_t)L.patch_off.size() != L.n_patch + 1 || L.patch_off[0] != 0) bad("patch offsets");
+    if (L.csr_off.size() != L.patch_nodes.size() + 1) bad("csr offsets size");
+    if ((int64_t)L.csr_slots.size() != p->n_cell * nloc) bad("slot count");
+    std::vector<uint8_t> slot_seen((size_t)L.n_patch * P * nloc, 0);
+    std::vector<int32_t> partial_writes((size_t)L.fix_off.back(), 0);
+    for (int64_t pt = 0; pt < L.n_patch; ++pt) {
+        const int nb = L.patch_off[pt], U = L.patch_off[pt + 1] - nb;
+        if (U < 0 || U > L.max_nodes) bad("node count");
+        const int64_t c0 = pt * P;
+        for (int j = 0; j < U; ++j) {
+            const int32_t nd = L.patch_nodes[nb + j];
+            if (nd < 0 || nd >= p->n_node) bad("node id");
+            if (j > 0 && L.patch_nodes[nb + j - 1] >= nd) bad("node order");
+            const int e0 = L.csr_off[nb + j], e1 = L.csr_off[nb + j + 1];
+            if (e0 < 0 || e1 < e0 || e1 > (int)L.csr_slots.size()) bad("csr range");
+            for (int e = e0; e < e1; ++e) {
+                const int sl = L.csr_slots[e], a = sl / P, cl = sl % P;
+                if (a >= nloc) bad("slot node index");
+                const int64_t s = c0 + cl;
+                if (s >= p->n_cell) bad("slot of an absent cell");
+                if (cell_nodes[L.order[s] * nloc + a] != nd) bad("slot sums into the wrong node");
+                if (L.lidx[(size_t)a * L.stride + s] != j) bad("local index");
+                uint8_t &seen = slot_seen[(size_t)(pt * P + cl) * nloc + a];
+                if (seen) bad("slot summed twice");
+                seen = 1;
+            }
+            const int dest = L.patch_dest[nb + j];
+            if (dest >= 0) {
+                if (dest >= (int)partial_writes.size()) bad("partial slot range");
+                partial_writes[dest]++;
+                const auto it = std::lower_bound(L.fix_node.begin(), L.fix_node.end(), nd);
+                if (it == L.fix_node.end() || *it != nd) bad("partial of an unshared node");
+                const size_t k = it - L.fix_node.begin();
+                if (dest < L.fix_off[k] || dest >= L.fix_off[k + 1]) bad("partial outside its node");
+            }
+        }
+    }
+    for (int64_t s = 0; s < p->n_cell; ++s)
+        for (int a = 0; a < nloc; ++a)
+            if (!slot_seen[(size_t)s * nloc + a]) bad("slot never summed");
+    for (int32_t w : partial_writes)
+        if (w != 1) bad("partial written " + std::to_string(w) + " times");
+}
+
+void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
+                   const int32_t *cell_nodes, int P)
+{
+    using femx::Error;
+    PatchLayout L = make_patch_layout(p, coords, cell_verts, cell_nodes, P);
+    const char *chk = std::getenv("FEM_CHECK");
+    if (chk && chk[0] == '1') validate_patch_layout(p, L, cell_nodes);
+    const size_t lds = femx::patch_lds_bytes(p->form, p->dim, p->degree, p->form == FEM_NEOHOOKEAN,
+                                             P, L.max_nodes);
+    if (lds > 160 * 1024)
+        throw Error(FEM_E_UNSUPPORTED, "patch of " + std::to_string(P) + " cells needs " +
+                                           std::to_string(lds) + " bytes of LDS");
+    free_patch_memory(p);
+    p->patch = P;
+    p->n_patch = L.n_patch;
+    p->n_pn = (int64_t)L.patch_nodes.size();
+    p->n_partial = L.fix_off.back();
+    p->n_shared = (int64_t)L.fix_node.size();
+    p->max_patch_nodes = L.max_nodes;
+    p->pstride = L.stride;
+    p->d_pverts = device_upload(L.pverts, "patch cell_verts");
+    p->d_lidx = device_upload(L.lidx, "patch local indices");
+    p->d_patch_off = device_upload(L.patch_off, "patch offsets");
+    p->d_patch_nodes = device_upload(L.patch_nodes, "patch nodes");
+    p->d_patch_dest = device_upload(L.patch_dest, "patch destinations");
+    p->d_csr_off = device_upload(L.csr_off, "patch csr offsets");
+    p->d_csr_slots = device_upload(L.csr_slots, "patch csr slots");
+    p->d_fix_node = device_upload(L.fix_node, "shared nodes");
+    p->d_fix_off = device_upload(L.fix_off, "shared offsets");
+    if (p->n_partial > 0) {
+        std::vector<double> zeros((size_t)p->n_partial * p->ncomp, 0.0);
+        p->d_partial = device_upload(zeros, "partials");
+    }
+}
+
+int default_patch(const fem_plan *p)
+{
+    // the largest power-of-two patch whose element buffer fits in 64 KB of LDS
+    for (int P = 256; P >= 64; P /= 2)
+        if ((size_t)P * p->nloc * p->ncomp * 8 <= 64 * 1024) return P;
+    return 64;
 }
 
 void check_plan(const fem_plan *p)
@@ -216,6 +476,36 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
     if (p->n_untouched > 0)
         femx::check_hip(femx::launch_zero_nodes(p->d_untouched, p->n_untouched, p->ncomp, y, s),
                         "zero untouched nodes");
+    // the linear forms are symmetric: their VJP is the action applied to v
+    const bool nl_vjp = vjp && p->form == FEM_NEOHOOKEAN;
+    const double *in = (vjp && !nl_vjp) ? v : u;
+    if (p->strategy == femx::STRAT_PATCH && p->patch > 0) {
+        femx::PatchArgs a{};
+        a.verts = p->d_pverts;
+        a.lidx = p->d_lidx;
+        a.patch_off = p->d_patch_off;
+        a.patch_nodes = p->d_patch_nodes;
+        a.patch_dest = p->d_patch_dest;
+        a.csr_off = p->d_csr_off;
+        a.csr_slots = p->d_csr_slots;
+        a.coords = p->d_coords;
+        a.tab = p->d_tab;
+        a.u = in;
+        a.v = nl_vjp ? v : nullptr;
+        a.y = y;
+        a.partial = p->d_partial;
+        a.stride = p->pstride;
+        a.n_cell = p->n_cell;
+        a.nq = p->nq;
+        a.lam = p->lam;
+        a.mu = p->mu;
+        femx::check_hip(femx::launch_patch(*p, a, nl_vjp, s), "patch launch");
+        if (p->n_shared > 0)
+            femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off, p->n_shared,
+                                               p->d_partial, p->ncomp, y, s),
+                            "fixup launch");
+        return;
+    }
     femx::LaunchArgs a{};
     a.verts = p->d_verts;
     a.nodes = p->d_nodes;
@@ -227,9 +517,7 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
     a.lam = p->lam;
     a.mu = p->mu;
     a.y = y;
-    // the linear forms are symmetric: their VJP is the action applied to v
-    const bool nl_vjp = vjp && p->form == FEM_NEOHOOKEAN;
-    a.u = (vjp && !nl_vjp) ? v : u;
+    a.u = in;
     a.v = nl_vjp ? v : nullptr;
     for (int c = 0; c < p->n_colours; ++c) {
         a.begin = p->colour_off[c];
@@ -286,6 +574,9 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
         p->n_node = n_node;
         p->n_dof = n_node * p->ncomp;
         validate_mesh(p, coords, cell_verts, cell_nodes, params, n_params);
+        p->h_coords.assign(coords, coords + n_vert * dim);
+        p->h_cell_verts.assign(cell_verts, cell_verts + n_cell * (dim + 1));
+        p->h_cell_nodes.assign(cell_nodes, cell_nodes + n_cell * p->nloc);
         femx::check_hip(hipGetDevice(&p->device), "hipGetDevice");
         build_plan(p, coords, cell_verts, cell_nodes);
     });
@@ -379,6 +670,75 @@ int fem_colouring(int64_t n_cell, int n_loc, const int32_t *cell_nodes, int64_t 
         const int nc = n_cell ? greedy_colouring(n_cell, n_loc, cell_nodes, n_node, col) : 0;
         if (n_cell) std::memcpy(colour, col.data(), col.size() * sizeof(int32_t));
         if (n_colours) *n_colours = nc;
+    });
+}
+
+int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const double *coords,
+                           int64_t n_cell, const int32_t *cell_verts, const int32_t *cell_nodes,
+                           int64_t n_node, int patch_cells, int64_t *stats)
+{
+    return guarded([&] {
+        using femx::Error;
+        if (form < FEM_MASS || form > FEM_NEOHOOKEAN || (dim != 2 && dim != 3) || degree < 1 ||
+            degree > 8)
+            throw Error(FEM_E_UNSUPPORTED, "unsupported form/dim/degree");
+        if (n_vert < 0 || n_cell < 1 || n_node < 0) throw Error(FEM_E_ARG, "bad size");
+        if (!coords || !cell_verts || !cell_nodes) throw Error(FEM_E_ARG, "null mesh array");
+        fem_plan p;
+        p.form = form;
+        p.dim = dim;
+        p.degree = degree;
+        p.nloc = femx::n_local(dim, degree);
+        p.ncomp = form == FEM_MASS ? 1 : dim;
+        p.n_vert = n_vert;
+        p.n_cell = n_cell;
+        p.n_node = n_node;
+        const double lm[2] = {1.0, 1.0};
+        validate_mesh(&p, coords, cell_verts, cell_nodes, lm, 2);
+        const int P = patch_cells == 0 ? default_patch(&p) : patch_cells;
+        PatchLayout L = make_patch_layout(&p, coords, cell_verts, cell_nodes, P);
+        validate_patch_layout(&p, L, cell_nodes);
+        if (stats) {
+            stats[0] = L.P;
+            stats[1] = L.n_patch;
+            stats[2] = L.max_nodes;
+            stats[3] = (int64_t)L.patch_nodes.size();
+            stats[4] = (int64_t)L.fix_node.size();
+            stats[5] = L.fix_off.back();
+            stats[6] = (int64_t)femx::patch_lds_bytes(form, dim, degree, form == FEM_NEOHOOKEAN, P,
+                                                      L.max_nodes);
+        }
+    });
+}
+
+int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells)
+{
+    return guarded([&] {
+        check_plan(plan);
+        if (strategy == FEM_SCATTER_COLOUR) {
+            if (patch_cells != 0) throw femx::Error(FEM_E_ARG, "patch_cells must be 0 for colours");
+            plan->strategy = femx::STRAT_COLOUR;
+            return;
+        }
+        if (strategy != FEM_SCATTER_PATCH) throw femx::Error(FEM_E_ARG, "unknown strategy");
+        if (plan->n_cell == 0) throw femx::Error(FEM_E_ARG, "empty mesh has no patches");
+        const int P = patch_cells == 0 ? default_patch(plan) : patch_cells;
+        if (P != plan->patch) {
+            if (!plan->h_cell_verts.size()) throw femx::Error(FEM_E_ARG, "plan keeps no host mesh");
+            femx::check_hip(hipDeviceSynchronize(), "synchronise before rebuilding patches");
+            build_patches(plan, plan->h_coords.data(), plan->h_cell_verts.data(),
+                          plan->h_cell_nodes.data(), P);
+        }
+        plan->strategy = femx::STRAT_PATCH;
+    });
+}
+
+int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells)
+{
+    return guarded([&] {
+        check_plan(plan);
+        if (strategy) *strategy = plan->strategy == femx::STRAT_PATCH ? FEM_SCATTER_PATCH : FEM_SCATTER_COLOUR;
+        if (patch_cells) *patch_cells = plan->strategy == femx::STRAT_PATCH ? plan->patch : 0;
     });
 }
 

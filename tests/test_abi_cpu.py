@@ -116,3 +116,22 @@ def test_plan_without_device_reports_hip_error():
         pass
     st, msg = _create()
     assert st == -5 and "hipGetDevice" in msg
+
+
+@pytest.mark.parametrize("form,dim,n,k,P", [(0, 2, 9, 2, 64), (2, 2, 12, 4, 128), (2, 2, 16, 4, 256),
+                                            (1, 3, 3, 2, 64), (1, 3, 4, 2, 256), (0, 3, 3, 4, 64),
+                                            (2, 2, 7, 6, 0), (1, 3, 2, 3, 0), (0, 2, 1, 1, 64)])
+def test_patch_layout_valid(form, dim, n, k, P):
+    m = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(n))
+    st = fx.check_patch_layout(form, m, P)
+    assert st["n_patch"] == -(-m.n_cell // st["patch_cells"])
+    assert st["max_patch_nodes"] <= st["patch_cells"] * m.cell_nodes.shape[1]
+    assert st["lds_bytes"] <= 160 * 1024
+    # every node held by some patch; shared nodes have one partial per holding patch
+    assert st["patch_node_pairs"] == m.n_node + st["partial_slots"] - st["shared_nodes"]
+
+
+def test_patch_layout_rejects_bad_size():
+    m = meshgen.unit_square(4, 2)
+    with pytest.raises(fx.FemError):
+        fx.check_patch_layout(0, m, 100)

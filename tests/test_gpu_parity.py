@@ -66,29 +66,36 @@ CASES = [(f, 2, k) for f in (0, 1, 2) for k in range(1, 7)] + \
         [(f, 3, k) for f in (0, 1, 2) for k in range(1, 5)]
 
 
+STRATS = [(fx.SCATTER_PATCH, 0), (fx.SCATTER_PATCH, 64), (fx.SCATTER_COLOUR, 0)]
+
+
+@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64", "colour"])
 @pytest.mark.parametrize("form,dim,k", CASES)
-def test_action_small_meshes(form, dim, k):
-    # 2D n=9: 162 cells; 3D n=3: 162 cells -- several wavefronts per colour plus a tail
+def test_action_small_meshes(form, dim, k, strategy):
+    # 2D n=9: 162 cells; 3D n=3: 162 cells -- several wavefronts / patches plus a ragged tail
     n = 9 if dim == 2 else 3
     mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(100 + k))
     u, _ = inputs(form, mesh, k)
     qd = qdeg(form, k)
-    say(f"[action] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd}")
+    say(f"[action] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd} strat={strategy}")
     plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    plan.set_strategy(*strategy)
     y = plan.action(gpu(u)).cpu().numpy()
     ref = oracle.action(form, mesh, u, qd, params_for(form))
     emax, el2 = rel_err(y, ref)
     assert emax < TOL and el2 < TOL, (emax, el2)
 
 
+@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64", "colour"])
 @pytest.mark.parametrize("form,dim,k", CASES)
-def test_vjp_small_meshes(form, dim, k):
+def test_vjp_small_meshes(form, dim, k, strategy):
     n = 7 if dim == 2 else 2
     mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(200 + k))
     u, v = inputs(form, mesh, 50 + k)
     qd = qdeg(form, k)
-    say(f"[vjp] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd}")
+    say(f"[vjp] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd} strat={strategy}")
     plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    plan.set_strategy(*strategy)
     g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
     ref = oracle.vjp(form, mesh, u, v, qd, params_for(form))
     emax, el2 = rel_err(g, ref)
@@ -100,6 +107,7 @@ def test_block_sizes_bitwise_identical(block):
     w = meshgen.workload("nh_p4_2d", n=24)
     say(f"[block] nh_p4_2d n=24 block={block}")
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    plan.set_strategy(fx.SCATTER_COLOUR)
     u = gpu(w.u)
     y0 = plan.action(u).cpu().numpy()
     plan.set_block(block)
@@ -107,12 +115,15 @@ def test_block_sizes_bitwise_identical(block):
     assert np.array_equal(y0, y1)
 
 
-def test_determinism_and_stream():
+@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64", "colour"])
+def test_determinism_and_stream(strategy):
     w = meshgen.workload("elast_p2_3d", n=6)
-    say("[determinism] elast_p2_3d n=6")
+    say(f"[determinism] elast_p2_3d n=6 {strategy}")
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    plan.set_strategy(*strategy)
     u = gpu(w.u)
     y0 = plan.action(u)
+    torch.cuda.synchronize()
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         y1 = plan.action(u)
@@ -163,22 +174,32 @@ def test_single_cell_and_ragged_counts():
 
 
 FULL = ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d", "nh_vjp_p4_2d", "mass_p2_2d_1024"]
+_ref_cache = {}
 
 
+@pytest.mark.parametrize("strategy", [(fx.SCATTER_PATCH, 0), (fx.SCATTER_COLOUR, 0)],
+                         ids=["patch", "colour"])
 @pytest.mark.parametrize("name", FULL)
-def test_full_size_against_oracle(name):
+def test_full_size_against_oracle(name, strategy):
     """Every output of the full-size workloads against the oracle (seconds on the host)."""
-    w = meshgen.workload(name)
-    say(f"[full] {name} cells={w.mesh.n_cell} dofs={w.n_dof}")
-    if w.form == fx.FORM_NEOHOOKEAN:
-        assert oracle.min_det_f(w.mesh, w.u, w.quad_degree) > 0.5
+    if name not in _ref_cache:
+        _ref_cache.clear()
+        w = meshgen.workload(name)
+        if w.form == fx.FORM_NEOHOOKEAN:
+            assert oracle.min_det_f(w.mesh, w.u, w.quad_degree) > 0.5
+        if w.v is not None:
+            ref = oracle.vjp(w.form, w.mesh, w.u, w.v, w.quad_degree, w.params)
+        else:
+            ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
+        _ref_cache[name] = (w, ref)
+    w, ref = _ref_cache[name]
+    say(f"[full] {name} cells={w.mesh.n_cell} dofs={w.n_dof} {strategy}")
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    plan.set_strategy(*strategy)
     if w.v is not None:
         out = plan.vjp(gpu(w.u), gpu(w.v)).cpu().numpy()
-        ref = oracle.vjp(w.form, w.mesh, w.u, w.v, w.quad_degree, w.params)
     else:
         out = plan.action(gpu(w.u)).cpu().numpy()
-        ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
     emax, el2 = rel_err(out, ref)
     say(f"[full] {name} rel_max={emax:.3e} rel_l2={el2:.3e}")
     assert emax < TOL and el2 < TOL
