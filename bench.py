@@ -181,6 +181,9 @@ def main():
     ap.add_argument("--workload", default="nh_p4_2d")
     ap.add_argument("--all", action="store_true", help="also time the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), to calibrate the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the action "
@@ -190,6 +193,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        n = args.copy_calibration * 1024 * 1024 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 5}))
+        return
 
     main_info, w, plan = run_workload(args.workload, args.steps, args.warmup)
     print(f"# {args.workload}: {main_info['ms_mean']:.4f} ms/step", file=sys.stderr, flush=True)

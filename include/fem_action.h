@@ -17,8 +17,13 @@
  *   3D  for l: for j: for i (i + j + l <= k).  n_loc = C(k + d, d).
  * - Geometry is affine: J = [x_1 - x_0 | ... | x_d - x_0] from the cell's vertices in
  *   cell_verts order; integrals use |det J| (cells with det J < 0 in 3D are valid).
- * - Quadrature: the conical-product (collapsed Gauss-Jacobi) rule with
- *   ceil((quad_degree + 1)/2) points per direction, exact to quad_degree.
+ * - Quadrature: a rule exact to quad_degree on the reference simplex, from one of two
+ *   families: FEM_QUAD_CONICAL, the conical-product (collapsed Gauss-Jacobi) rule with
+ *   ceil((quad_degree + 1)/2) points per direction (any degree); FEM_QUAD_SYMMETRIC, the
+ *   fully symmetric rules with fewest points, built for quad_degree <= 2 (1 point, or 3 /
+ *   4 points on the orbit of (a, b, b[, b])).  A plan of the mass or elasticity form uses
+ *   the symmetric rule when one exists (their integrands are polynomials, so the operator
+ *   does not depend on the exact rule); the neo-Hookean form uses the conical rule.
  * - Vectors are node-major interleaved: component c of node n at index n * ncomp + c,
  *   ncomp = 1 for the mass form and d for the vector forms.
  * - Host arrays are read during the call only.  Device arrays (u, v, y, g) are caller-
@@ -29,6 +34,9 @@
  *   thread-local message for the last failure.  No C++ exception crosses the ABI.
  * - Results are deterministic: the scatter-add never uses atomics; it runs in colour order
  *   or in a fixed per-patch order (fem_plan_set_strategy).
+ * - A plan owns a small device scratch area (partial sums of nodes shared by patches):
+ *   calls on one plan (or on batches holding it) that overlap in time on different streams
+ *   race on it.
  */
 #ifndef FEM_ACTION_H
 #define FEM_ACTION_H
@@ -38,6 +46,10 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* quadrature families */
+#define FEM_QUAD_CONICAL 0
+#define FEM_QUAD_SYMMETRIC 1
 
 /* form ids */
 #define FEM_MASS 0        /* a(u, v) = int u v                                        */
@@ -129,13 +141,19 @@ int fem_colouring(int64_t n_cell, int n_loc, const int32_t *cell_nodes, int64_t 
                   int32_t *colour, int32_t *n_colours);
 
 /*
- * Reference tables as used by the kernels (for testing the tabulation): HOST outputs
- *   points [n_quad][dim], weights [n_quad], phi [n_quad][n_loc],
- *   dphi [n_quad][n_loc][dim] (derivatives in the reference coordinates xi).
- * Call with points == NULL to get n_quad and n_loc only.
+ * Reference tables as used by the kernels (for testing the tabulation; paper Sec. 2.2,
+ * tabulated-values equation): HOST outputs points [n_quad][dim], weights [n_quad],
+ * phi [n_quad][n_loc], dphi [n_quad][n_loc][dim] (derivatives in the reference coordinates
+ * xi), for the rule of `family` (FEM_QUAD_*).  Call with points == NULL to get n_quad and
+ * n_loc only.  Errors: FEM_E_UNSUPPORTED (no such rule), FEM_E_ARG.
  */
-int fem_reference_tables(int dim, int degree, int quad_degree, int *n_quad, int *n_loc,
-                         double *points, double *weights, double *phi, double *dphi);
+int fem_reference_tables(int dim, int degree, int quad_degree, int family, int *n_quad,
+                         int *n_loc, double *points, double *weights, double *phi,
+                         double *dphi);
+
+/* Switch the plan's quadrature family (FEM_QUAD_*) and re-tabulate.  Synchronises.
+ * Errors: FEM_E_UNSUPPORTED (no rule of that family for the plan's degree), FEM_E_ARG. */
+int fem_plan_set_quadrature(fem_plan *plan, int family);
 
 /* Launch tuning of the colour strategy: cells per workgroup (64, 128 or 256); 0 restores
  * the default.  Errors: FEM_E_ARG for any other value. */
@@ -147,19 +165,72 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *   FEM_SCATTER_COLOUR  one launch per colour of the greedy colouring; a lane owning a
  *                       cell read-add-writes its nodes (no two cells of a launch share one).
  *   FEM_SCATTER_PATCH   one launch over patches of `patch_cells` consecutive cells along a
- *                       Morton curve of the cell centroids (64, 128 or 256; 0 = the largest
- *                       whose element buffer fits 64 KB of LDS).  A workgroup stages its
- *                       patch's nodal values in LDS, keeps the cell vectors in an LDS
- *                       element buffer and sums every node in a fixed order; nodes that
+ *                       Morton curve of the cell centroids (64, 128 or 256).  A workgroup
+ *                       stages its patch's nodal values in LDS, keeps the cell vectors in an
+ *                       LDS element buffer and sums every node in a fixed order; nodes that
  *                       several patches hold are summed in patch order by a second, small
- *                       kernel.  The default.
- * Rebuilding patches synchronises the device.  Errors: FEM_E_ARG, FEM_E_UNSUPPORTED (the
- * patch needs more than 160 KB of LDS), FEM_E_HIP, FEM_E_NOMEM.
+ *                       kernel.  `lanes_per_cell` 2 splits a cell's two components over a
+ *                       lane pair (2D vector forms only; patch_cells * lanes <= 256).  The
+ *                       default; 0 for either size picks the plan's default (two lanes for
+ *                       the 2D vector forms, the largest patch whose element buffer fits
+ *                       64 KB of LDS).
+ * Rebuilding patches synchronises the device.  Errors: FEM_E_ARG, FEM_E_UNSUPPORTED (a lane
+ * split the form lacks, or more than 160 KB of LDS), FEM_E_HIP, FEM_E_NOMEM.
  */
 #define FEM_SCATTER_COLOUR 0
 #define FEM_SCATTER_PATCH 1
-int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells);
-int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells);
+int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell);
+int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
+                          int *lanes_per_cell);
+
+/*
+ * Autotuner: time every launch configuration of the plan on the caller's vectors and keep
+ * the fastest on the plan.  Candidates: the colour strategy with 64/128/256 cells per
+ * workgroup; the patch strategy with 64/128/256 cells per patch and 1 or (2D vector forms)
+ * 2 lanes per cell.  Timing follows the paper's protocol (Sec. 6.2.1): 5 warm-up runs,
+ * then timed runs until 15 are collected or 0.2 s accumulates, arithmetic mean, HIP
+ * events on `stream`.  Synchronises; may rebuild the plan's patches (host work).
+ *   u, v   DEVICE inputs (v only for vjp != 0, which tunes fem_action_vjp instead)
+ *   y      DEVICE scratch output of n_dof doubles (overwritten)
+ *   cache_path  HOST path of a JSON cache to update (NULL: none).  fem_plan_create applies
+ *          a cached configuration when the environment variable FEM_TUNE_CACHE names the
+ *          file.  Keys: device architecture, form, dimension, degree, quadrature degree,
+ *          round(log2(cell count)).
+ *   results HOST f64 [max_results][5] out: strategy, cells per patch, lanes per cell,
+ *          cells per workgroup (colour), mean milliseconds; n_results HOST out.
+ * Errors: FEM_E_ARG, FEM_E_HIP, FEM_E_NOMEM.
+ */
+int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vjp,
+             const char *cache_path, void *stream, double *results, int max_results,
+             int *n_results);
+
+/*
+ * Batched actions over many meshes (y_i = A_i(u_i) for every plan of the batch) in a few
+ * launches recorded once into a HIP graph.  The paper launches one kernel per mesh and
+ * names small meshes as an open problem (Sec. 7); here the plans are grouped by kernel
+ * variant (form, dimension, degree, lanes per cell, cells per patch), each group is one
+ * launch over all patches of its meshes, and one launch sums every mesh's shared nodes.
+ *
+ * fem_batch_create: plans HOST [n] (each switched to the patch strategy if it is not on
+ *   it; the plans must outlive the batch and must not change strategy meanwhile);
+ *   u, y HOST arrays [n] of DEVICE pointers, mesh i reading u[i] and writing y[i] (no two
+ *   meshes may share an output).  Synchronous.
+ * fem_batch_set_vectors: rebind the vectors (synchronous; the graph is re-recorded at the
+ *   next run).
+ * fem_batch_run: enqueue the whole batch on `stream`; use_graph != 0 replays the recorded
+ *   graph (recording it on the first call, on a private stream), 0 launches eagerly.  Both
+ *   produce bitwise the same result as fem_action on each plan with the same strategy.
+ * fem_batch_info: meshes, launch groups, total patches, total shared nodes (all optional).
+ * Errors: FEM_E_ARG, FEM_E_UNSUPPORTED, FEM_E_HIP, FEM_E_NOMEM.
+ */
+typedef struct fem_batch fem_batch;
+int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const double *const *u,
+                     double *const *y);
+int fem_batch_set_vectors(fem_batch *batch, const double *const *u, double *const *y);
+int fem_batch_run(fem_batch *batch, void *stream, int use_graph);
+int fem_batch_info(const fem_batch *batch, int *n_mesh, int *n_groups, int64_t *n_patches,
+                   int64_t *n_shared);
+void fem_batch_destroy(fem_batch *batch);
 
 /*
  * Host-only check of the patch layout the library would build for this mesh (no device

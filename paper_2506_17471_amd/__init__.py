@@ -20,10 +20,11 @@ import os
 import numpy as np
 
 __all__ = ["FORM_MASS", "FORM_ELASTICITY", "FORM_NEOHOOKEAN", "FemError", "Plan", "FemAction",
-           "lib", "reference_tables", "colouring", "check_patch_layout", "LIB_PATH",
+           "lib", "reference_tables", "colouring", "check_patch_layout", "LIB_PATH", "Batch",
            "SCATTER_COLOUR", "SCATTER_PATCH"]
 
 FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN = 0, 1, 2
+QUAD_CONICAL, QUAD_SYMMETRIC = 0, 1
 SCATTER_COLOUR, SCATTER_PATCH = 0, 1
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfemx.so")
 
@@ -64,16 +65,30 @@ def lib() -> ctypes.CDLL:
     L.fem_plan_info.restype = i32
     L.fem_plan_colouring.argtypes = [P, P]
     L.fem_plan_colouring.restype = i32
-    L.fem_reference_tables.argtypes = [i32, i32, i32, P, P, P, P, P, P]
+    L.fem_reference_tables.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P]
+    L.fem_plan_set_quadrature.argtypes = [P, i32]
+    L.fem_plan_set_quadrature.restype = i32
     L.fem_reference_tables.restype = i32
     L.fem_plan_set_block.argtypes = [P, i32]
     L.fem_plan_set_block.restype = i32
-    L.fem_plan_set_strategy.argtypes = [P, i32, i32]
+    L.fem_plan_set_strategy.argtypes = [P, i32, i32, i32]
     L.fem_plan_set_strategy.restype = i32
-    L.fem_plan_get_strategy.argtypes = [P, P, P]
+    L.fem_plan_get_strategy.argtypes = [P, P, P, P]
     L.fem_plan_get_strategy.restype = i32
+    L.fem_tune.argtypes = [P, P, P, P, i32, ctypes.c_char_p, P, P, i32, P]
+    L.fem_tune.restype = i32
     L.fem_check_patch_layout.argtypes = [i32, i32, i32, i64, P, i64, P, P, i64, i32, P]
     L.fem_check_patch_layout.restype = i32
+    L.fem_batch_create.argtypes = [ctypes.POINTER(P), i32, P, P, P]
+    L.fem_batch_create.restype = i32
+    L.fem_batch_set_vectors.argtypes = [P, P, P]
+    L.fem_batch_set_vectors.restype = i32
+    L.fem_batch_run.argtypes = [P, P, i32]
+    L.fem_batch_run.restype = i32
+    L.fem_batch_info.argtypes = [P, P, P, P, P]
+    L.fem_batch_info.restype = i32
+    L.fem_batch_destroy.argtypes = [P]
+    L.fem_batch_destroy.restype = None
     L.fem_colouring.argtypes = [i64, i32, P, i64, P, P]
     L.fem_colouring.restype = i32
     L.fem_last_error.argtypes = []
@@ -93,18 +108,18 @@ def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def reference_tables(dim: int, degree: int, quad_degree: int):
+def reference_tables(dim: int, degree: int, quad_degree: int, family: int = 0):
     """The library's quadrature rule and tabulation: (points, weights, phi, dphi)."""
     L = lib()
     nq, nl = ctypes.c_int(), ctypes.c_int()
-    _check(L.fem_reference_tables(dim, degree, quad_degree, ctypes.byref(nq), ctypes.byref(nl),
-                                  None, None, None, None))
+    _check(L.fem_reference_tables(dim, degree, quad_degree, family, ctypes.byref(nq),
+                                  ctypes.byref(nl), None, None, None, None))
     pts = np.empty((nq.value, dim))
     w = np.empty(nq.value)
     phi = np.empty((nq.value, nl.value))
     dphi = np.empty((nq.value, nl.value, dim))
-    _check(L.fem_reference_tables(dim, degree, quad_degree, None, None, _np_ptr(pts), _np_ptr(w),
-                                  _np_ptr(phi), _np_ptr(dphi)))
+    _check(L.fem_reference_tables(dim, degree, quad_degree, family, None, None, _np_ptr(pts),
+                                  _np_ptr(w), _np_ptr(phi), _np_ptr(dphi)))
     return pts, w, phi, dphi
 
 
@@ -207,16 +222,40 @@ class Plan:
         except Exception:
             pass
 
+    def set_quadrature(self, family: int):
+        _check(lib().fem_plan_set_quadrature(self.handle, family))
+        nq = ctypes.c_int()
+        _check(lib().fem_plan_info(self.handle, None, None, ctypes.byref(nq), None, None))
+        self.n_quad = nq.value
+
     def set_block(self, cells_per_block: int):
         _check(lib().fem_plan_set_block(self.handle, cells_per_block))
 
-    def set_strategy(self, strategy: int, patch_cells: int = 0):
-        _check(lib().fem_plan_set_strategy(self.handle, strategy, patch_cells))
+    def set_strategy(self, strategy: int, patch_cells: int = 0, lanes_per_cell: int = 0):
+        _check(lib().fem_plan_set_strategy(self.handle, strategy, patch_cells, lanes_per_cell))
 
     def strategy(self):
-        st, pc = ctypes.c_int(), ctypes.c_int()
-        _check(lib().fem_plan_get_strategy(self.handle, ctypes.byref(st), ctypes.byref(pc)))
-        return st.value, pc.value
+        st, pc, ln = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().fem_plan_get_strategy(self.handle, ctypes.byref(st), ctypes.byref(pc),
+                                           ctypes.byref(ln)))
+        return st.value, pc.value, ln.value
+
+    def tune(self, u, y=None, v=None, cache_path: str | None = None, stream=None):
+        """Time every launch configuration on (u[, v]) and keep the fastest.
+
+        Returns a list of (strategy, cells_per_patch, lanes_per_cell, block, ms)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(u)
+        res = np.zeros((32, 5))
+        nres = ctypes.c_int()
+        vjp = v is not None
+        _check(lib().fem_tune(self.handle, _dev_ptr(u, self.n_dof, "u"),
+                              _dev_ptr(v, self.n_dof, "v") if vjp else None,
+                              _dev_ptr(y, self.n_dof, "y"), int(vjp),
+                              cache_path.encode() if cache_path else None, _stream_handle(stream),
+                              _np_ptr(res), 32, ctypes.byref(nres)))
+        return [tuple(r) for r in res[:nres.value]]
 
     def colouring(self) -> np.ndarray:
         out = np.empty(self.n_cell, dtype=np.int32)
@@ -241,6 +280,45 @@ class Plan:
                                     _dev_ptr(v, self.n_dof, "v"),
                                     _dev_ptr(out, self.n_dof, "g"), _stream_handle(stream)))
         return out
+
+
+class Batch:
+    """Many plans' actions in a few launches recorded into one HIP graph.
+
+    `us` and `ys` are float64 CUDA tensors (one per plan), bound at creation; keep them
+    alive (and the plans) as long as the batch."""
+
+    def __init__(self, plans, us, ys):
+        L = lib()
+        n = len(plans)
+        if not (len(us) == len(ys) == n) or n == 0:
+            raise ValueError("need one input and one output per plan")
+        self.plans, self.us, self.ys = list(plans), list(us), list(ys)
+        ph = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+        up = (ctypes.c_void_p * n)(*[_dev_ptr(u, p.n_dof, "u") for u, p in zip(us, plans)])
+        yp = (ctypes.c_void_p * n)(*[_dev_ptr(y, p.n_dof, "y") for y, p in zip(ys, plans)])
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(L.fem_batch_create(ctypes.byref(h), n, ph, up, yp))
+        self._h = h
+        nm, ng, npat, nsh = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+        _check(L.fem_batch_info(h, ctypes.byref(nm), ctypes.byref(ng), ctypes.byref(npat),
+                                ctypes.byref(nsh)))
+        self.n_groups, self.n_patches, self.n_shared = ng.value, npat.value, nsh.value
+
+    def run(self, graph: bool = True, stream=None):
+        _check(lib().fem_batch_run(self._h, _stream_handle(stream), int(graph)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fem_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _autograd_function():

@@ -23,6 +23,56 @@ __host__ __device__ constexpr int record_of(int form, int dim, int nloc)
     return (((form == FEM_MASS ? nloc : dim * nloc) + 1) + 1) & ~1;
 }
 
+// 1/d: hardware reciprocal estimate refined by two Newton-Raphson steps (each doubles the
+// number of correct bits), then one residual correction; within 1 ulp of 1/d for finite
+// nonzero normal d.
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+
+// Natural logarithm of a positive finite double by the classical reduction
+//   x = 2^e m,  m in [1/sqrt2, sqrt2),  ln m = 2 atanh(s),  s = (m-1)/(m+1),  |s| <= 0.1716,
+// with the Taylor series atanh(s) = s + s^3/3 + s^5/5 + ... summed to s^23 (the first
+// omitted term is below 2^-58 relative), and ln 2 split in two parts so that e ln 2 is
+// exact to double precision.  Error a few ulp; no special cases for x <= 0, inf or nan
+// (the forms only take logarithms of det F > 0).
+__device__ __forceinline__ double ln_pos(double x)
+{
+    int e = __builtin_amdgcn_frexp_exp(x);
+    double m = __builtin_amdgcn_frexp_mant(x);          // [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double num = m - 1.0, den = m + 1.0;
+    const double r = recip(den);
+    double s = num * r;
+    s = fma(fma(-s, den, num), r, s);                    // correct the quotient
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double lnm = fma(2.0 * s * z, p, 2.0 * s);     // 2 s (1 + z p)
+    const double fe = (double)e;
+    // ln 2 = ln2_hi + ln2_lo: ln2_hi is ln 2 truncated to 36 fraction bits (so e * ln2_hi is
+    // exact for any exponent of a double), ln2_lo the rounded remainder.
+    constexpr double ln2_hi = 0x1.62e42fefa0000p-1;
+    constexpr double ln2_lo = 1.6465949582897082e-12;
+    return fma(fe, ln2_hi, fma(fe, ln2_lo, lnm));
+}
+
 // K = J^{-1} and |det J| from the vertex coordinates (J[i][r] = x_{r+1,i} - x_{0,i}).
 template <int DIM>
 __device__ __forceinline__ double affine_geometry(const double (&x)[DIM + 1][DIM],
@@ -66,7 +116,7 @@ __device__ __forceinline__ double invert(const double (&A)[DIM][DIM], double (&B
 {
     if constexpr (DIM == 2) {
         const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
-        const double inv = 1.0 / det;
+        const double inv = recip(det);
         B[0][0] = A[1][1] * inv;
         B[0][1] = -A[0][1] * inv;
         B[1][0] = -A[1][0] * inv;
@@ -77,7 +127,7 @@ __device__ __forceinline__ double invert(const double (&A)[DIM][DIM], double (&B
         const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
         const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
         const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
-        const double inv = 1.0 / det;
+        const double inv = recip(det);
         B[0][0] = c00 * inv;
         B[1][0] = c01 * inv;
         B[2][0] = c02 * inv;
@@ -148,7 +198,7 @@ __device__ __forceinline__ void stress_neohookean(const double (&G)[DIM][DIM], d
 #pragma unroll
         for (int j = 0; j < DIM; ++j) F[i][j] = G[i][j] + (i == j ? 1.0 : 0.0);
     const double detF = invert<DIM>(F, Fi);
-    const double c = lam * log(detF) - mu;
+    const double c = lam * ln_pos(detF) - mu;
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
@@ -169,7 +219,7 @@ __device__ __forceinline__ void tangent_neohookean(const double (&G)[DIM][DIM],
 #pragma unroll
         for (int j = 0; j < DIM; ++j) F[i][j] = G[i][j] + (i == j ? 1.0 : 0.0);
     const double detF = invert<DIM>(F, Fi);
-    const double b = mu - lam * log(detF);
+    const double b = mu - lam * ln_pos(detF);
     double tr = 0.0;
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
@@ -270,6 +320,74 @@ __device__ __forceinline__ void cell_quadrature(
                     for (int c = 0; c < DIM; ++c) yl[n][c] = fma(tr, T[c][r], yl[n][c]);
                 }
         }
+    }
+}
+
+// Exchange a double with the neighbouring lane of the pair (lanes 2i <-> 2i+1) through
+// DPP quad permutation [1,0,3,2]; both lanes of a pair must be active.
+__device__ __forceinline__ double pair_swap(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// The 2D vector forms with the two components of a cell on a lane pair: lane c holds
+// component c of the cell's values and output, evaluates row c of the reference gradient,
+// swaps rows with its partner, evaluates the (whole) pointwise form, and accumulates the
+// row c of the stress against the test gradients.
+template <int FORM, int K, bool VJP>
+__device__ __forceinline__ void cell_quadrature_pair(
+    const double (&ul)[nloc_of(2, K)], const double (&vl)[VJP ? nloc_of(2, K) : 1], int c,
+    const double (&Kinv)[2][2], double adet, const double *table, int nq, double lam,
+    double mu, double (&yl)[nloc_of(2, K)])
+{
+    constexpr int NLOC = nloc_of(2, K);
+    constexpr int REC = record_of(FORM, 2, NLOC);
+    const FEMX_CONSTANT double *tab = (const FEMX_CONSTANT double *)table;
+    const bool odd = c != 0;
+#pragma unroll
+    for (int n = 0; n < NLOC; ++n) yl[n] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < nq; ++q) {
+        const FEMX_CONSTANT double *t = tab + q * REC;
+        double g0 = 0.0, g1 = 0.0, h0 = 0.0, h1 = 0.0;
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n) {
+            g0 = fma(t[n], ul[n], g0);
+            g1 = fma(t[NLOC + n], ul[n], g1);
+            if constexpr (VJP) {
+                h0 = fma(t[n], vl[n], h0);
+                h1 = fma(t[NLOC + n], vl[n], h1);
+            }
+        }
+        // rows of the reference gradient: this lane's row c and the partner's row 1 - c
+        const double o0 = pair_swap(g0), o1 = pair_swap(g1);
+        double gu[2][2], G[2][2], S[2][2], T[2][2];
+        gu[0][0] = odd ? o0 : g0;
+        gu[0][1] = odd ? o1 : g1;
+        gu[1][0] = odd ? g0 : o0;
+        gu[1][1] = odd ? g1 : o1;
+        to_physical<2>(gu, Kinv, G);
+        if constexpr (VJP) {
+            const double p0 = pair_swap(h0), p1 = pair_swap(h1);
+            double gv[2][2], H[2][2];
+            gv[0][0] = odd ? p0 : h0;
+            gv[0][1] = odd ? p1 : h1;
+            gv[1][0] = odd ? h0 : p0;
+            gv[1][1] = odd ? h1 : p1;
+            to_physical<2>(gv, Kinv, H);
+            tangent_neohookean<2>(G, H, lam, mu, S);
+        } else if constexpr (FORM == FEM_ELASTICITY) {
+            stress_elasticity<2>(G, lam, mu, S);
+        } else {
+            stress_neohookean<2>(G, lam, mu, S);
+        }
+        pull_back<2>(S, Kinv, t[2 * NLOC] * adet, T);
+        const double t0 = odd ? T[1][0] : T[0][0];
+        const double t1 = odd ? T[1][1] : T[0][1];
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n) yl[n] = fma(t[n], t0, fma(t[NLOC + n], t1, yl[n]));
     }
 }
 

@@ -19,6 +19,7 @@ struct Error : std::runtime_error {
 };
 
 void check_hip(hipError_t e, const char *what);
+std::string &last_error();   // thread-local message behind fem_last_error()
 
 inline int n_local(int dim, int k)
 {
@@ -33,7 +34,8 @@ struct RefTables {
     std::vector<double> phi;      // [nq][nloc]
     std::vector<double> dphi;     // [nq][nloc][dim]
 };
-RefTables reference_tables(int dim, int degree, int quad_degree);
+RefTables reference_tables(int dim, int degree, int quad_degree, int family = FEM_QUAD_CONICAL);
+bool has_symmetric_rule(int dim, int quad_degree);
 
 // Kernel-side table layout: per quadrature point a contiguous record.
 //   mass:  [phi_0 .. phi_{nloc-1}, w]                       (nloc + 1 doubles)
@@ -82,10 +84,27 @@ struct PatchArgs {
 
 enum Strategy { STRAT_COLOUR = 0, STRAT_PATCH = 1 };
 
+// One mesh of a batched launch (device-resident array of these).
+struct BatchDesc {
+    PatchArgs args;
+    int64_t first_patch;     // index of the mesh's first patch in the launch
+};
+
+// Shared-node sums of one mesh of a batch.
+struct FixDesc {
+    const int32_t *fix_node;
+    const int32_t *fix_off;
+    const double *partial;
+    double *y;
+    int64_t first;           // index of the mesh's first shared node in the launch
+    int ncomp;
+};
+
 }  // namespace femx
 
 struct fem_plan {
     int form = 0, dim = 0, degree = 0, quad_degree = 0, nloc = 0, ncomp = 0, nq = 0;
+    int quad_family = FEM_QUAD_CONICAL;
     int64_t n_vert = 0, n_cell = 0, n_node = 0, n_dof = 0;
     double lam = 0.0, mu = 0.0;
     int n_colours = 0;
@@ -104,6 +123,7 @@ struct fem_plan {
     // patch strategy
     int strategy = femx::STRAT_PATCH;
     int patch = 0;                       // cells per patch (0: not built)
+    int lanes = 1;                       // lanes per cell in the patch kernel (1 or 2)
     int64_t n_patch = 0, n_pn = 0, n_partial = 0, n_shared = 0;
     int max_patch_nodes = 0;
     int32_t *d_pverts = nullptr;
@@ -129,6 +149,19 @@ hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double 
 // `max_nodes` distinct nodes.
 size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes);
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
+bool pair_available(int form, int dim, int degree);
+hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch,
+                              const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
+                              size_t lds, hipStream_t s);
+hipError_t launch_batch_fixup(const FixDesc *fix, int n_mesh, int64_t n, hipStream_t s);
+// plan.cpp (throwing versions of the ABI calls, for the tuner and the batch)
+void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell);
+void run_action(const fem_plan *p, const double *u, const double *v, double *y, hipStream_t s,
+                bool vjp);
+// tune.cpp
+void apply_tuning_cache(fem_plan *p);
+int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
+         hipStream_t s, double *results, int max_results, int *n_results);
 hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t n_shared,
                         const double *partial, int ncomp, double *y, hipStream_t s);
 }  // namespace femx

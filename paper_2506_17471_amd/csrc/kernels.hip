@@ -31,6 +31,15 @@ namespace {
 
 constexpr int kMaxBlock = 256;
 
+// Waves per SIMD the register allocator is asked to leave room for (occupancy target):
+// the lane-pair kernels and the one-lane low-degree 2D kernels fit without spilling in
+// the loop; everything else keeps the allocator's default.
+constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc)
+{
+    if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : 4;
+    return (!vjp && dim == 2 && k <= 4 && form != FEM_MASS) ? 3 : 1;
+}
+
 template <int DIM>
 __device__ __forceinline__ double gather_geometry(const int32_t *__restrict__ verts,
                                                   int64_t stride, int64_t s,
@@ -85,20 +94,24 @@ __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
 }
 
 // ------------------------------------------------------------------- patch strategy
-template <int FORM, int DIM, int K, bool VJP>
-__global__ void __launch_bounds__(kMaxBlock) patch_kernel(const PatchArgs a, int logp)
+// LPC lanes per cell: 1, or 2 for the 2D vector forms (lane c of a pair owns component c).
+template <int FORM, int DIM, int K, bool VJP, int LPC>
+__device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int logp)
 {
     constexpr int NLOC = nloc_of(DIM, K);
     constexpr int NC = FORM == FEM_MASS ? 1 : DIM;
+    static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && FORM != FEM_MASS), "lane split");
     extern __shared__ double lds[];
-    const int P = 1 << logp;
+    const int P = 1 << logp;                  // cells per patch
     const int tid = threadIdx.x;
-    const int64_t p = blockIdx.x;
+    const int nthreads = P * LPC;
+    const int cl = LPC == 1 ? tid : tid >> 1; // local cell
+    const int comp = LPC == 1 ? 0 : tid & 1;
     const int nb = a.patch_off[p];
     const int U = a.patch_off[p + 1] - nb;
 
     // 1. stage the values of the patch's distinct nodes
-    for (int j = tid; j < U; j += P) {
+    for (int j = tid; j < U; j += nthreads) {
         const int64_t nd = a.patch_nodes[nb + j];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -109,19 +122,20 @@ __global__ void __launch_bounds__(kMaxBlock) patch_kernel(const PatchArgs a, int
     __syncthreads();
 
     // 2. gather the cell's values from LDS and its geometry from global memory
-    const int64_t s = (p << logp) + tid;
+    const int64_t s = (p << logp) + cl;
     const bool active = s < a.n_cell;
+    constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
     double Kinv[DIM][DIM], adet = 0.0;
-    double ul[NLOC][NC], vl[VJP ? NLOC : 1][NC], yl[NLOC][NC];
+    double ul[NLOC][CW], vl[VJP ? NLOC : 1][CW], yl[NLOC][CW];
     if (active) {
         adet = gather_geometry<DIM>(a.verts, a.stride, s, a.coords, Kinv);
 #pragma unroll
         for (int n = 0; n < NLOC; ++n) {
             const int l = a.lidx[n * a.stride + s];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                ul[n][c] = lds[l * NC + c];
-                if constexpr (VJP) vl[n][c] = lds[(U + l) * NC + c];
+            for (int c = 0; c < CW; ++c) {
+                ul[n][c] = lds[l * NC + c + comp];
+                if constexpr (VJP) vl[n][c] = lds[(U + l) * NC + c + comp];
             }
         }
     }
@@ -129,25 +143,38 @@ __global__ void __launch_bounds__(kMaxBlock) patch_kernel(const PatchArgs a, int
 
     // 3. the cell's quadrature loop; its vector goes to the element buffer
     if (active) {
-        cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
+        if constexpr (LPC == 1) {
+            cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
+        } else {
+            double u1[NLOC], v1[VJP ? NLOC : 1], y1[NLOC];
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) {
+                u1[n] = ul[n][0];
+                if constexpr (VJP) v1[n] = vl[n][0];
+            }
+            cell_quadrature_pair<FORM, K, VJP>(u1, v1, comp, Kinv, adet, a.tab, a.nq, a.lam, a.mu,
+                                               y1);
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) yl[n][0] = y1[n];
+        }
 #pragma unroll
         for (int n = 0; n < NLOC; ++n)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) lds[(n * NC + c) * P + tid] = yl[n][c];
+            for (int c = 0; c < CW; ++c) lds[(n * NC + c + comp) * P + cl] = yl[n][c];
     }
     __syncthreads();
 
     // 4. each distinct node summed by one lane in a fixed order
-    for (int j = tid; j < U; j += P) {
+    for (int j = tid; j < U; j += nthreads) {
         const int e0 = a.csr_off[nb + j], e1 = a.csr_off[nb + j + 1];
         double sum[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) sum[c] = 0.0;
         for (int e = e0; e < e1; ++e) {
             const int sl = a.csr_slots[e];
-            const int an = sl >> logp, cl = sl & (P - 1);
+            const int an = sl >> logp, sc = sl & (P - 1);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sum[c] += lds[(an * NC + c) * P + cl];
+            for (int c = 0; c < NC; ++c) sum[c] += lds[(an * NC + c) * P + sc];
         }
         const int dest = a.patch_dest[nb + j];
         if (dest < 0) {
@@ -158,6 +185,49 @@ __global__ void __launch_bounds__(kMaxBlock) patch_kernel(const PatchArgs a, int
 #pragma unroll
             for (int c = 0; c < NC; ++c) a.partial[(int64_t)dest * NC + c] = sum[c];
         }
+    }
+}
+
+template <int FORM, int DIM, int K, bool VJP, int LPC>
+__global__ void __launch_bounds__(kMaxBlock)
+    __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
+    patch_kernel(const PatchArgs a, int logp)
+{
+    patch_body<FORM, DIM, K, VJP, LPC>(a, blockIdx.x, logp);
+}
+
+// Many meshes of one kernel variant in one launch: workgroup b works on patch
+// b - desc[m].first_patch of mesh m = patch_mesh[b].
+template <int FORM, int DIM, int K, bool VJP, int LPC>
+__global__ void __launch_bounds__(kMaxBlock)
+    __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
+    batch_patch_kernel(const BatchDesc *__restrict__ desc, const int32_t *__restrict__ patch_mesh,
+                       int logp)
+{
+    const int m = patch_mesh[blockIdx.x];
+    const BatchDesc &d = desc[m];
+    patch_body<FORM, DIM, K, VJP, LPC>(d.args, (int64_t)blockIdx.x - d.first_patch, logp);
+}
+
+// Shared-node sums of many meshes: thread i sums shared node i - fix[m].first of the mesh m
+// whose range holds i (binary search over the meshes' first indices).
+__global__ void batch_fixup_kernel(const FixDesc *__restrict__ fix, int n_mesh, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = n_mesh - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (fix[mid].first <= i) lo = mid; else hi = mid - 1;
+    }
+    const FixDesc &f = fix[lo];
+    const int64_t k = i - f.first;
+    const int64_t nd = f.fix_node[k];
+    const int o0 = f.fix_off[k], o1 = f.fix_off[k + 1];
+    for (int c = 0; c < f.ncomp; ++c) {
+        double s = 0.0;
+        for (int o = o0; o < o1; ++o) s += f.partial[(int64_t)o * f.ncomp + c];
+        f.y[nd * f.ncomp + c] = s;
     }
 }
 
@@ -188,16 +258,26 @@ __global__ void zero_nodes_kernel(const int32_t *__restrict__ nodes, int64_t n, 
 // ----------------------------------------------------------------------- dispatch
 using ColourFn = void (*)(const LaunchArgs);
 using PatchFn = void (*)(const PatchArgs, int);
+using BatchFn = void (*)(const BatchDesc *, const int32_t *, int);
 
 struct Kernels {
     ColourFn colour;
     PatchFn patch;
+    PatchFn patch_pair;   // two lanes per cell (2D vector forms), else null
+    BatchFn batch;
+    BatchFn batch_pair;
 };
 
 template <int FORM, int DIM, int K, bool VJP>
 Kernels entry()
 {
-    return {colour_kernel<FORM, DIM, K, VJP>, patch_kernel<FORM, DIM, K, VJP>};
+    if constexpr (DIM == 2 && FORM != FEM_MASS)
+        return {colour_kernel<FORM, DIM, K, VJP>, patch_kernel<FORM, DIM, K, VJP, 1>,
+                patch_kernel<FORM, DIM, K, VJP, 2>, batch_patch_kernel<FORM, DIM, K, VJP, 1>,
+                batch_patch_kernel<FORM, DIM, K, VJP, 2>};
+    else
+        return {colour_kernel<FORM, DIM, K, VJP>, patch_kernel<FORM, DIM, K, VJP, 1>, nullptr,
+                batch_patch_kernel<FORM, DIM, K, VJP, 1>, nullptr};
 }
 
 template <int DIM, int K>
@@ -211,7 +291,7 @@ Kernels pick(int form, bool vjp)
 
 Kernels lookup(int form, int dim, int degree, bool vjp)
 {
-    if (form < FEM_MASS || form > FEM_NEOHOOKEAN) return {nullptr, nullptr};
+    if (form < FEM_MASS || form > FEM_NEOHOOKEAN) return {nullptr, nullptr, nullptr, nullptr, nullptr};
     if (dim == 2) {
         switch (degree) {
         case 1: return pick<2, 1>(form, vjp);
@@ -231,7 +311,7 @@ Kernels lookup(int form, int dim, int degree, bool vjp)
         default: break;
         }
     }
-    return {nullptr, nullptr};
+    return {nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
 int log2_exact(int v)
@@ -270,28 +350,61 @@ size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int m
     return 8 * (stage > elem ? stage : elem);
 }
 
+bool pair_available(int form, int dim, int degree)
+{
+    return lookup(form, dim, degree, false).patch_pair != nullptr;
+}
+
+hipError_t allow_lds(const void *fn, size_t lds)
+{
+    if (lds <= 64 * 1024) return hipSuccess;
+    static std::mutex mu;
+    static std::set<const void *> raised;
+    std::lock_guard<std::mutex> g(mu);
+    if (raised.count(fn)) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess) raised.insert(fn);
+    return e;
+}
+
+hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch,
+                              const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
+                              size_t lds, hipStream_t s)
+{
+    const Kernels ks = lookup(form, dim, degree, false);
+    BatchFn fn = lanes == 2 ? ks.batch_pair : ks.batch;
+    if (!fn) return hipErrorInvalidDeviceFunction;
+    const int logp = log2_exact(patch);
+    if (logp < 0 || patch * lanes > kMaxBlock || lds > 160 * 1024 || n_patch > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    hipError_t e = allow_lds((const void *)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_patch), dim3(patch * lanes), lds, s, desc, patch_mesh,
+                       logp);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fixup(const FixDesc *fix, int n_mesh, int64_t n, hipStream_t s)
+{
+    const int block = 256;
+    const int64_t grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(batch_fixup_kernel, dim3((unsigned)grid), dim3(block), 0, s, fix, n_mesh, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s)
 {
-    PatchFn fn = lookup(p.form, p.dim, p.degree, vjp).patch;
+    const Kernels ks = lookup(p.form, p.dim, p.degree, vjp);
+    PatchFn fn = p.lanes == 2 ? ks.patch_pair : ks.patch;
     if (!fn) return hipErrorInvalidDeviceFunction;
     const int logp = log2_exact(p.patch);
-    if (logp < 0 || p.patch > kMaxBlock) return hipErrorInvalidConfiguration;
+    if (logp < 0 || p.patch * p.lanes > kMaxBlock) return hipErrorInvalidConfiguration;
     const size_t lds = patch_lds_bytes(p.form, p.dim, p.degree, vjp, p.patch, p.max_patch_nodes);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-    if (lds > 64 * 1024) {
-        static std::mutex mu;
-        static std::set<const void *> raised;
-        std::lock_guard<std::mutex> g(mu);
-        if (!raised.count((const void *)fn)) {
-            hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               160 * 1024);
-            if (e != hipSuccess) return e;
-            raised.insert((const void *)fn);
-        }
-    }
+    hipError_t e = allow_lds((const void *)fn, lds);
+    if (e != hipSuccess) return e;
     if (p.n_patch > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(fn, dim3((unsigned)p.n_patch), dim3(p.patch), lds, s, a, logp);
+    hipLaunchKernelGGL(fn, dim3((unsigned)p.n_patch), dim3(p.patch * p.lanes), lds, s, a, logp);
     return hipGetLastError();
 }
 

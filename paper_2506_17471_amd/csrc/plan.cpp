@@ -16,8 +16,16 @@
 
 #include "internal.h"
 
+namespace femx {
+std::string &last_error()
+{
+    static thread_local std::string msg;
+    return msg;
+}
+}  // namespace femx
+
 namespace {
-thread_local std::string g_last_error;
+#define g_last_error femx::last_error()
 
 int fail(const femx::Error &e)
 {
@@ -137,6 +145,7 @@ int greedy_colouring(int64_t n_cell, int nloc, const int32_t *cell_nodes, int64_
 void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
                    const int32_t *cell_nodes, int P);
 int default_patch(const fem_plan *p);
+int default_lanes(const fem_plan *p);
 
 // Host-side validation of the mesh; runs before any HIP call.
 void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
@@ -180,7 +189,12 @@ void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
 {
     const int d = p->dim, nv = d + 1, nloc = p->nloc;
     // --- reference tables
-    femx::RefTables t = femx::reference_tables(d, p->degree, p->quad_degree);
+    // the linear forms integrate polynomials exactly, so the rule with fewest points that
+    // has the requested degree gives the same operator; the neo-Hookean integrand is not
+    // polynomial and keeps the conical rule
+    p->quad_family = (p->form != FEM_NEOHOOKEAN && femx::has_symmetric_rule(d, p->quad_degree))
+                         ? FEM_QUAD_SYMMETRIC : FEM_QUAD_CONICAL;
+    femx::RefTables t = femx::reference_tables(d, p->degree, p->quad_degree, p->quad_family);
     p->nq = t.nq;
     std::vector<double> tab = femx::kernel_table(p->form, t);
 
@@ -222,6 +236,7 @@ void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
     p->d_first = device_upload(first, "first-touch masks");
     p->d_tab = device_upload(tab, "tables");
     p->d_untouched = device_upload(untouched, "untouched nodes");
+    p->lanes = default_lanes(p);
     if (p->n_cell > 0) build_patches(p, coords, cell_verts, cell_nodes, default_patch(p));
     else p->strategy = femx::STRAT_COLOUR;
 }
@@ -449,13 +464,21 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
     }
 }
 
-int default_patch(const fem_plan *p)
+int default_lanes(const fem_plan *p)
 {
-    // the largest power-of-two patch whose element buffer fits in 64 KB of LDS
+    return femx::pair_available(p->form, p->dim, p->degree) ? 2 : 1;
+}
+
+int default_patch_for(const fem_plan *p, int lanes)
+{
+    // the largest power-of-two patch whose workgroup fits 256 lanes and whose element
+    // buffer fits 64 KB of LDS
     for (int P = 256; P >= 64; P /= 2)
-        if ((size_t)P * p->nloc * p->ncomp * 8 <= 64 * 1024) return P;
+        if (P * lanes <= 256 && (size_t)P * p->nloc * p->ncomp * 8 <= 64 * 1024) return P;
     return 64;
 }
+
+int default_patch(const fem_plan *p) { return default_patch_for(p, p->lanes); }
 
 void check_plan(const fem_plan *p)
 {
@@ -530,6 +553,39 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
 }  // namespace
 
 namespace femx {
+void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell)
+{
+    check_plan(plan);
+    if (strategy == FEM_SCATTER_COLOUR) {
+        if (patch_cells != 0 || lanes_per_cell > 1)
+            throw Error(FEM_E_ARG, "the colour strategy takes no patch size or lane split");
+        plan->strategy = STRAT_COLOUR;
+        return;
+    }
+    if (strategy != FEM_SCATTER_PATCH) throw Error(FEM_E_ARG, "unknown strategy");
+    if (plan->n_cell == 0) throw Error(FEM_E_ARG, "empty mesh has no patches");
+    const int lanes = lanes_per_cell == 0 ? default_lanes(plan) : lanes_per_cell;
+    if (lanes != 1 && lanes != 2) throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1 or 2");
+    if (lanes == 2 && !pair_available(plan->form, plan->dim, plan->degree))
+        throw Error(FEM_E_UNSUPPORTED, "two lanes per cell exist for the 2D vector forms only");
+    const int P = patch_cells == 0 ? default_patch_for(plan, lanes) : patch_cells;
+    if (P * lanes > 256) throw Error(FEM_E_ARG, "patch_cells * lanes_per_cell exceeds 256");
+    if (P != plan->patch) {
+        if (plan->h_cell_verts.empty()) throw Error(FEM_E_ARG, "plan keeps no host mesh");
+        check_hip(hipDeviceSynchronize(), "synchronise before rebuilding patches");
+        build_patches(plan, plan->h_coords.data(), plan->h_cell_verts.data(),
+                      plan->h_cell_nodes.data(), P);
+    }
+    plan->lanes = lanes;
+    plan->strategy = STRAT_PATCH;
+}
+
+void run_action(const fem_plan *p, const double *u, const double *v, double *y, hipStream_t s,
+                bool vjp)
+{
+    run(p, u, v, y, (void *)s, vjp);
+}
+
 void check_hip(hipError_t e, const char *what)
 {
     if (e != hipSuccess) {
@@ -579,6 +635,7 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
         p->h_cell_nodes.assign(cell_nodes, cell_nodes + n_cell * p->nloc);
         femx::check_hip(hipGetDevice(&p->device), "hipGetDevice");
         build_plan(p, coords, cell_verts, cell_nodes);
+        femx::apply_tuning_cache(p);
     });
     if (st != FEM_OK) {
         free_plan_memory(p);
@@ -629,11 +686,11 @@ int fem_plan_colouring(const fem_plan *plan, int32_t *colour)
     });
 }
 
-int fem_reference_tables(int dim, int degree, int quad_degree, int *n_quad, int *n_loc,
-                         double *points, double *weights, double *phi, double *dphi)
+int fem_reference_tables(int dim, int degree, int quad_degree, int family, int *n_quad,
+                         int *n_loc, double *points, double *weights, double *phi, double *dphi)
 {
     return guarded([&] {
-        femx::RefTables t = femx::reference_tables(dim, degree, quad_degree);
+        femx::RefTables t = femx::reference_tables(dim, degree, quad_degree, family);
         if (n_quad) *n_quad = t.nq;
         if (n_loc) *n_loc = t.nloc;
         if (!points) return;
@@ -695,6 +752,7 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
         p.n_node = n_node;
         const double lm[2] = {1.0, 1.0};
         validate_mesh(&p, coords, cell_verts, cell_nodes, lm, 2);
+        p.lanes = default_lanes(&p);
         const int P = patch_cells == 0 ? default_patch(&p) : patch_cells;
         PatchLayout L = make_patch_layout(&p, coords, cell_verts, cell_nodes, P);
         validate_patch_layout(&p, L, cell_nodes);
@@ -711,34 +769,49 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
     });
 }
 
-int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells)
+int fem_plan_set_quadrature(fem_plan *plan, int family)
 {
     return guarded([&] {
         check_plan(plan);
-        if (strategy == FEM_SCATTER_COLOUR) {
-            if (patch_cells != 0) throw femx::Error(FEM_E_ARG, "patch_cells must be 0 for colours");
-            plan->strategy = femx::STRAT_COLOUR;
-            return;
-        }
-        if (strategy != FEM_SCATTER_PATCH) throw femx::Error(FEM_E_ARG, "unknown strategy");
-        if (plan->n_cell == 0) throw femx::Error(FEM_E_ARG, "empty mesh has no patches");
-        const int P = patch_cells == 0 ? default_patch(plan) : patch_cells;
-        if (P != plan->patch) {
-            if (!plan->h_cell_verts.size()) throw femx::Error(FEM_E_ARG, "plan keeps no host mesh");
-            femx::check_hip(hipDeviceSynchronize(), "synchronise before rebuilding patches");
-            build_patches(plan, plan->h_coords.data(), plan->h_cell_verts.data(),
-                          plan->h_cell_nodes.data(), P);
-        }
-        plan->strategy = femx::STRAT_PATCH;
+        femx::RefTables t = femx::reference_tables(plan->dim, plan->degree, plan->quad_degree, family);
+        std::vector<double> tab = femx::kernel_table(plan->form, t);
+        double *d = device_upload(tab, "tables");
+        femx::check_hip(hipDeviceSynchronize(), "synchronise before replacing tables");
+        (void)hipFree(plan->d_tab);
+        plan->d_tab = d;
+        plan->nq = t.nq;
+        plan->quad_family = family;
     });
 }
 
-int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells)
+int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell)
+{
+    return guarded([&] { femx::set_strategy(plan, strategy, patch_cells, lanes_per_cell); });
+}
+
+int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vjp,
+             const char *cache_path, void *stream, double *results, int max_results,
+             int *n_results)
 {
     return guarded([&] {
         check_plan(plan);
-        if (strategy) *strategy = plan->strategy == femx::STRAT_PATCH ? FEM_SCATTER_PATCH : FEM_SCATTER_COLOUR;
-        if (patch_cells) *patch_cells = plan->strategy == femx::STRAT_PATCH ? plan->patch : 0;
+        if (plan->n_cell == 0) throw femx::Error(FEM_E_ARG, "nothing to tune on an empty mesh");
+        if (!u || !y || (vjp && !v)) throw femx::Error(FEM_E_ARG, "null vector");
+        if (max_results < 0) throw femx::Error(FEM_E_ARG, "negative max_results");
+        femx::tune(plan, u, v, y, vjp != 0, cache_path, (hipStream_t)stream, results, max_results,
+                   n_results);
+    });
+}
+
+int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
+                          int *lanes_per_cell)
+{
+    return guarded([&] {
+        check_plan(plan);
+        const bool patch = plan->strategy == femx::STRAT_PATCH;
+        if (strategy) *strategy = patch ? FEM_SCATTER_PATCH : FEM_SCATTER_COLOUR;
+        if (patch_cells) *patch_cells = patch ? plan->patch : 0;
+        if (lanes_per_cell) *lanes_per_cell = patch ? plan->lanes : 1;
     });
 }
 

@@ -11,6 +11,7 @@
 // Basis: equispaced P_k Lagrange in barycentric product form; the derivative of each
 // factor product is carried along the product recurrence.
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -121,6 +122,38 @@ void conical_rule(int dim, int degree, std::vector<double> &pts, std::vector<dou
     }
 }
 
+// Fully symmetric rules of degree <= 2 from their moment equations (closed form).
+//   degree <= 1: the centroid, weight |T|.
+//   degree 2, triangle: the orbit of (a, b, b), a = 1 - 2b, weight |T|/3 each; matching
+//     int lambda_1^2 = |T|/6 gives 6b^2 - 4b + 1/2 = 0, b = 1/6 (the interior root).
+//   degree 2, tetrahedron: the orbit of (a, b, b, b), a = 1 - 3b, weight |T|/4 each;
+//     int lambda_1^2 = |T|/10 gives 12b^2 - 6b + 3/5 = 0, b = (5 - sqrt 5)/20.
+// Returns false when no such rule is built for (dim, degree).
+bool symmetric_rule(int dim, int degree, std::vector<double> &pts, std::vector<double> &wts)
+{
+    pts.clear();
+    wts.clear();
+    const double vol = dim == 2 ? 0.5 : 1.0 / 6.0;
+    if (degree <= 1) {
+        for (int r = 0; r < dim; ++r) pts.push_back(1.0 / (dim + 1));
+        wts.push_back(vol);
+        return true;
+    }
+    if (degree != 2) return false;
+    double b;
+    if (dim == 2) {
+        b = (4.0 - std::sqrt(16.0 - 12.0)) / 12.0;            // roots of 6b^2 - 4b + 1/2
+    } else {
+        b = (6.0 - std::sqrt(36.0 - 4.0 * 12.0 * 0.6)) / 24.0; // roots of 12b^2 - 6b + 3/5
+    }
+    const double a = 1.0 - dim * b;
+    for (int k = 0; k <= dim; ++k) {          // the point with barycentric a in slot k
+        for (int r = 0; r < dim; ++r) pts.push_back(r + 1 == k ? a : b);
+        wts.push_back(vol / (dim + 1));
+    }
+    return true;
+}
+
 // reference lattice multi-indices, first coordinate fastest
 std::vector<int> lattice(int dim, int k)
 {
@@ -157,7 +190,7 @@ void factor(int k, int m, double lam, double &f, double &df)
 
 }  // namespace
 
-RefTables reference_tables(int dim, int degree, int quad_degree)
+RefTables reference_tables(int dim, int degree, int quad_degree, int family)
 {
     if (dim != 2 && dim != 3) throw Error(FEM_E_UNSUPPORTED, "dim must be 2 or 3");
     if (degree < 1 || degree > 8) throw Error(FEM_E_UNSUPPORTED, "degree out of range");
@@ -167,7 +200,14 @@ RefTables reference_tables(int dim, int degree, int quad_degree)
     t.dim = dim;
     t.degree = degree;
     t.quad_degree = quad_degree;
-    conical_rule(dim, quad_degree, t.points, t.weights);
+    if (family == FEM_QUAD_SYMMETRIC) {
+        if (!symmetric_rule(dim, quad_degree, t.points, t.weights))
+            throw Error(FEM_E_UNSUPPORTED, "no symmetric rule of degree " + std::to_string(quad_degree));
+    } else if (family == FEM_QUAD_CONICAL) {
+        conical_rule(dim, quad_degree, t.points, t.weights);
+    } else {
+        throw Error(FEM_E_ARG, "unknown quadrature family");
+    }
     t.nq = (int)t.weights.size();
     const std::vector<int> lat = lattice(dim, degree);
     t.nloc = (int)lat.size() / dim;
@@ -227,6 +267,12 @@ std::vector<double> kernel_table(int form, const RefTables &t)
         }
     }
     return out;
+}
+
+bool has_symmetric_rule(int dim, int quad_degree)
+{
+    std::vector<double> p, w;
+    return symmetric_rule(dim, quad_degree, p, w);
 }
 
 }  // namespace femx

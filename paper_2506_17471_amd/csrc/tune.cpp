@@ -1,0 +1,205 @@
+// Autotuner: measures the launch configurations of a plan and keeps the fastest.
+//
+// Candidates: the colour strategy with 64/128/256 cells per workgroup, and the patch
+// strategy with 64/128/256 cells per patch and one or (2D vector forms) two lanes per
+// cell.  Each candidate is timed with HIP events on the caller's stream using the paper's
+// protocol (Sec. 6.2.1): five warm-up runs, then timed runs until 15 have been collected
+// or 0.2 s has accumulated, the arithmetic mean being the candidate's time.  Results can
+// be kept in a small JSON cache keyed by device architecture, form, dimension, degree,
+// quadrature degree and log2 of the cell count, which fem_plan_create consults when the
+// environment variable FEM_TUNE_CACHE names the file.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+struct Candidate {
+    int strategy, patch, lanes, block;
+};
+
+std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string s = prop.gcnArchName;
+    const size_t colon = s.find(':');
+    return colon == std::string::npos ? s : s.substr(0, colon);
+}
+
+std::string cache_key(const fem_plan *p)
+{
+    const int bucket = p->n_cell > 0 ? (int)std::lround(std::log2((double)p->n_cell)) : 0;
+    std::ostringstream k;
+    k << arch_name() << "/f" << p->form << "/d" << p->dim << "/k" << p->degree << "/q"
+      << p->quad_degree << "/c" << bucket;
+    return k.str();
+}
+
+// The cache file: one JSON object whose values are [strategy, patch, lanes, block, ms].
+std::map<std::string, std::vector<double>> read_cache(const std::string &path)
+{
+    std::map<std::string, std::vector<double>> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = s.substr(i + 1, j - i - 1);
+        const size_t lb = s.find('[', j), rb = s.find(']', j);
+        if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+        std::vector<double> vals;
+        std::stringstream vs(s.substr(lb + 1, rb - lb - 1));
+        std::string tok;
+        while (std::getline(vs, tok, ',')) vals.push_back(std::atof(tok.c_str()));
+        if (vals.size() == 5) out[key] = vals;
+        i = rb + 1;
+    }
+    return out;
+}
+
+void write_cache(const std::string &path, const std::map<std::string, std::vector<double>> &c)
+{
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) throw femx::Error(FEM_E_ARG, "cannot write tuning cache " + path);
+        f << "{\n";
+        size_t n = 0;
+        for (const auto &kv : c) {
+            f << "  \"" << kv.first << "\": [" << (int)kv.second[0] << ", " << (int)kv.second[1]
+              << ", " << (int)kv.second[2] << ", " << (int)kv.second[3] << ", " << kv.second[4]
+              << "]" << (++n < c.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0)
+        throw femx::Error(FEM_E_ARG, "cannot replace tuning cache " + path);
+}
+
+void apply(fem_plan *p, const Candidate &c)
+{
+    if (c.strategy == FEM_SCATTER_COLOUR) {
+        femx::set_strategy(p, FEM_SCATTER_COLOUR, 0, 0);
+        p->block = c.block;
+    } else {
+        femx::set_strategy(p, FEM_SCATTER_PATCH, c.patch, c.lanes);
+    }
+}
+
+double time_candidate(fem_plan *p, const double *u, const double *v, double *y, bool vjp,
+                      hipStream_t s)
+{
+    hipEvent_t a, b;
+    femx::check_hip(hipEventCreate(&a), "hipEventCreate");
+    femx::check_hip(hipEventCreate(&b), "hipEventCreate");
+    auto once = [&] { femx::run_action(p, u, v, y, s, vjp); };
+    double total = 0.0;
+    int runs = 0;
+    try {
+        for (int i = 0; i < 5; ++i) once();
+        while (runs < 15 && total < 0.2) {
+            femx::check_hip(hipEventRecord(a, s), "hipEventRecord");
+            once();
+            femx::check_hip(hipEventRecord(b, s), "hipEventRecord");
+            femx::check_hip(hipEventSynchronize(b), "hipEventSynchronize");
+            float ms = 0.f;
+            femx::check_hip(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+            total += ms * 1e-3;
+            ++runs;
+        }
+    } catch (...) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        throw;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return total / runs * 1e3;
+}
+
+}  // namespace
+
+namespace femx {
+
+// Apply a cached configuration for this plan, if FEM_TUNE_CACHE names a file holding one.
+void apply_tuning_cache(fem_plan *p)
+{
+    const char *path = std::getenv("FEM_TUNE_CACHE");
+    if (!path || !*path || p->n_cell == 0) return;
+    const auto cache = read_cache(path);
+    const auto it = cache.find(cache_key(p));
+    if (it == cache.end()) return;
+    const auto &v = it->second;
+    Candidate c{(int)v[0], (int)v[1], (int)v[2], (int)v[3]};
+    try {
+        apply(p, c);
+    } catch (const Error &) {
+        // a stale or foreign entry: keep the defaults
+    }
+}
+
+int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
+         hipStream_t s, double *results, int max_results, int *n_results)
+{
+    std::vector<Candidate> cands;
+    for (int blk : {64, 128, 256}) cands.push_back({FEM_SCATTER_COLOUR, 0, 1, blk});
+    const bool pair = pair_available(p->form, p->dim, p->degree);
+    for (int lanes : {1, 2}) {
+        if (lanes == 2 && !pair) continue;
+        for (int P : {64, 128, 256})
+            if (P * lanes <= 256) cands.push_back({FEM_SCATTER_PATCH, P, lanes, 0});
+    }
+    double best = 1e300;
+    Candidate best_c = cands[0];
+    int nres = 0;
+    for (const Candidate &c : cands) {
+        double ms;
+        try {
+            apply(p, c);
+            ms = time_candidate(p, u, v, y, vjp, s);
+        } catch (const Error &e) {
+            if (e.code != FEM_E_UNSUPPORTED) throw;
+            continue;   // e.g. a patch that needs more LDS than a workgroup has
+        }
+        if (results && nres < max_results) {
+            double *r = results + 5 * nres;
+            r[0] = c.strategy;
+            r[1] = c.patch;
+            r[2] = c.lanes;
+            r[3] = c.block;
+            r[4] = ms;
+        }
+        ++nres;
+        if (ms < best) {
+            best = ms;
+            best_c = c;
+        }
+    }
+    if (n_results) *n_results = nres;
+    apply(p, best_c);
+    if (cache && *cache) {
+        auto c = read_cache(cache);
+        c[cache_key(p)] = {(double)best_c.strategy, (double)best_c.patch, (double)best_c.lanes,
+                           (double)best_c.block, best};
+        write_cache(cache, c);
+    }
+    return FEM_OK;
+}
+
+}  // namespace femx

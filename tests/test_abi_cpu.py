@@ -135,3 +135,22 @@ def test_patch_layout_rejects_bad_size():
     m = meshgen.unit_square(4, 2)
     with pytest.raises(fx.FemError):
         fx.check_patch_layout(0, m, 100)
+
+
+@pytest.mark.parametrize("dim,deg", [(2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2)])
+def test_symmetric_rules_exact(dim, deg):
+    import itertools
+    import math
+    pts, w, phi, dphi = fx.reference_tables(dim, 2, deg, fx.QUAD_SYMMETRIC)
+    assert len(w) == {0: 1, 1: 1, 2: dim + 1}[deg]
+    assert np.all(w > 0) and np.all(pts > 0) and np.all(pts.sum(1) < 1)
+    for b in itertools.product(range(deg + 1), repeat=dim):
+        if sum(b) > deg:
+            continue
+        ref = math.prod(math.factorial(x) for x in b) / math.factorial(sum(b) + dim)
+        assert abs(np.sum(w * np.prod(pts ** np.asarray(b), axis=1)) - ref) <= 1e-15 * ref
+    # tabulation at the symmetric points agrees with the oracle's basis at the same points
+    ophi, odphi = basis.tabulate(dim, 2, pts)
+    assert np.max(np.abs(phi - ophi)) < 1e-14 and np.max(np.abs(dphi - odphi)) < 1e-13
+    with pytest.raises(fx.FemError):
+        fx.reference_tables(dim, 2, 3, fx.QUAD_SYMMETRIC)

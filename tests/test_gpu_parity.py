@@ -4,6 +4,7 @@ Bar: relative max error and relative L2 error <= 1e-12 against the oracle on the
 seeded inputs (the forms are evaluated in FP64 on both sides, only the summation order
 differs), bit-exact for the colouring, bitwise-identical repeated runs.
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -66,10 +67,10 @@ CASES = [(f, 2, k) for f in (0, 1, 2) for k in range(1, 7)] + \
         [(f, 3, k) for f in (0, 1, 2) for k in range(1, 5)]
 
 
-STRATS = [(fx.SCATTER_PATCH, 0), (fx.SCATTER_PATCH, 64), (fx.SCATTER_COLOUR, 0)]
+STRATS = [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 64, 1), (fx.SCATTER_COLOUR, 0, 0)]
 
 
-@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64", "colour"])
+@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64x1", "colour"])
 @pytest.mark.parametrize("form,dim,k", CASES)
 def test_action_small_meshes(form, dim, k, strategy):
     # 2D n=9: 162 cells; 3D n=3: 162 cells -- several wavefronts / patches plus a ragged tail
@@ -86,7 +87,7 @@ def test_action_small_meshes(form, dim, k, strategy):
     assert emax < TOL and el2 < TOL, (emax, el2)
 
 
-@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64", "colour"])
+@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64x1", "colour"])
 @pytest.mark.parametrize("form,dim,k", CASES)
 def test_vjp_small_meshes(form, dim, k, strategy):
     n = 7 if dim == 2 else 2
@@ -115,7 +116,7 @@ def test_block_sizes_bitwise_identical(block):
     assert np.array_equal(y0, y1)
 
 
-@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64", "colour"])
+@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64x1", "colour"])
 def test_determinism_and_stream(strategy):
     w = meshgen.workload("elast_p2_3d", n=6)
     say(f"[determinism] elast_p2_3d n=6 {strategy}")
@@ -177,8 +178,9 @@ FULL = ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d", "nh_vjp_p4_2d", "mass_p2_2d_102
 _ref_cache = {}
 
 
-@pytest.mark.parametrize("strategy", [(fx.SCATTER_PATCH, 0), (fx.SCATTER_COLOUR, 0)],
-                         ids=["patch", "colour"])
+@pytest.mark.parametrize("strategy", [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 128, 1),
+                                      (fx.SCATTER_COLOUR, 0, 0)],
+                         ids=["patch", "patch128x1", "colour"])
 @pytest.mark.parametrize("name", FULL)
 def test_full_size_against_oracle(name, strategy):
     """Every output of the full-size workloads against the oracle (seconds on the host)."""
@@ -250,3 +252,63 @@ def test_vjp_against_assembled_jacobian_transpose(n, ncols):
         jtv[j] = torch.dot(vt, (plan.action(ut + e) - plan.action(ut - e)) / (2 * h)).item()
     g = plan.vjp(ut, vt).cpu().numpy()[cols]
     assert np.max(np.abs(jtv - g)) < 1e-6 * np.max(np.abs(g))
+
+
+def test_tuner_picks_a_candidate_and_keeps_parity(tmp_path):
+    w = meshgen.workload("nh_p4_2d", n=32)
+    say("[tune] nh_p4_2d n=32")
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    u = gpu(w.u)
+    cache = tmp_path / "tune.json"
+    res = plan.tune(u, cache_path=str(cache))
+    assert len(res) >= 6
+    best = min(res, key=lambda r: r[4])
+    st, pc, ln = plan.strategy()
+    assert st == int(best[0])
+    y = plan.action(u).cpu().numpy()
+    ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
+    assert rel_err(y, ref)[0] < TOL
+    assert cache.exists() and "f2/d2/k4/q8" in cache.read_text()
+
+
+def _batch_meshes(n_mesh=9, seed=11):
+    """An uneven mix of the three batch forms at sizes the oracle handles quickly."""
+    return meshgen.batch_workloads(n_mesh=n_mesh, seed=seed, lo=20, hi=600)
+
+
+def test_batch_matches_oracle_and_per_mesh():
+    ws = _batch_meshes()
+    say("[batch] " + ", ".join(f"{w.name}:{w.mesh.n_cell}" for w in ws))
+    plans = [fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params) for w in ws]
+    us = [gpu(w.u) for w in ws]
+    ys = [torch.full_like(u, 3.0) for u in us]
+    b = fx.Batch(plans, us, ys)
+    assert b.n_groups == 3
+    for graph in (False, True, True):
+        for y in ys:
+            y.fill_(3.0)
+        b.run(graph=graph)
+        torch.cuda.synchronize()
+        for w, p, u, y in zip(ws, plans, us, ys):
+            ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
+            assert rel_err(y.cpu().numpy(), ref)[0] < TOL, w.name
+            assert torch.equal(y, p.action(u)), w.name        # bitwise the per-mesh result
+    b.close()
+
+
+def test_batch_rebind_vectors():
+    ws = _batch_meshes(n_mesh=4, seed=12)
+    plans = [fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params) for w in ws]
+    us = [gpu(w.u) for w in ws]
+    ys = [torch.empty_like(u) for u in us]
+    b = fx.Batch(plans, us, ys)
+    b.run()
+    us2 = [2.0 * u for u in us]
+    ys2 = [torch.empty_like(u) for u in us]
+    fx.lib().fem_batch_set_vectors(b._h,
+                                   (ctypes.c_void_p * 4)(*[u.data_ptr() for u in us2]),
+                                   (ctypes.c_void_p * 4)(*[y.data_ptr() for y in ys2]))
+    b.run()
+    torch.cuda.synchronize()
+    for p, u, y in zip(plans, us2, ys2):
+        assert torch.equal(y, p.action(u))
