@@ -92,44 +92,56 @@ def cold_flush(buf):
     buf.add_(1.0)
 
 
-def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bool = False):
+def make_plan(w, tune: bool, vjp: bool = False):
     import torch
-    import meshgen
     import paper_2506_17471_amd as fx
-
-    w = meshgen.workload(name)
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
     u = torch.as_tensor(w.u, device="cuda")
     y = torch.empty_like(u)
+    v = None
     if vjp:
-        v = torch.as_tensor(w.v if w.v is not None else np.random.default_rng(9).uniform(-1, 1, w.n_dof),
-                            device="cuda")
+        v = torch.as_tensor(w.v if w.v is not None else
+                            np.random.default_rng(9).uniform(-1, 1, w.n_dof), device="cuda")
+    tuned = None
+    if tune:
+        res = plan.tune(u, y=y, v=v)
+        best = min(res, key=lambda r: r[4])
+        tuned = {"strategy": "patch" if best[0] == 1 else "colour", "cells_per_patch": int(best[1]),
+                 "lanes_per_cell": int(best[2]), "block": int(best[3]), "tuner_ms": best[4],
+                 "candidates": len(res)}
+    return plan, u, v, y, tuned
+
+
+def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bool = False,
+                 tune: bool = True):
+    import torch
+    import meshgen
+
+    w = meshgen.workload(name, with_v=vjp)
+    plan, u, v, y, tuned = make_plan(w, tune, vjp)
+    if vjp:
         fn = lambda: plan.vjp(u, v, out=y)  # noqa: E731
     else:
         fn = lambda: plan.action(u, out=y)  # noqa: E731
     if cold:
-        flush = torch.zeros(160 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 1.25 GiB
-
-        def fn_cold(f=fn):
-            cold_flush(flush)
-            f()
-        # time only the action: events around fn, flush outside
-        import torch as _t
+        # stream 1.25 GiB (more than the 256 MB last-level cache) before every timed run
+        flush = torch.zeros(160 * 1024 * 1024, dtype=torch.float64, device="cuda")
         for _ in range(warmup):
             fn()
-        _t.cuda.synchronize()
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
         ms = []
-        st = _t.cuda.current_stream()
         for _ in range(steps):
             cold_flush(flush)
-            a, b = _t.cuda.Event(enable_timing=True), _t.cuda.Event(enable_timing=True)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(st)
             fn()
             b.record(st)
-            _t.cuda.synchronize()
+            torch.cuda.synchronize()
             ms.append(a.elapsed_time(b))
         ms = np.array(ms)
         wall = float(ms.sum()) / 1e3
+        del flush
     else:
         ms, wall = time_steps(fn, steps, warmup)
     nv = w.mesh.n_vert
@@ -137,8 +149,8 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
         fl = vjp_flops_per_cell(w.mesh.dim, plan.n_loc, plan.n_quad)
     else:
         fl = flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad)
-    info = dict(workload=name, n_cell=w.mesh.n_cell, n_dof=w.n_dof, n_loc=plan.n_loc,
-                n_quad=plan.n_quad, n_colours=plan.n_colours,
+    info = dict(workload=name, vjp=vjp, cold=cold, n_cell=w.mesh.n_cell, n_dof=w.n_dof,
+                n_loc=plan.n_loc, n_quad=plan.n_quad, tuned=tuned,
                 flops_per_cell=fl, flops=fl * w.mesh.n_cell,
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
                                       3 if vjp and w.form == 2 else 2),
@@ -148,7 +160,65 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
     info["dof_per_s"] = w.n_dof / t
     info["tflops"] = info["flops"] / t / 1e12
     info["hbm_gbs_footprint"] = info["bytes"] / t / 1e9
-    return info, w, plan
+    info["hbm_frac_footprint"] = info["hbm_gbs_footprint"] / HBM_PEAK_GBS
+    info["fp64_frac"] = info["tflops"] / FP64_PEAK_TFLOPS
+    del plan
+    return info, w
+
+
+def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
+    """64 uneven meshes (2D P3 mass, 2D P6 neo-Hookean, 3D P4 elasticity): the sum of the
+    per-mesh actions launched one by one against one replay of the batch graph."""
+    import torch
+    import meshgen
+    import paper_2506_17471_amd as fx
+
+    ws = meshgen.batch_workloads(n_mesh=n_mesh)
+    plans, us, ys = [], [], []
+    for w in ws:
+        plan, u, _, y, _ = make_plan(w, False)
+        plans.append(plan)
+        us.append(u)
+        ys.append(y)
+    tuned = {}
+    if tune:
+        # tune the largest mesh of each kind and give its configuration to the others
+        kinds = {}
+        for i, w in enumerate(ws):
+            k = w.name.split("_", 1)[1]
+            if k not in kinds or w.mesh.n_cell > ws[kinds[k]].mesh.n_cell:
+                kinds[k] = i
+        for k, i in kinds.items():
+            res = plans[i].tune(us[i], y=ys[i])
+            best = min(res, key=lambda r: r[4])
+            tuned[k] = [int(best[0]), int(best[1]), int(best[2]), int(best[3])]
+            for j, w in enumerate(ws):
+                if w.name.split("_", 1)[1] == k and j != i:
+                    if best[0] == 1:
+                        plans[j].set_strategy(1, int(best[1]), int(best[2]))
+                    else:
+                        plans[j].set_strategy(0)
+                        plans[j].set_block(int(best[3]))
+    per_mesh = lambda: [p.action(u, out=y) for p, u, y in zip(plans, us, ys)]  # noqa: E731
+    ms_each, _ = time_steps(per_mesh, steps, warmup)
+    # each mesh alone, to split out launch overhead
+    alone = []
+    for p, u, y in zip(plans, us, ys):
+        m, _ = time_steps(lambda p=p, u=u, y=y: p.action(u, out=y), max(5, steps // 3), 2)
+        alone.append(float(m.mean()))
+    batch = fx.Batch(plans, us, ys)
+    ms_graph, _ = time_steps(lambda: batch.run(graph=True), steps, warmup)
+    ms_eager, _ = time_steps(lambda: batch.run(graph=False), steps, warmup)
+    n_dof = sum(w.n_dof for w in ws)
+    n_cell = sum(w.mesh.n_cell for w in ws)
+    out = dict(n_mesh=len(ws), n_cell=n_cell, n_dof=n_dof, groups=batch.n_groups, tuned=tuned,
+               patches=batch.n_patches,
+               per_mesh_loop_ms=float(ms_each.mean()), sum_of_alone_ms=float(np.sum(alone)),
+               batch_graph_ms=float(ms_graph.mean()), batch_eager_ms=float(ms_eager.mean()),
+               dof_per_s=n_dof / (ms_graph.mean() / 1e3))
+    out["speedup_vs_per_mesh"] = out["per_mesh_loop_ms"] / out["batch_graph_ms"]
+    batch.close()
+    return out
 
 
 def cpu_baseline(w, max_cells: int = 65536):
@@ -179,7 +249,9 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="nh_p4_2d")
-    ap.add_argument("--all", action="store_true", help="also time the other workloads")
+    ap.add_argument("--all", action="store_true", help="also time the other workloads and the batch")
+    ap.add_argument("--batch", action="store_true", help="also time the 64-mesh batch")
+    ap.add_argument("--no-tune", action="store_true", help="use the plans' default launch configuration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate the "
@@ -202,26 +274,33 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 5}))
         return
+    tune = not args.no_tune
 
-    main_info, w, plan = run_workload(args.workload, args.steps, args.warmup)
-    print(f"# {args.workload}: {main_info['ms_mean']:.4f} ms/step", file=sys.stderr, flush=True)
+    def note(msg):
+        print(f"# {msg}", file=sys.stderr, flush=True)
+
+    main_info, w = run_workload(args.workload, args.steps, args.warmup, tune=tune)
+    note(f"{args.workload}: {main_info['ms_mean']:.4f} ms/step, tuned {main_info['tuned']}")
     extras = {}
     if w.form == 2:
-        vinfo, _, _ = run_workload(args.workload, args.steps, args.warmup, vjp=True)
+        vinfo, _ = run_workload(args.workload, args.steps, args.warmup, vjp=True, tune=tune)
         extras["vjp"] = vinfo
         extras["adjoint_forward_time_ratio"] = vinfo["ms_mean"] / main_info["ms_mean"]
-        print(f"# vjp: {vinfo['ms_mean']:.4f} ms/step", file=sys.stderr, flush=True)
+        note(f"vjp: {vinfo['ms_mean']:.4f} ms/step")
     if args.all:
         for name in ("mass_p2_2d", "mass_p2_2d_1024", "elast_p2_3d"):
-            info, _, _ = run_workload(name, args.steps, args.warmup)
+            info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
             extras[name] = info
-            print(f"# {name}: {info['ms_mean']:.4f} ms/step", file=sys.stderr, flush=True)
-        info, _, _ = run_workload("mass_p2_2d_1024", args.steps, args.warmup, cold=True)
-        extras["mass_p2_2d_1024_cold"] = info
+            note(f"{name}: {info['ms_mean']:.4f} ms/step")
+        for name in ("mass_p2_2d_1024", "nh_p4_2d", "elast_p2_3d"):
+            info, _ = run_workload(name, args.steps, args.warmup, cold=True, tune=tune)
+            extras[name + "_cold"] = info
+            note(f"{name} cold: {info['ms_mean']:.4f} ms/step")
+    if args.all or args.batch:
+        extras["batch"] = run_batch(args.steps, args.warmup, tune=tune)
+        note(f"batch: {extras['batch']}")
 
-    t = main_info["ms_mean"] / 1e3
     achieved = main_info["tflops"]
-    n_launch = plan.n_colours
     out = {
         "metric": "FP64 FE action DoF/s",
         "value": main_info["dof_per_s"],
@@ -237,12 +316,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_cell": main_info["n_cell"],
                    "n_dof": main_info["n_dof"], "n_quad": main_info["n_quad"],
-                   "n_colours": main_info["n_colours"]},
+                   "launch": main_info["tuned"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "vector_kernel (neo-Hookean, 2D, P4)",
-                     "launches_per_step": n_launch,
-                     "avg_launch_ms": main_info["ms_mean"] / n_launch,
+                     "kernel": "patch_kernel (neo-Hookean, 2D, P4) + fixup_kernel",
+                     "flops_per_launch": main_info["flops"],
+                     "avg_step_ms": main_info["ms_mean"],
                      "footprint_gbs": main_info["hbm_gbs_footprint"]},
         "extras": extras,
     }

@@ -220,7 +220,8 @@ int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vj
  * fem_batch_run: enqueue the whole batch on `stream`; use_graph != 0 replays the recorded
  *   graph (recording it on the first call, on a private stream), 0 launches eagerly.  Both
  *   produce bitwise the same result as fem_action on each plan with the same strategy.
- * fem_batch_info: meshes, launch groups, total patches, total shared nodes (all optional).
+ * fem_batch_info: meshes, launch groups, total patches, total (shared node, component)
+ *   items summed by the fixup launch (all optional).
  * Errors: FEM_E_ARG, FEM_E_UNSUPPORTED, FEM_E_HIP, FEM_E_NOMEM.
  */
 typedef struct fem_batch fem_batch;

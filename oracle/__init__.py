@@ -49,7 +49,30 @@ def _load():
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build()
-    lib = ctypes.CDLL(_LIB)
+    _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+class using_library:
+    """Temporarily route the oracle through another build of fem_oracle.c (the mutation
+    tests compile deliberately broken copies to check that the pins catch them)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _load()
+        _lib = _bind(ctypes.CDLL(self.path))
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _bind(lib):
     P = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_double
     lib.oracle_action.argtypes = [i32, i32, i32, i32, P, P, P, i64, P, P, P, f64, f64, P, P, i64]
@@ -62,7 +85,6 @@ def _load():
     lib.oracle_min_det_f.restype = f64
     lib.oracle_colouring.argtypes = [i64, i32, P, i32, P, P]
     lib.oracle_colouring.restype = i32
-    _lib = lib
     return lib
 
 

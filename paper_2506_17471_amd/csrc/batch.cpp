@@ -219,7 +219,7 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
                 f.ncomp = p->ncomp;
                 b->fix.push_back(f);
                 b->fix_member.push_back(i);
-                b->n_fix += p->n_shared;
+                b->n_fix += p->n_shared * p->ncomp;   // (node, component) items
             }
         }
         for (auto &g : b->groups) {

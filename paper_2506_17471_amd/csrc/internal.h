@@ -96,7 +96,7 @@ struct FixDesc {
     const int32_t *fix_off;
     const double *partial;
     double *y;
-    int64_t first;           // index of the mesh's first shared node in the launch
+    int64_t first;           // index of the mesh's first (shared node, component) item
     int ncomp;
 };
 

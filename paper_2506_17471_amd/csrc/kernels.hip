@@ -110,7 +110,18 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int lo
     const int nb = a.patch_off[p];
     const int U = a.patch_off[p + 1] - nb;
 
-    // 1. stage the values of the patch's distinct nodes
+    // 1. the cell's own loads (geometry, local node indices) go out first, then the patch's
+    //    distinct nodal values are staged in LDS
+    const int64_t s = (p << logp) + cl;
+    const bool active = s < a.n_cell;
+    constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
+    double Kinv[DIM][DIM], adet = 0.0;
+    int lid[NLOC];
+    if (active) {
+        adet = gather_geometry<DIM>(a.verts, a.stride, s, a.coords, Kinv);
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n) lid[n] = a.lidx[n * a.stride + s];
+    }
     for (int j = tid; j < U; j += nthreads) {
         const int64_t nd = a.patch_nodes[nb + j];
 #pragma unroll
@@ -121,17 +132,12 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int lo
     }
     __syncthreads();
 
-    // 2. gather the cell's values from LDS and its geometry from global memory
-    const int64_t s = (p << logp) + cl;
-    const bool active = s < a.n_cell;
-    constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
-    double Kinv[DIM][DIM], adet = 0.0;
+    // 2. the cell's values from LDS
     double ul[NLOC][CW], vl[VJP ? NLOC : 1][CW], yl[NLOC][CW];
     if (active) {
-        adet = gather_geometry<DIM>(a.verts, a.stride, s, a.coords, Kinv);
 #pragma unroll
         for (int n = 0; n < NLOC; ++n) {
-            const int l = a.lidx[n * a.stride + s];
+            const int l = lid[n];
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 ul[n][c] = lds[l * NC + c + comp];
@@ -211,6 +217,7 @@ __global__ void __launch_bounds__(kMaxBlock)
 
 // Shared-node sums of many meshes: thread i sums shared node i - fix[m].first of the mesh m
 // whose range holds i (binary search over the meshes' first indices).
+// (`first` counts (node, component) items, so meshes of different ncomp mix freely)
 __global__ void batch_fixup_kernel(const FixDesc *__restrict__ fix, int n_mesh, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -221,29 +228,30 @@ __global__ void batch_fixup_kernel(const FixDesc *__restrict__ fix, int n_mesh, 
         if (fix[mid].first <= i) lo = mid; else hi = mid - 1;
     }
     const FixDesc &f = fix[lo];
-    const int64_t k = i - f.first;
+    const int64_t item = i - f.first;
+    const int64_t k = item / f.ncomp;
+    const int c = (int)(item - k * f.ncomp);
     const int64_t nd = f.fix_node[k];
     const int o0 = f.fix_off[k], o1 = f.fix_off[k + 1];
-    for (int c = 0; c < f.ncomp; ++c) {
-        double s = 0.0;
-        for (int o = o0; o < o1; ++o) s += f.partial[(int64_t)o * f.ncomp + c];
-        f.y[nd * f.ncomp + c] = s;
-    }
+    double s = 0.0;
+    for (int o = o0; o < o1; ++o) s += f.partial[(int64_t)o * f.ncomp + c];
+    f.y[nd * f.ncomp + c] = s;
 }
 
+// thread i sums component i % ncomp of shared node i / ncomp over its partials, in patch order
 __global__ void fixup_kernel(const int32_t *__restrict__ fix_node, const int32_t *__restrict__ fix_off,
                              int64_t n, const double *__restrict__ partial, int ncomp,
                              double *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t nd = fix_node[i];
-    const int o0 = fix_off[i], o1 = fix_off[i + 1];
-    for (int c = 0; c < ncomp; ++c) {
-        double s = 0.0;
-        for (int o = o0; o < o1; ++o) s += partial[(int64_t)o * ncomp + c];
-        y[nd * ncomp + c] = s;
-    }
+    if (i >= n * ncomp) return;
+    const int64_t k = i / ncomp;
+    const int c = (int)(i - k * ncomp);
+    const int64_t nd = fix_node[k];
+    const int o0 = fix_off[k], o1 = fix_off[k + 1];
+    double s = 0.0;
+    for (int o = o0; o < o1; ++o) s += partial[(int64_t)o * ncomp + c];
+    y[nd * ncomp + c] = s;
 }
 
 __global__ void zero_nodes_kernel(const int32_t *__restrict__ nodes, int64_t n, int ncomp,
@@ -412,7 +420,7 @@ hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t
                         const double *partial, int ncomp, double *y, hipStream_t s)
 {
     const int block = 256;
-    const int64_t grid = (n_shared + block - 1) / block;
+    const int64_t grid = (n_shared * ncomp + block - 1) / block;
     hipLaunchKernelGGL(fixup_kernel, dim3((unsigned)grid), dim3(block), 0, s, fix_node, fix_off,
                        n_shared, partial, ncomp, y);
     return hipGetLastError();

@@ -1,0 +1,76 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each case copies oracle/fem_oracle.c, plants one mistake (a dropped term, a wrong sign,
+a transposed index, a missing factor), compiles the copy, routes the oracle through it and
+runs the pins that should notice: at least one must fail.  The mistakes live only in the
+temporary copy.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_action as pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
+                   "fem_oracle.c")
+
+MUTATIONS = {
+    "nh_drop_log_term": ("S[i][j] = mu * (F[i][j] - FiT) + lam * lnJ * FiT;",
+                         "S[i][j] = mu * (F[i][j] - FiT);",
+                         [lambda: pins.test_nh_residual_is_energy_gradient(2, 2),
+                          lambda: pins.test_nh_vjp_at_zero_is_elasticity(2, 2)]),
+    "nh_sign_of_cofactor": ("S[i][j] = mu * (F[i][j] - FiT) + lam * lnJ * FiT;",
+                            "S[i][j] = mu * (F[i][j] + FiT) + lam * lnJ * FiT;",
+                            [lambda: pins.test_nh_invariances(2, 2)]),
+    "jacobian_transposed": ("J[i][r] = x[r + 1][i] - x[0][i];",
+                            "J[r][i] = x[r + 1][i] - x[0][i];",
+                            [lambda: pins.test_elasticity_equals_exact_assembly(2, 2, 2, pins.LAME)]),
+    "no_abs_det": ("double detJ = fabs(geometry(d, x, J, K));\n        for (int i = 0; i < nloc * ncomp; ++i)",
+                   "double detJ = geometry(d, x, J, K);\n        for (int i = 0; i < nloc * ncomp; ++i)",
+                   [lambda: pins.test_mass_partition_of_unity(3, 2)]),
+    "weight_without_det": ("const double W = w[q] * detJ;\n            if (form == OR_MASS)",
+                           "const double W = w[q];\n            if (form == OR_MASS)",
+                           [lambda: pins.test_mass_partition_of_unity(2, 2)]),
+    "elasticity_half_shear": ("S[i][j] = 2.0 * mu * eps + (i == j ? lam * tr : 0.0);",
+                              "S[i][j] = mu * eps + (i == j ? lam * tr : 0.0);",
+                              [lambda: pins.test_elasticity_equals_exact_assembly(2, 2, 2, pins.LAME)]),
+    "contraction_transposed": ("out[a * d + c] += dq[a * d + r] * E[c][r];\n            }\n        }\n        for (int a = 0; a < nloc; ++a)\n            for (int c = 0; c < ncomp; ++c)",
+                               "out[a * d + c] += dq[a * d + r] * E[r][c];\n            }\n        }\n        for (int a = 0; a < nloc; ++a)\n            for (int c = 0; c < ncomp; ++c)",
+                               [lambda: pins.test_elasticity_equals_exact_assembly(2, 2, 2, pins.LAME)]),
+    "vjp_tangent_index": ("+ (mu - lam * lnJ) * Fi[j][k] * Fi[l][i]",
+                          "+ (mu - lam * lnJ) * Fi[k][j] * Fi[l][i]",
+                          [lambda: pins.test_nh_vjp_against_finite_differences(2, 2, 2)]),
+    "energy_sign": ("return 0.5 * mu * (trC - d) - mu * lnJ + 0.5 * lam * lnJ * lnJ;",
+                    "return 0.5 * mu * (trC - d) + mu * lnJ + 0.5 * lam * lnJ * lnJ;",
+                    [lambda: pins.test_nh_residual_is_energy_gradient(2, 2)]),
+    "mass_test_function_dropped": ("out[a] += phi[q * nloc + a] * e;",
+                                   "out[a] += e / nloc;",
+                                   [lambda: pins.test_mass_equals_exact_assembly(2, 2, 2)]),
+    "colouring_ignores_conflicts": ("if ((masks[nd * nwords + c / 64] >> (c % 64)) & 1u) {",
+                                    "if (0) {",
+                                    [lambda: pins.test_colouring_valid_and_greedy(2, 6, 1)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new, checks = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    mut = tmp_path / "fem_oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", str(so), str(mut), "-lm"],
+                   check=True)
+    caught = 0
+    with oracle.using_library(str(so)):
+        for check in checks:
+            try:
+                with np.errstate(all="ignore"):
+                    check()
+            except AssertionError:
+                caught += 1
+    assert caught >= 1, f"no pin noticed the planted mistake {name}"
