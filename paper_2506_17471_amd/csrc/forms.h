@@ -391,4 +391,58 @@ __device__ __forceinline__ void cell_quadrature_pair(
     }
 }
 
+// The 3D vector forms with the three components of a cell on a lane triple (lanes 3g,
+// 3g+1, 3g+2 of a wavefront; `base` = 3g): lane c holds component c, evaluates row c of the
+// reference gradient, gathers the three rows from the triple by lane shuffles, evaluates
+// the (whole) pointwise form and accumulates row c of the stress.
+template <int FORM, int K, bool VJP>
+__device__ __forceinline__ void cell_quadrature_triple(
+    const double (&ul)[nloc_of(3, K)], const double (&vl)[VJP ? nloc_of(3, K) : 1], int c,
+    int base, const double (&Kinv)[3][3], double adet, const double *table, int nq, double lam,
+    double mu, double (&yl)[nloc_of(3, K)])
+{
+    constexpr int NLOC = nloc_of(3, K);
+    constexpr int REC = record_of(FORM, 3, NLOC);
+    const FEMX_CONSTANT double *tab = (const FEMX_CONSTANT double *)table;
+#pragma unroll
+    for (int n = 0; n < NLOC; ++n) yl[n] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < nq; ++q) {
+        const FEMX_CONSTANT double *t = tab + q * REC;
+        double g[3] = {0.0, 0.0, 0.0}, h[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                g[r] = fma(t[r * NLOC + n], ul[n], g[r]);
+                if constexpr (VJP) h[r] = fma(t[r * NLOC + n], vl[n], h[r]);
+            }
+        double gu[3][3], gv[3][3], G[3][3], S[3][3], T[3][3];
+#pragma unroll
+        for (int row = 0; row < 3; ++row)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                gu[row][r] = __shfl(g[r], base + row);
+                if constexpr (VJP) gv[row][r] = __shfl(h[r], base + row);
+            }
+        to_physical<3>(gu, Kinv, G);
+        if constexpr (VJP) {
+            double H[3][3];
+            to_physical<3>(gv, Kinv, H);
+            tangent_neohookean<3>(G, H, lam, mu, S);
+        } else if constexpr (FORM == FEM_ELASTICITY) {
+            stress_elasticity<3>(G, lam, mu, S);
+        } else {
+            stress_neohookean<3>(G, lam, mu, S);
+        }
+        pull_back<3>(S, Kinv, t[3 * NLOC] * adet, T);
+        double tc[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) tc[r] = c == 0 ? T[0][r] : (c == 1 ? T[1][r] : T[2][r]);
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n)
+            yl[n] = fma(t[n], tc[0], fma(t[NLOC + n], tc[1], fma(t[2 * NLOC + n], tc[2], yl[n])));
+    }
+}
+
 }  // namespace femx

@@ -69,7 +69,7 @@ struct PatchArgs {
     const int32_t *patch_nodes; // global node id of each (patch, node)
     const int32_t *patch_dest;  // -1: node held by this patch only, else partial slot
     const int32_t *csr_off;     // [n_pn + 1] element-buffer slots summed into (patch, node)
-    const uint16_t *csr_slots;  // slot = a * P + local cell, in ascending (cell, a)
+    const uint16_t *csr_slots;  // slot = a << 8 | local cell, in ascending (cell, a)
     const double *coords;
     const double *tab;
     const double *u;
@@ -123,7 +123,7 @@ struct fem_plan {
     // patch strategy
     int strategy = femx::STRAT_PATCH;
     int patch = 0;                       // cells per patch (0: not built)
-    int lanes = 1;                       // lanes per cell in the patch kernel (1 or 2)
+    int lanes = 1;                       // lanes per cell in the patch kernel (1, 2 or 3)
     int64_t n_patch = 0, n_pn = 0, n_partial = 0, n_shared = 0;
     int max_patch_nodes = 0;
     int32_t *d_pverts = nullptr;
@@ -150,6 +150,7 @@ hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double 
 size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes);
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
 bool pair_available(int form, int dim, int degree);
+bool triple_available(int form, int dim, int degree);
 hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch,
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
                               size_t lds, hipStream_t s);

@@ -36,6 +36,7 @@ constexpr int kMaxBlock = 256;
 // the loop; everything else keeps the allocator's default.
 constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc)
 {
+    if (lpc == 3) return 1;
     if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : 4;
     return (!vjp && dim == 2 && k <= 4 && form != FEM_MASS) ? 3 : 1;
 }
@@ -94,26 +95,40 @@ __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
 }
 
 // ------------------------------------------------------------------- patch strategy
-// LPC lanes per cell: 1, or 2 for the 2D vector forms (lane c of a pair owns component c).
+// LPC lanes per cell: 1; 2 for the 2D vector forms (lane c of a pair owns component c);
+// 3 for the 3D vector forms (lane c of a triple owns component c; a wavefront holds 21
+// triples and leaves its last lane idle).
 template <int FORM, int DIM, int K, bool VJP, int LPC>
-__device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int logp)
+__device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 {
     constexpr int NLOC = nloc_of(DIM, K);
     constexpr int NC = FORM == FEM_MASS ? 1 : DIM;
-    static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && FORM != FEM_MASS), "lane split");
+    static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && FORM != FEM_MASS) ||
+                      (LPC == 3 && DIM == 3 && FORM != FEM_MASS),
+                  "lane split");
     extern __shared__ double lds[];
-    const int P = 1 << logp;                  // cells per patch
     const int tid = threadIdx.x;
-    const int nthreads = P * LPC;
-    const int cl = LPC == 1 ? tid : tid >> 1; // local cell
-    const int comp = LPC == 1 ? 0 : tid & 1;
+    const int nthreads = blockDim.x;
+    int cl, comp, base = 0;                   // local cell, component, first lane of the triple
+    if constexpr (LPC == 1) {
+        cl = tid;
+        comp = 0;
+    } else if constexpr (LPC == 2) {
+        cl = tid >> 1;
+        comp = tid & 1;
+    } else {
+        const int lane = tid & 63, wave = tid >> 6;
+        cl = lane < 63 ? wave * 21 + lane / 3 : P;    // the idle lane owns no cell
+        comp = lane < 63 ? lane % 3 : 0;
+        base = lane < 63 ? lane - comp : 0;
+    }
     const int nb = a.patch_off[p];
     const int U = a.patch_off[p + 1] - nb;
 
     // 1. the cell's own loads (geometry, local node indices) go out first, then the patch's
     //    distinct nodal values are staged in LDS
-    const int64_t s = (p << logp) + cl;
-    const bool active = s < a.n_cell;
+    const int64_t s = p * P + cl;
+    const bool active = cl < P && s < a.n_cell;
     constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
     double Kinv[DIM][DIM], adet = 0.0;
     int lid[NLOC];
@@ -151,6 +166,17 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int lo
     if (active) {
         if constexpr (LPC == 1) {
             cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
+        } else if constexpr (LPC == 3) {
+            double u1[NLOC], v1[VJP ? NLOC : 1], y1[NLOC];
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) {
+                u1[n] = ul[n][0];
+                if constexpr (VJP) v1[n] = vl[n][0];
+            }
+            cell_quadrature_triple<FORM, K, VJP>(u1, v1, comp, base, Kinv, adet, a.tab, a.nq,
+                                                 a.lam, a.mu, y1);
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) yl[n][0] = y1[n];
         } else {
             double u1[NLOC], v1[VJP ? NLOC : 1], y1[NLOC];
 #pragma unroll
@@ -178,7 +204,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int lo
         for (int c = 0; c < NC; ++c) sum[c] = 0.0;
         for (int e = e0; e < e1; ++e) {
             const int sl = a.csr_slots[e];
-            const int an = sl >> logp, sc = sl & (P - 1);
+            const int an = sl >> 8, sc = sl & 255;
 #pragma unroll
             for (int c = 0; c < NC; ++c) sum[c] += lds[(an * NC + c) * P + sc];
         }
@@ -197,9 +223,9 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int lo
 template <int FORM, int DIM, int K, bool VJP, int LPC>
 __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
-    patch_kernel(const PatchArgs a, int logp)
+    patch_kernel(const PatchArgs a, int P)
 {
-    patch_body<FORM, DIM, K, VJP, LPC>(a, blockIdx.x, logp);
+    patch_body<FORM, DIM, K, VJP, LPC>(a, blockIdx.x, P);
 }
 
 // Many meshes of one kernel variant in one launch: workgroup b works on patch
@@ -208,11 +234,11 @@ template <int FORM, int DIM, int K, bool VJP, int LPC>
 __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
     batch_patch_kernel(const BatchDesc *__restrict__ desc, const int32_t *__restrict__ patch_mesh,
-                       int logp)
+                       int P)
 {
     const int m = patch_mesh[blockIdx.x];
     const BatchDesc &d = desc[m];
-    patch_body<FORM, DIM, K, VJP, LPC>(d.args, (int64_t)blockIdx.x - d.first_patch, logp);
+    patch_body<FORM, DIM, K, VJP, LPC>(d.args, (int64_t)blockIdx.x - d.first_patch, P);
 }
 
 // Shared-node sums of many meshes: thread i sums shared node i - fix[m].first of the mesh m
@@ -265,27 +291,31 @@ __global__ void zero_nodes_kernel(const int32_t *__restrict__ nodes, int64_t n, 
 
 // ----------------------------------------------------------------------- dispatch
 using ColourFn = void (*)(const LaunchArgs);
-using PatchFn = void (*)(const PatchArgs, int);
+using PatchFn = void (*)(const PatchArgs, int);   // (arguments, cells per patch)
 using BatchFn = void (*)(const BatchDesc *, const int32_t *, int);
 
 struct Kernels {
     ColourFn colour;
-    PatchFn patch;
-    PatchFn patch_pair;   // two lanes per cell (2D vector forms), else null
-    BatchFn batch;
-    BatchFn batch_pair;
+    PatchFn patch[4];     // by lanes per cell (index 1..3), null where the split is absent
+    BatchFn batch[4];
 };
 
 template <int FORM, int DIM, int K, bool VJP>
 Kernels entry()
 {
-    if constexpr (DIM == 2 && FORM != FEM_MASS)
-        return {colour_kernel<FORM, DIM, K, VJP>, patch_kernel<FORM, DIM, K, VJP, 1>,
-                patch_kernel<FORM, DIM, K, VJP, 2>, batch_patch_kernel<FORM, DIM, K, VJP, 1>,
-                batch_patch_kernel<FORM, DIM, K, VJP, 2>};
-    else
-        return {colour_kernel<FORM, DIM, K, VJP>, patch_kernel<FORM, DIM, K, VJP, 1>, nullptr,
-                batch_patch_kernel<FORM, DIM, K, VJP, 1>, nullptr};
+    Kernels k{};
+    k.colour = colour_kernel<FORM, DIM, K, VJP>;
+    k.patch[1] = patch_kernel<FORM, DIM, K, VJP, 1>;
+    k.batch[1] = batch_patch_kernel<FORM, DIM, K, VJP, 1>;
+    if constexpr (DIM == 2 && FORM != FEM_MASS) {
+        k.patch[2] = patch_kernel<FORM, DIM, K, VJP, 2>;
+        k.batch[2] = batch_patch_kernel<FORM, DIM, K, VJP, 2>;
+    }
+    if constexpr (DIM == 3 && FORM != FEM_MASS) {
+        k.patch[3] = patch_kernel<FORM, DIM, K, VJP, 3>;
+        k.batch[3] = batch_patch_kernel<FORM, DIM, K, VJP, 3>;
+    }
+    return k;
 }
 
 template <int DIM, int K>
@@ -299,7 +329,7 @@ Kernels pick(int form, bool vjp)
 
 Kernels lookup(int form, int dim, int degree, bool vjp)
 {
-    if (form < FEM_MASS || form > FEM_NEOHOOKEAN) return {nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (form < FEM_MASS || form > FEM_NEOHOOKEAN) return Kernels{};
     if (dim == 2) {
         switch (degree) {
         case 1: return pick<2, 1>(form, vjp);
@@ -319,15 +349,9 @@ Kernels lookup(int form, int dim, int degree, bool vjp)
         default: break;
         }
     }
-    return {nullptr, nullptr, nullptr, nullptr, nullptr};
+    return Kernels{};
 }
 
-int log2_exact(int v)
-{
-    int l = 0;
-    while ((1 << l) < v) ++l;
-    return (1 << l) == v ? l : -1;
-}
 
 }  // namespace
 
@@ -360,7 +384,18 @@ size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int m
 
 bool pair_available(int form, int dim, int degree)
 {
-    return lookup(form, dim, degree, false).patch_pair != nullptr;
+    return lookup(form, dim, degree, false).patch[2] != nullptr;
+}
+
+bool triple_available(int form, int dim, int degree)
+{
+    return lookup(form, dim, degree, false).patch[3] != nullptr;
+}
+
+// threads of a patch workgroup: P * lanes, or 64 per 21 cells for lane triples
+int patch_threads(int P, int lanes)
+{
+    return lanes == 3 ? 64 * ((P + 20) / 21) : P * lanes;
 }
 
 hipError_t allow_lds(const void *fn, size_t lds)
@@ -379,16 +414,16 @@ hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patc
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
                               size_t lds, hipStream_t s)
 {
+    if (lanes < 1 || lanes > 3) return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(form, dim, degree, false);
-    BatchFn fn = lanes == 2 ? ks.batch_pair : ks.batch;
+    BatchFn fn = ks.batch[lanes];
     if (!fn) return hipErrorInvalidDeviceFunction;
-    const int logp = log2_exact(patch);
-    if (logp < 0 || patch * lanes > kMaxBlock || lds > 160 * 1024 || n_patch > 0x7fffffff)
+    const int threads = patch_threads(patch, lanes);
+    if (patch < 1 || patch > 256 || threads > kMaxBlock || lds > 160 * 1024 || n_patch > 0x7fffffff)
         return hipErrorInvalidConfiguration;
     hipError_t e = allow_lds((const void *)fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3((unsigned)n_patch), dim3(patch * lanes), lds, s, desc, patch_mesh,
-                       logp);
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_patch), dim3(threads), lds, s, desc, patch_mesh, patch);
     return hipGetLastError();
 }
 
@@ -402,17 +437,18 @@ hipError_t launch_batch_fixup(const FixDesc *fix, int n_mesh, int64_t n, hipStre
 
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s)
 {
+    if (p.lanes < 1 || p.lanes > 3) return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(p.form, p.dim, p.degree, vjp);
-    PatchFn fn = p.lanes == 2 ? ks.patch_pair : ks.patch;
+    PatchFn fn = ks.patch[p.lanes];
     if (!fn) return hipErrorInvalidDeviceFunction;
-    const int logp = log2_exact(p.patch);
-    if (logp < 0 || p.patch * p.lanes > kMaxBlock) return hipErrorInvalidConfiguration;
+    const int threads = patch_threads(p.patch, p.lanes);
+    if (p.patch < 1 || p.patch > 256 || threads > kMaxBlock) return hipErrorInvalidConfiguration;
     const size_t lds = patch_lds_bytes(p.form, p.dim, p.degree, vjp, p.patch, p.max_patch_nodes);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
     hipError_t e = allow_lds((const void *)fn, lds);
     if (e != hipSuccess) return e;
     if (p.n_patch > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(fn, dim3((unsigned)p.n_patch), dim3(p.patch * p.lanes), lds, s, a, logp);
+    hipLaunchKernelGGL(fn, dim3((unsigned)p.n_patch), dim3(threads), lds, s, a, p.patch);
     return hipGetLastError();
 }
 

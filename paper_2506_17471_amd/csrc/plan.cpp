@@ -311,8 +311,8 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
 {
     using femx::Error;
     const int nv = p->dim + 1, nloc = p->nloc;
-    if (P != 64 && P != 128 && P != 256) throw Error(FEM_E_ARG, "patch size must be 64, 128 or 256");
-    if ((int64_t)P * nloc > 65536) throw Error(FEM_E_UNSUPPORTED, "patch slots exceed 16 bits");
+    if (P < 1 || P > 256) throw Error(FEM_E_ARG, "patch size must be 1..256");
+    if (nloc > 255) throw Error(FEM_E_UNSUPPORTED, "more than 255 nodes per cell");
     PatchLayout L;
     L.P = P;
     L.order = morton_order(p, coords, cell_verts);
@@ -325,7 +325,7 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
     L.patch_nodes.reserve((size_t)(p->n_cell * nloc / 2 + 16));
     L.csr_slots.reserve((size_t)(p->n_cell * nloc));
     std::vector<int32_t> node_count((size_t)p->n_node, 0);
-    std::vector<std::pair<int64_t, int32_t>> pairs;   // ((node*P + cl)*nloc + a, slot)
+    std::vector<std::pair<int64_t, int32_t>> pairs;   // ((node*P + cl)*nloc + a, slot = a<<8 | cl)
     for (int64_t pt = 0; pt < L.n_patch; ++pt) {
         const int64_t c0 = pt * P, c1 = std::min<int64_t>(p->n_cell, c0 + P);
         pairs.clear();
@@ -335,7 +335,7 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
             for (int j = 0; j < nv; ++j) L.pverts[(size_t)j * L.stride + s] = cell_verts[c * nv + j];
             for (int a = 0; a < nloc; ++a) {
                 const int64_t nd = cell_nodes[c * nloc + a];
-                pairs.push_back({(nd * P + cl) * nloc + a, a * P + cl});
+                pairs.push_back({(nd * P + cl) * nloc + a, (a << 8) | cl});
             }
         }
         std::sort(pairs.begin(), pairs.end());
@@ -401,8 +401,8 @@ void validate_patch_layout(const fem_plan *p, const PatchLayout &L, const int32_
             const int e0 = L.csr_off[nb + j], e1 = L.csr_off[nb + j + 1];
             if (e0 < 0 || e1 < e0 || e1 > (int)L.csr_slots.size()) bad("csr range");
             for (int e = e0; e < e1; ++e) {
-                const int sl = L.csr_slots[e], a = sl / P, cl = sl % P;
-                if (a >= nloc) bad("slot node index");
+                const int sl = L.csr_slots[e], a = sl >> 8, cl = sl & 255;
+                if (a >= nloc || cl >= P) bad("slot index");
                 const int64_t s = c0 + cl;
                 if (s >= p->n_cell) bad("slot of an absent cell");
                 if (cell_nodes[L.order[s] * nloc + a] != nd) bad("slot sums into the wrong node");
@@ -466,16 +466,30 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
 
 int default_lanes(const fem_plan *p)
 {
-    return femx::pair_available(p->form, p->dim, p->degree) ? 2 : 1;
+    if (femx::pair_available(p->form, p->dim, p->degree)) return 2;
+    if (femx::triple_available(p->form, p->dim, p->degree) && p->degree >= 3) return 3;
+    return 1;
+}
+
+// Patch sizes a lane split allows: powers of two up to 256 lanes for one or two lanes per
+// cell; multiples of 21 cells (one wavefront of 21 lane triples) for three.
+bool patch_allowed(int P, int lanes)
+{
+    if (lanes == 3) return P == 21 || P == 42 || P == 63 || P == 84;
+    return (P == 64 || P == 128 || P == 256) && P * lanes <= 256;
 }
 
 int default_patch_for(const fem_plan *p, int lanes)
 {
-    // the largest power-of-two patch whose workgroup fits 256 lanes and whose element
-    // buffer fits 64 KB of LDS
-    for (int P = 256; P >= 64; P /= 2)
-        if (P * lanes <= 256 && (size_t)P * p->nloc * p->ncomp * 8 <= 64 * 1024) return P;
-    return 64;
+    // the largest allowed patch whose element buffer fits 64 KB of LDS
+    static const int sizes12[] = {256, 128, 64};
+    static const int sizes3[] = {84, 63, 42, 21};
+    const int *sz = lanes == 3 ? sizes3 : sizes12;
+    const int n = lanes == 3 ? 4 : 3;
+    for (int i = 0; i < n; ++i)
+        if (patch_allowed(sz[i], lanes) && (size_t)sz[i] * p->nloc * p->ncomp * 8 <= 64 * 1024)
+            return sz[i];
+    return sz[n - 1];
 }
 
 int default_patch(const fem_plan *p) { return default_patch_for(p, p->lanes); }
@@ -565,11 +579,15 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
     if (strategy != FEM_SCATTER_PATCH) throw Error(FEM_E_ARG, "unknown strategy");
     if (plan->n_cell == 0) throw Error(FEM_E_ARG, "empty mesh has no patches");
     const int lanes = lanes_per_cell == 0 ? default_lanes(plan) : lanes_per_cell;
-    if (lanes != 1 && lanes != 2) throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1 or 2");
+    if (lanes < 1 || lanes > 3) throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1, 2 or 3");
     if (lanes == 2 && !pair_available(plan->form, plan->dim, plan->degree))
         throw Error(FEM_E_UNSUPPORTED, "two lanes per cell exist for the 2D vector forms only");
+    if (lanes == 3 && !triple_available(plan->form, plan->dim, plan->degree))
+        throw Error(FEM_E_UNSUPPORTED, "three lanes per cell exist for the 3D vector forms only");
     const int P = patch_cells == 0 ? default_patch_for(plan, lanes) : patch_cells;
-    if (P * lanes > 256) throw Error(FEM_E_ARG, "patch_cells * lanes_per_cell exceeds 256");
+    if (!patch_allowed(P, lanes))
+        throw Error(FEM_E_ARG, "patch_cells must be 64, 128 or 256 (at most 256 lanes) for one or "
+                               "two lanes per cell, and 21, 42, 63 or 84 for three");
     if (P != plan->patch) {
         if (plan->h_cell_verts.empty()) throw Error(FEM_E_ARG, "plan keeps no host mesh");
         check_hip(hipDeviceSynchronize(), "synchronise before rebuilding patches");

@@ -1,9 +1,9 @@
 // Autotuner: measures the launch configurations of a plan and keeps the fastest.
 //
 // Candidates: the colour strategy with 64/128/256 cells per workgroup, and the patch
-// strategy with 64/128/256 cells per patch and one or (2D vector forms) two lanes per
-// cell.  Each candidate is timed with HIP events on the caller's stream using the paper's
-// protocol (Sec. 6.2.1): five warm-up runs, then timed runs until 15 have been collected
+// strategy with 64/128/256 cells per patch and one lane per cell, 64/128 with two lanes
+// (2D vector forms), 42/63/84 with three lanes (3D vector forms).  Each candidate is
+// timed with HIP events on the caller's stream using the paper's protocol (Sec. 6.2.1): five warm-up runs, then timed runs until 15 have been collected
 // or 0.2 s has accumulated, the arithmetic mean being the candidate's time.  Results can
 // be kept in a small JSON cache keyed by device architecture, form, dimension, degree,
 // quadrature degree and log2 of the cell count, which fem_plan_create consults when the
@@ -159,12 +159,11 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
 {
     std::vector<Candidate> cands;
     for (int blk : {64, 128, 256}) cands.push_back({FEM_SCATTER_COLOUR, 0, 1, blk});
-    const bool pair = pair_available(p->form, p->dim, p->degree);
-    for (int lanes : {1, 2}) {
-        if (lanes == 2 && !pair) continue;
-        for (int P : {64, 128, 256})
-            if (P * lanes <= 256) cands.push_back({FEM_SCATTER_PATCH, P, lanes, 0});
-    }
+    for (int P : {64, 128, 256}) cands.push_back({FEM_SCATTER_PATCH, P, 1, 0});
+    if (pair_available(p->form, p->dim, p->degree))
+        for (int P : {64, 128}) cands.push_back({FEM_SCATTER_PATCH, P, 2, 0});
+    if (triple_available(p->form, p->dim, p->degree))
+        for (int P : {42, 63, 84}) cands.push_back({FEM_SCATTER_PATCH, P, 3, 0});
     double best = 1e300;
     Candidate best_c = cands[0];
     int nres = 0;

@@ -120,7 +120,8 @@ def test_plan_without_device_reports_hip_error():
 
 @pytest.mark.parametrize("form,dim,n,k,P", [(0, 2, 9, 2, 64), (2, 2, 12, 4, 128), (2, 2, 16, 4, 256),
                                             (1, 3, 3, 2, 64), (1, 3, 4, 2, 256), (0, 3, 3, 4, 64),
-                                            (2, 2, 7, 6, 0), (1, 3, 2, 3, 0), (0, 2, 1, 1, 64)])
+                                            (2, 2, 7, 6, 0), (1, 3, 2, 3, 0), (0, 2, 1, 1, 64),
+                                            (1, 3, 3, 4, 63), (2, 3, 3, 2, 21), (1, 3, 4, 2, 84)])
 def test_patch_layout_valid(form, dim, n, k, P):
     m = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(n))
     st = fx.check_patch_layout(form, m, P)
@@ -134,7 +135,7 @@ def test_patch_layout_valid(form, dim, n, k, P):
 def test_patch_layout_rejects_bad_size():
     m = meshgen.unit_square(4, 2)
     with pytest.raises(fx.FemError):
-        fx.check_patch_layout(0, m, 100)
+        fx.check_patch_layout(0, m, 300)
 
 
 @pytest.mark.parametrize("dim,deg", [(2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2)])

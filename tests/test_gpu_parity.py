@@ -67,10 +67,18 @@ CASES = [(f, 2, k) for f in (0, 1, 2) for k in range(1, 7)] + \
         [(f, 3, k) for f in (0, 1, 2) for k in range(1, 5)]
 
 
-STRATS = [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 64, 1), (fx.SCATTER_COLOUR, 0, 0)]
+STRATS = [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 64, 1), (fx.SCATTER_COLOUR, 0, 0),
+          (fx.SCATTER_PATCH, 42, 3)]
+STRAT_IDS = ["patch", "patch64x1", "colour", "patch42x3"]
 
 
-@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64x1", "colour"])
+def apply_strategy(plan, strategy, form, dim):
+    if strategy[2] == 3 and (dim != 3 or form == fx.FORM_MASS):
+        pytest.skip("three lanes per cell exist for the 3D vector forms only")
+    plan.set_strategy(*strategy)
+
+
+@pytest.mark.parametrize("strategy", STRATS, ids=STRAT_IDS)
 @pytest.mark.parametrize("form,dim,k", CASES)
 def test_action_small_meshes(form, dim, k, strategy):
     # 2D n=9: 162 cells; 3D n=3: 162 cells -- several wavefronts / patches plus a ragged tail
@@ -80,14 +88,14 @@ def test_action_small_meshes(form, dim, k, strategy):
     qd = qdeg(form, k)
     say(f"[action] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd} strat={strategy}")
     plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
-    plan.set_strategy(*strategy)
+    apply_strategy(plan, strategy, form, dim)
     y = plan.action(gpu(u)).cpu().numpy()
     ref = oracle.action(form, mesh, u, qd, params_for(form))
     emax, el2 = rel_err(y, ref)
     assert emax < TOL and el2 < TOL, (emax, el2)
 
 
-@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64x1", "colour"])
+@pytest.mark.parametrize("strategy", STRATS, ids=STRAT_IDS)
 @pytest.mark.parametrize("form,dim,k", CASES)
 def test_vjp_small_meshes(form, dim, k, strategy):
     n = 7 if dim == 2 else 2
@@ -96,7 +104,7 @@ def test_vjp_small_meshes(form, dim, k, strategy):
     qd = qdeg(form, k)
     say(f"[vjp] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd} strat={strategy}")
     plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
-    plan.set_strategy(*strategy)
+    apply_strategy(plan, strategy, form, dim)
     g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
     ref = oracle.vjp(form, mesh, u, v, qd, params_for(form))
     emax, el2 = rel_err(g, ref)
@@ -116,7 +124,7 @@ def test_block_sizes_bitwise_identical(block):
     assert np.array_equal(y0, y1)
 
 
-@pytest.mark.parametrize("strategy", STRATS, ids=["patch", "patch64x1", "colour"])
+@pytest.mark.parametrize("strategy", STRATS, ids=STRAT_IDS)
 def test_determinism_and_stream(strategy):
     w = meshgen.workload("elast_p2_3d", n=6)
     say(f"[determinism] elast_p2_3d n=6 {strategy}")
@@ -179,8 +187,8 @@ _ref_cache = {}
 
 
 @pytest.mark.parametrize("strategy", [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 128, 1),
-                                      (fx.SCATTER_COLOUR, 0, 0)],
-                         ids=["patch", "patch128x1", "colour"])
+                                      (fx.SCATTER_COLOUR, 0, 0), (fx.SCATTER_PATCH, 84, 3)],
+                         ids=["patch", "patch128x1", "colour", "patch84x3"])
 @pytest.mark.parametrize("name", FULL)
 def test_full_size_against_oracle(name, strategy):
     """Every output of the full-size workloads against the oracle (seconds on the host)."""
@@ -197,7 +205,7 @@ def test_full_size_against_oracle(name, strategy):
     w, ref = _ref_cache[name]
     say(f"[full] {name} cells={w.mesh.n_cell} dofs={w.n_dof} {strategy}")
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
-    plan.set_strategy(*strategy)
+    apply_strategy(plan, strategy, w.form, w.mesh.dim)
     if w.v is not None:
         out = plan.vjp(gpu(w.u), gpu(w.v)).cpu().numpy()
     else:
