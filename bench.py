@@ -87,6 +87,31 @@ def time_steps(fn, steps: int, warmup: int):
     return ms, wall
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in ("paper_2506_17471_amd/csrc/forms.h", "paper_2506_17471_amd/csrc/kernels.hip"):
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json), or None
+    when the kernel sources changed since they were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash() or workload not in rec:
+        return None
+    r = rec[workload]
+    return r["fetch_kib"] * 1024 * r["fetch_scale"] + r["write_kib"] * 1024 * r["write_scale"]
+
+
 def cold_flush(buf):
     """Stream a buffer larger than the 256 MB MALL so that the next step starts cold."""
     buf.add_(1.0)
@@ -318,7 +343,8 @@ def main():
                    "n_dof": main_info["n_dof"], "n_quad": main_info["n_quad"],
                    "launch": main_info["tuned"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": recorded_traffic(args.workload),
                      "kernel": "patch_kernel (neo-Hookean, 2D, P4) + fixup_kernel",
                      "flops_per_launch": main_info["flops"],
                      "avg_step_ms": main_info["ms_mean"],

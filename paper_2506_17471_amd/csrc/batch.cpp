@@ -19,6 +19,7 @@ struct fem_batch {
         size_t lds = 0;
         int64_t n_patch = 0;
         std::vector<int> members;
+        std::vector<size_t> members_lds_a;
         std::vector<femx::BatchDesc> desc;
         femx::BatchDesc *d_desc = nullptr;
         int32_t *d_patch_mesh = nullptr;
@@ -210,6 +211,8 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             g.n_patch += p->n_patch;
             g.lds = std::max(g.lds, femx::patch_lds_bytes(p->form, p->dim, p->degree, false, p->patch,
                                                           p->max_patch_nodes));
+            g.members_lds_a.push_back(
+                femx::patch_lds_a(p->form, p->dim, p->degree, false, p->patch, p->max_patch_nodes));
             if (p->n_shared > 0) {
                 femx::FixDesc f{};
                 f.fix_node = p->d_fix_node;
@@ -223,6 +226,20 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             }
         }
         for (auto &g : b->groups) {
+            // every mesh of the group shares one dynamic LDS size: region A takes the
+            // group's largest, region B follows it
+            size_t a_max = 0;
+            for (size_t v : g.members_lds_a) a_max = std::max(a_max, v);
+            size_t b_max = 0;
+            for (size_t k = 0; k < g.members.size(); ++k) {
+                const fem_plan *p = b->plans[g.members[k]];
+                const size_t bb = femx::patch_lds_bytes(p->form, p->dim, p->degree, false, p->patch,
+                                                        p->max_patch_nodes) -
+                                  8 * g.members_lds_a[k];
+                b_max = std::max(b_max, bb);
+                g.desc[k].args.lds_a = (int)a_max;
+            }
+            g.lds = 8 * a_max + b_max;
             std::vector<int32_t> pm((size_t)g.n_patch);
             for (size_t k = 0; k < g.members.size(); ++k) {
                 const fem_plan *p = b->plans[g.members[k]];

@@ -79,6 +79,7 @@ struct PatchArgs {
     int64_t stride;
     int64_t n_cell;
     int nq;
+    int lds_a;                  // doubles of LDS region A (staging / element buffer)
     double lam, mu;
 };
 
@@ -148,6 +149,7 @@ hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double 
 // LDS bytes the patch kernel needs for a patch of `patch` cells with at most
 // `max_nodes` distinct nodes.
 size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes);
+size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes);
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
 bool pair_available(int form, int dim, int degree);
 bool triple_available(int form, int dim, int degree);

@@ -126,7 +126,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     const int U = a.patch_off[p + 1] - nb;
 
     // 1. the cell's own loads (geometry, local node indices) go out first, then the patch's
-    //    distinct nodal values are staged in LDS
+    //    distinct nodal values are staged in LDS (region A)
     const int64_t s = p * P + cl;
     const bool active = cl < P && s < a.n_cell;
     constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
@@ -137,12 +137,25 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 #pragma unroll
         for (int n = 0; n < NLOC; ++n) lid[n] = a.lidx[n * a.stride + s];
     }
+    // LDS region B: the metadata of the final sums (slot ranges relative to the patch's
+    // first slot, destinations, node ids, slots), loaded now so that the last phase
+    // touches global memory only to store
+    const int e_base = a.csr_off[nb];
+    const int n_slots = a.csr_off[nb + U] - e_base;
+    int32_t *b_off = reinterpret_cast<int32_t *>(lds + a.lds_a);
+    int32_t *b_dest = b_off + U + 1;
+    int32_t *b_node = b_dest + U;
+    uint16_t *b_slot = reinterpret_cast<uint16_t *>(b_node + U);
+    for (int j = tid; j <= U; j += nthreads) b_off[j] = a.csr_off[nb + j] - e_base;
+    for (int e = tid; e < n_slots; e += nthreads) b_slot[e] = a.csr_slots[e_base + e];
     for (int j = tid; j < U; j += nthreads) {
-        const int64_t nd = a.patch_nodes[nb + j];
+        const int32_t nd = a.patch_nodes[nb + j];
+        b_node[j] = nd;
+        b_dest[j] = a.patch_dest[nb + j];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            lds[j * NC + c] = a.u[nd * NC + c];
-            if constexpr (VJP) lds[(U + j) * NC + c] = a.v[nd * NC + c];
+            lds[j * NC + c] = a.u[(int64_t)nd * NC + c];
+            if constexpr (VJP) lds[(U + j) * NC + c] = a.v[(int64_t)nd * NC + c];
         }
     }
     __syncthreads();
@@ -198,19 +211,19 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 
     // 4. each distinct node summed by one lane in a fixed order
     for (int j = tid; j < U; j += nthreads) {
-        const int e0 = a.csr_off[nb + j], e1 = a.csr_off[nb + j + 1];
+        const int e0 = b_off[j], e1 = b_off[j + 1];
         double sum[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) sum[c] = 0.0;
         for (int e = e0; e < e1; ++e) {
-            const int sl = a.csr_slots[e];
+            const int sl = b_slot[e];
             const int an = sl >> 8, sc = sl & 255;
 #pragma unroll
             for (int c = 0; c < NC; ++c) sum[c] += lds[(an * NC + c) * P + sc];
         }
-        const int dest = a.patch_dest[nb + j];
+        const int dest = b_dest[j];
         if (dest < 0) {
-            const int64_t nd = a.patch_nodes[nb + j];
+            const int64_t nd = b_node[j];
 #pragma unroll
             for (int c = 0; c < NC; ++c) a.y[nd * NC + c] = sum[c];
         } else {
@@ -373,13 +386,20 @@ hipError_t launch_action(const fem_plan &p, const LaunchArgs &a, int block, bool
     return hipGetLastError();
 }
 
-size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes)
+size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes)
 {
     const int nloc = nloc_of(dim, degree);
     const int nc = form == FEM_MASS ? 1 : dim;
     const size_t stage = (size_t)max_nodes * nc * (vjp ? 2 : 1);
     const size_t elem = (size_t)patch * nloc * nc;
-    return 8 * (stage > elem ? stage : elem);
+    return stage > elem ? stage : elem;   // doubles
+}
+
+size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes)
+{
+    const int nloc = nloc_of(dim, degree);
+    const size_t b = 4 * (3 * (size_t)max_nodes + 1) + 2 * (size_t)patch * nloc;
+    return 8 * patch_lds_a(form, dim, degree, vjp, patch, max_nodes) + ((b + 7) & ~(size_t)7);
 }
 
 bool pair_available(int form, int dim, int degree)

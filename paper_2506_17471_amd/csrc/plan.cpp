@@ -534,6 +534,8 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         a.stride = p->pstride;
         a.n_cell = p->n_cell;
         a.nq = p->nq;
+        a.lds_a = (int)femx::patch_lds_a(p->form, p->dim, p->degree, nl_vjp, p->patch,
+                                         p->max_patch_nodes);
         a.lam = p->lam;
         a.mu = p->mu;
         femx::check_hip(femx::launch_patch(*p, a, nl_vjp, s), "patch launch");
