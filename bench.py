@@ -130,10 +130,11 @@ def make_plan(w, tune: bool, vjp: bool = False):
     tuned = None
     if tune:
         res = plan.tune(u, y=y, v=v)
-        best = min(res, key=lambda r: r[4])
+        best = min(res, key=lambda r: r[5])
         tuned = {"strategy": "patch" if best[0] == 1 else "colour", "cells_per_patch": int(best[1]),
-                 "lanes_per_cell": int(best[2]), "block": int(best[3]), "tuner_ms": best[4],
-                 "candidates": len(res)}
+                 "lanes_per_cell": int(best[2]), "block": int(best[3]),
+                 "sum_mode": {1: "element", 2: "coloured"}.get(int(best[4]), "-"),
+                 "tuner_ms": best[5], "candidates": len(res)}
     return plan, u, v, y, tuned
 
 
@@ -215,12 +216,12 @@ def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
                 kinds[k] = i
         for k, i in kinds.items():
             res = plans[i].tune(us[i], y=ys[i])
-            best = min(res, key=lambda r: r[4])
-            tuned[k] = [int(best[0]), int(best[1]), int(best[2]), int(best[3])]
+            best = min(res, key=lambda r: r[5])
+            tuned[k] = [int(best[0]), int(best[1]), int(best[2]), int(best[3]), int(best[4])]
             for j, w in enumerate(ws):
                 if w.name.split("_", 1)[1] == k and j != i:
                     if best[0] == 1:
-                        plans[j].set_strategy(1, int(best[1]), int(best[2]))
+                        plans[j].set_strategy(1, int(best[1]), int(best[2]), int(best[4]))
                     else:
                         plans[j].set_strategy(0)
                         plans[j].set_block(int(best[3]))

@@ -165,23 +165,34 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *   FEM_SCATTER_COLOUR  one launch per colour of the greedy colouring; a lane owning a
  *                       cell read-add-writes its nodes (no two cells of a launch share one).
  *   FEM_SCATTER_PATCH   one launch over patches of `patch_cells` consecutive cells along a
- *                       Morton curve of the cell centroids (64, 128 or 256).  A workgroup
- *                       stages its patch's nodal values in LDS, keeps the cell vectors in an
- *                       LDS element buffer and sums every node in a fixed order; nodes that
- *                       several patches hold are summed in patch order by a second, small
- *                       kernel.  `lanes_per_cell` 2 splits a cell's two components over a
- *                       lane pair (2D vector forms only; patch_cells * lanes <= 256).  The
- *                       default; 0 for either size picks the plan's default (two lanes for
- *                       the 2D vector forms, the largest patch whose element buffer fits
- *                       64 KB of LDS).
+ *                       Morton curve of the cell centroids.  A workgroup stages its patch's
+ *                       nodal values in LDS and sums its cells' vectors into the patch's
+ *                       nodes in a fixed order; nodes no other patch holds are stored, the
+ *                       others leave as partial sums that a second, small kernel adds in
+ *                       patch order.  The default.
+ *   lanes_per_cell  1; 2 (2D vector forms: lane c of a pair owns component c); 3 (3D vector
+ *                   forms: lane triples, 21 per wavefront).
+ *   patch_cells     64, 128 or 256 with 1 or 2 lanes (at most 256 lanes per workgroup);
+ *                   21, 42, 63 or 84 with 3.
+ *   sum_mode        FEM_SUM_ELEMENT: every cell vector to an LDS element buffer, each node
+ *                   summing its slots in ascending (cell, local node); FEM_SUM_COLOURED:
+ *                   cells greedily coloured inside the patch accumulate into an LDS node
+ *                   buffer colour by colour (smaller LDS, one barrier per colour).
+ *   0 for lanes_per_cell, patch_cells or sum_mode picks the plan's default (three lanes
+ *   for 3D vector forms of degree >= 3 when the patch size allows it, one otherwise; the
+ *   largest patch whose element buffer fits 64 KB; coloured sums in 2D, element buffer in
+ *   3D).
  * Rebuilding patches synchronises the device.  Errors: FEM_E_ARG, FEM_E_UNSUPPORTED (a lane
  * split the form lacks, or more than 160 KB of LDS), FEM_E_HIP, FEM_E_NOMEM.
  */
 #define FEM_SCATTER_COLOUR 0
 #define FEM_SCATTER_PATCH 1
-int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell);
+#define FEM_SUM_ELEMENT 1
+#define FEM_SUM_COLOURED 2
+int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell,
+                          int sum_mode);
 int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
-                          int *lanes_per_cell);
+                          int *lanes_per_cell, int *sum_mode);
 
 /*
  * Autotuner: time every launch configuration of the plan on the caller's vectors and keep
@@ -196,8 +207,8 @@ int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
  *          a cached configuration when the environment variable FEM_TUNE_CACHE names the
  *          file.  Keys: device architecture, form, dimension, degree, quadrature degree,
  *          round(log2(cell count)).
- *   results HOST f64 [max_results][5] out: strategy, cells per patch, lanes per cell,
- *          cells per workgroup (colour), mean milliseconds; n_results HOST out.
+ *   results HOST f64 [max_results][6] out: strategy, cells per patch, lanes per cell,
+ *          cells per workgroup (colour), sum mode, mean milliseconds; n_results HOST out.
  * Errors: FEM_E_ARG, FEM_E_HIP, FEM_E_NOMEM.
  */
 int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vjp,
@@ -239,9 +250,9 @@ void fem_batch_destroy(fem_batch *batch);
  * map names, every index the kernels follow lies inside its buffer, and every shared node's
  * partial slots are written once.  The same check runs inside fem_plan_create when the
  * environment variable FEM_CHECK=1 is set.
- *   stats HOST i64 [7] out (may be NULL): cells per patch, patches, most distinct nodes in a
+ *   stats HOST i64 [8] out (may be NULL): cells per patch, patches, most distinct nodes in a
  *         patch, (patch, node) pairs, shared nodes, partial slots, LDS bytes per workgroup
- *         for the forward kernel.
+ *         for the forward kernel in the default sum mode, most sub-colours in a patch.
  * Errors: FEM_E_ARG (including a layout violation), FEM_E_INDEX, FEM_E_INVERTED,
  * FEM_E_UNSUPPORTED.
  */

@@ -26,6 +26,7 @@ __all__ = ["FORM_MASS", "FORM_ELASTICITY", "FORM_NEOHOOKEAN", "FemError", "Plan"
 FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN = 0, 1, 2
 QUAD_CONICAL, QUAD_SYMMETRIC = 0, 1
 SCATTER_COLOUR, SCATTER_PATCH = 0, 1
+SUM_ELEMENT, SUM_COLOURED = 1, 2
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfemx.so")
 
 _STATUS = {0: "FEM_OK", -1: "FEM_E_ARG", -2: "FEM_E_UNSUPPORTED", -3: "FEM_E_INDEX",
@@ -71,9 +72,9 @@ def lib() -> ctypes.CDLL:
     L.fem_reference_tables.restype = i32
     L.fem_plan_set_block.argtypes = [P, i32]
     L.fem_plan_set_block.restype = i32
-    L.fem_plan_set_strategy.argtypes = [P, i32, i32, i32]
+    L.fem_plan_set_strategy.argtypes = [P, i32, i32, i32, i32]
     L.fem_plan_set_strategy.restype = i32
-    L.fem_plan_get_strategy.argtypes = [P, P, P, P]
+    L.fem_plan_get_strategy.argtypes = [P, P, P, P, P]
     L.fem_plan_get_strategy.restype = i32
     L.fem_tune.argtypes = [P, P, P, P, i32, ctypes.c_char_p, P, P, i32, P]
     L.fem_tune.restype = i32
@@ -140,12 +141,12 @@ def check_patch_layout(form: int, mesh, patch_cells: int = 0) -> dict:
     xy = np.ascontiguousarray(mesh.coords, dtype=np.float64)
     cv = np.ascontiguousarray(mesh.cell_verts, dtype=np.int32)
     cn = np.ascontiguousarray(mesh.cell_nodes, dtype=np.int32)
-    st = np.zeros(7, dtype=np.int64)
+    st = np.zeros(8, dtype=np.int64)
     _check(L.fem_check_patch_layout(form, mesh.dim, mesh.k, xy.shape[0], _np_ptr(xy), cv.shape[0],
                                     _np_ptr(cv), _np_ptr(cn), int(mesh.n_node), patch_cells,
                                     _np_ptr(st)))
     keys = ["patch_cells", "n_patch", "max_patch_nodes", "patch_node_pairs", "shared_nodes",
-            "partial_slots", "lds_bytes"]
+            "partial_slots", "lds_bytes", "max_colours"]
     return dict(zip(keys, (int(x) for x in st)))
 
 
@@ -231,30 +232,32 @@ class Plan:
     def set_block(self, cells_per_block: int):
         _check(lib().fem_plan_set_block(self.handle, cells_per_block))
 
-    def set_strategy(self, strategy: int, patch_cells: int = 0, lanes_per_cell: int = 0):
-        _check(lib().fem_plan_set_strategy(self.handle, strategy, patch_cells, lanes_per_cell))
+    def set_strategy(self, strategy: int, patch_cells: int = 0, lanes_per_cell: int = 0,
+                     sum_mode: int = 0):
+        _check(lib().fem_plan_set_strategy(self.handle, strategy, patch_cells, lanes_per_cell,
+                                           sum_mode))
 
     def strategy(self):
-        st, pc, ln = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        st, pc, ln, sm = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().fem_plan_get_strategy(self.handle, ctypes.byref(st), ctypes.byref(pc),
-                                           ctypes.byref(ln)))
-        return st.value, pc.value, ln.value
+                                           ctypes.byref(ln), ctypes.byref(sm)))
+        return st.value, pc.value, ln.value, sm.value
 
     def tune(self, u, y=None, v=None, cache_path: str | None = None, stream=None):
         """Time every launch configuration on (u[, v]) and keep the fastest.
 
-        Returns a list of (strategy, cells_per_patch, lanes_per_cell, block, ms)."""
+        Returns a list of (strategy, cells_per_patch, lanes_per_cell, block, sum_mode, ms)."""
         import torch
         if y is None:
             y = torch.empty_like(u)
-        res = np.zeros((32, 5))
+        res = np.zeros((64, 6))
         nres = ctypes.c_int()
         vjp = v is not None
         _check(lib().fem_tune(self.handle, _dev_ptr(u, self.n_dof, "u"),
                               _dev_ptr(v, self.n_dof, "v") if vjp else None,
                               _dev_ptr(y, self.n_dof, "y"), int(vjp),
                               cache_path.encode() if cache_path else None, _stream_handle(stream),
-                              _np_ptr(res), 32, ctypes.byref(nres)))
+                              _np_ptr(res), 64, ctypes.byref(nres)))
         return [tuple(r) for r in res[:nres.value]]
 
     def colouring(self) -> np.ndarray:

@@ -15,7 +15,7 @@
 
 struct fem_batch {
     struct Group {
-        int form, dim, degree, lanes, patch;
+        int form, dim, degree, lanes, patch, sum_mode;
         size_t lds = 0;
         int64_t n_patch = 0;
         std::vector<int> members;
@@ -77,9 +77,12 @@ femx::PatchArgs patch_args(const fem_plan *p, const double *u, double *y)
     femx::PatchArgs a{};
     a.verts = p->d_pverts;
     a.lidx = p->d_lidx;
+    a.colour = p->d_colour;
     a.patch_off = p->d_patch_off;
     a.patch_nodes = p->d_patch_nodes;
-    a.patch_dest = p->d_patch_dest;
+    a.patch_nint = p->d_patch_nint;
+    a.patch_pbase = p->d_patch_pbase;
+    a.patch_ncol = p->d_patch_ncol;
     a.csr_off = p->d_csr_off;
     a.csr_slots = p->d_csr_slots;
     a.coords = p->d_coords;
@@ -146,8 +149,9 @@ void set_vectors(fem_batch *b, const double *const *u, double *const *y)
 void enqueue(fem_batch *b, hipStream_t s)
 {
     for (auto &g : b->groups)
-        femx::check_hip(femx::launch_batch_patch(g.form, g.dim, g.degree, g.lanes, g.patch, g.d_desc,
-                                                 g.d_patch_mesh, g.n_patch, g.lds, s),
+        femx::check_hip(femx::launch_batch_patch(g.form, g.dim, g.degree, g.lanes, g.patch,
+                                                 g.sum_mode, g.d_desc, g.d_patch_mesh, g.n_patch,
+                                                 g.lds, s),
                         "batched patch launch");
     if (b->n_fix > 0)
         femx::check_hip(femx::launch_batch_fixup(b->d_fix, (int)b->fix.size(), b->n_fix, s),
@@ -182,15 +186,16 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             for (int j = 0; j < i; ++j)
                 if (plans[j] == p) throw Error(FEM_E_ARG, "a plan appears twice in the batch");
             if (p->n_cell > 0 && (p->strategy != femx::STRAT_PATCH || p->patch == 0))
-                femx::set_strategy(p, FEM_SCATTER_PATCH, 0, 0);
+                femx::set_strategy(p, FEM_SCATTER_PATCH, 0, 0, 0);
             b->plans.push_back(p);
         }
         // group by kernel variant
-        std::map<std::tuple<int, int, int, int, int>, int> gid;
+        std::map<std::tuple<int, int, int, int, int, int>, int> gid;
         for (int i = 0; i < n; ++i) {
             fem_plan *p = b->plans[i];
             if (p->n_cell == 0) continue;
-            const auto key = std::make_tuple(p->form, p->dim, p->degree, p->lanes, p->patch);
+            const auto key =
+                std::make_tuple(p->form, p->dim, p->degree, p->lanes, p->patch, p->sum_mode);
             auto it = gid.find(key);
             if (it == gid.end()) {
                 it = gid.emplace(key, (int)b->groups.size()).first;
@@ -200,6 +205,7 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
                 g.degree = p->degree;
                 g.lanes = p->lanes;
                 g.patch = p->patch;
+                g.sum_mode = p->sum_mode;
                 b->groups.push_back(g);
             }
             fem_batch::Group &g = b->groups[it->second];
@@ -209,14 +215,13 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             d.first_patch = g.n_patch;
             g.desc.push_back(d);
             g.n_patch += p->n_patch;
-            g.lds = std::max(g.lds, femx::patch_lds_bytes(p->form, p->dim, p->degree, false, p->patch,
-                                                          p->max_patch_nodes));
-            g.members_lds_a.push_back(
-                femx::patch_lds_a(p->form, p->dim, p->degree, false, p->patch, p->max_patch_nodes));
+            g.members_lds_a.push_back(femx::patch_lds_a(p->form, p->dim, p->degree, false, p->patch,
+                                                        p->max_patch_nodes, p->sum_mode));
             if (p->n_shared > 0) {
                 femx::FixDesc f{};
                 f.fix_node = p->d_fix_node;
                 f.fix_off = p->d_fix_off;
+                f.fix_slot = p->d_fix_slot;
                 f.partial = p->d_partial;
                 f.first = b->n_fix;
                 f.ncomp = p->ncomp;
@@ -234,12 +239,14 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             for (size_t k = 0; k < g.members.size(); ++k) {
                 const fem_plan *p = b->plans[g.members[k]];
                 const size_t bb = femx::patch_lds_bytes(p->form, p->dim, p->degree, false, p->patch,
-                                                        p->max_patch_nodes) -
+                                                        p->max_patch_nodes, p->sum_mode) -
                                   8 * g.members_lds_a[k];
                 b_max = std::max(b_max, bb);
                 g.desc[k].args.lds_a = (int)a_max;
             }
             g.lds = 8 * a_max + b_max;
+            if (g.lds > 160 * 1024)
+                throw Error(FEM_E_UNSUPPORTED, "a batch group needs more than 160 KB of LDS");
             std::vector<int32_t> pm((size_t)g.n_patch);
             for (size_t k = 0; k < g.members.size(); ++k) {
                 const fem_plan *p = b->plans[g.members[k]];

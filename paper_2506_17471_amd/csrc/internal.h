@@ -65,9 +65,12 @@ struct LaunchArgs {
 struct PatchArgs {
     const int32_t *verts;       // SoA [(dim+1)][stride] vertex ids, patch-sorted cells
     const uint16_t *lidx;       // SoA [nloc][stride] patch-local node index of (cell, a)
+    const uint8_t *colour;      // [stride] sub-colour of each cell inside its patch
     const int32_t *patch_off;   // [n_patch + 1] into the (patch, node) list
-    const int32_t *patch_nodes; // global node id of each (patch, node)
-    const int32_t *patch_dest;  // -1: node held by this patch only, else partial slot
+    const int32_t *patch_nodes; // global node id of each (patch, node): interior ones first
+    const int32_t *patch_nint;  // [n_patch] interior (unshared) nodes of each patch
+    const int32_t *patch_pbase; // [n_patch] first partial slot of each patch's shared nodes
+    const uint8_t *patch_ncol;  // [n_patch] sub-colours of each patch
     const int32_t *csr_off;     // [n_pn + 1] element-buffer slots summed into (patch, node)
     const uint16_t *csr_slots;  // slot = a << 8 | local cell, in ascending (cell, a)
     const double *coords;
@@ -84,6 +87,7 @@ struct PatchArgs {
 };
 
 enum Strategy { STRAT_COLOUR = 0, STRAT_PATCH = 1 };
+enum SumMode { SUM_ELEMENT = 1, SUM_COLOURED = 2 };
 
 // One mesh of a batched launch (device-resident array of these).
 struct BatchDesc {
@@ -95,6 +99,7 @@ struct BatchDesc {
 struct FixDesc {
     const int32_t *fix_node;
     const int32_t *fix_off;
+    const int32_t *fix_slot;
     const double *partial;
     double *y;
     int64_t first;           // index of the mesh's first (shared node, component) item
@@ -129,10 +134,14 @@ struct fem_plan {
     int max_patch_nodes = 0;
     int32_t *d_pverts = nullptr;
     uint16_t *d_lidx = nullptr;
-    int32_t *d_patch_off = nullptr, *d_patch_nodes = nullptr, *d_patch_dest = nullptr;
+    int sum_mode = femx::SUM_ELEMENT;    // how a patch sums its cell vectors
+    int max_colours = 0;                 // most sub-colours in a patch
+    uint8_t *d_colour = nullptr, *d_patch_ncol = nullptr;
+    int32_t *d_patch_off = nullptr, *d_patch_nodes = nullptr;
+    int32_t *d_patch_nint = nullptr, *d_patch_pbase = nullptr;
     int32_t *d_csr_off = nullptr;
     uint16_t *d_csr_slots = nullptr;
-    int32_t *d_fix_node = nullptr, *d_fix_off = nullptr;
+    int32_t *d_fix_node = nullptr, *d_fix_off = nullptr, *d_fix_slot = nullptr;
     double *d_partial = nullptr;
     int64_t pstride = 0;
     std::vector<double> h_coords;        // host copies, to rebuild patches on request
@@ -148,23 +157,25 @@ hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double 
                              hipStream_t s);
 // LDS bytes the patch kernel needs for a patch of `patch` cells with at most
 // `max_nodes` distinct nodes.
-size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes);
-size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes);
+size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes,
+                       int sum_mode);
+size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode);
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
 bool pair_available(int form, int dim, int degree);
 bool triple_available(int form, int dim, int degree);
-hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch,
+hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch, int sum_mode,
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
                               size_t lds, hipStream_t s);
 hipError_t launch_batch_fixup(const FixDesc *fix, int n_mesh, int64_t n, hipStream_t s);
 // plan.cpp (throwing versions of the ABI calls, for the tuner and the batch)
-void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell);
+void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell, int sum_mode);
 void run_action(const fem_plan *p, const double *u, const double *v, double *y, hipStream_t s,
                 bool vjp);
 // tune.cpp
 void apply_tuning_cache(fem_plan *p);
 int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
          hipStream_t s, double *results, int max_results, int *n_results);
-hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t n_shared,
-                        const double *partial, int ncomp, double *y, hipStream_t s);
+hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, const int32_t *fix_slot,
+                        int64_t n_shared, const double *partial, int ncomp, double *y,
+                        hipStream_t s);
 }  // namespace femx

@@ -97,8 +97,9 @@ __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
 // ------------------------------------------------------------------- patch strategy
 // LPC lanes per cell: 1; 2 for the 2D vector forms (lane c of a pair owns component c);
 // 3 for the 3D vector forms (lane c of a triple owns component c; a wavefront holds 21
-// triples and leaves its last lane idle).
-template <int FORM, int DIM, int K, bool VJP, int LPC>
+// triples and leaves its last lane idle).  SUM: SUM_ELEMENT (LDS element buffer and fixed-
+// order node sums) or SUM_COLOURED (sub-colour phases accumulating into an LDS node buffer).
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
 __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 {
     constexpr int NLOC = nloc_of(DIM, K);
@@ -124,9 +125,12 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     }
     const int nb = a.patch_off[p];
     const int U = a.patch_off[p + 1] - nb;
+    const int nint = a.patch_nint[p];
+    const int pbase = a.patch_pbase[p];
 
     // 1. the cell's own loads (geometry, local node indices) go out first, then the patch's
-    //    distinct nodal values are staged in LDS (region A)
+    //    distinct nodal values are staged in LDS (region A) and its node ids (and, for the
+    //    element buffer, its sum lists) in region B
     const int64_t s = p * P + cl;
     const bool active = cl < P && s < a.n_cell;
     constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
@@ -137,21 +141,19 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 #pragma unroll
         for (int n = 0; n < NLOC; ++n) lid[n] = a.lidx[n * a.stride + s];
     }
-    // LDS region B: the metadata of the final sums (slot ranges relative to the patch's
-    // first slot, destinations, node ids, slots), loaded now so that the last phase
-    // touches global memory only to store
-    const int e_base = a.csr_off[nb];
-    const int n_slots = a.csr_off[nb + U] - e_base;
-    int32_t *b_off = reinterpret_cast<int32_t *>(lds + a.lds_a);
-    int32_t *b_dest = b_off + U + 1;
-    int32_t *b_node = b_dest + U;
-    uint16_t *b_slot = reinterpret_cast<uint16_t *>(b_node + U);
-    for (int j = tid; j <= U; j += nthreads) b_off[j] = a.csr_off[nb + j] - e_base;
-    for (int e = tid; e < n_slots; e += nthreads) b_slot[e] = a.csr_slots[e_base + e];
+    int32_t *b_node = reinterpret_cast<int32_t *>(lds + a.lds_a);
+    int32_t *b_off = b_node + U;              // element buffer only
+    uint16_t *b_slot = reinterpret_cast<uint16_t *>(b_off + U + 1);
+    int e_base = 0;
+    if constexpr (SUM == SUM_ELEMENT) {
+        e_base = a.csr_off[nb];
+        const int n_slots = a.csr_off[nb + U] - e_base;
+        for (int j = tid; j <= U; j += nthreads) b_off[j] = a.csr_off[nb + j] - e_base;
+        for (int e = tid; e < n_slots; e += nthreads) b_slot[e] = a.csr_slots[e_base + e];
+    }
     for (int j = tid; j < U; j += nthreads) {
         const int32_t nd = a.patch_nodes[nb + j];
         b_node[j] = nd;
-        b_dest[j] = a.patch_dest[nb + j];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             lds[j * NC + c] = a.u[(int64_t)nd * NC + c];
@@ -173,9 +175,13 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
             }
         }
     }
-    __syncthreads();   // the staged values are dead from here on; LDS becomes the element buffer
+    __syncthreads();   // the staged values are dead from here on; region A is reused
 
-    // 3. the cell's quadrature loop; its vector goes to the element buffer
+    if constexpr (SUM == SUM_COLOURED) {
+        for (int j = tid; j < U * NC; j += nthreads) lds[j] = 0.0;   // the node accumulator
+    }
+
+    // 3. the cell's quadrature loop
     if (active) {
         if constexpr (LPC == 1) {
             cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
@@ -202,48 +208,78 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 #pragma unroll
             for (int n = 0; n < NLOC; ++n) yl[n][0] = y1[n];
         }
-#pragma unroll
-        for (int n = 0; n < NLOC; ++n)
-#pragma unroll
-            for (int c = 0; c < CW; ++c) lds[(n * NC + c + comp) * P + cl] = yl[n][c];
     }
-    __syncthreads();
 
-    // 4. each distinct node summed by one lane in a fixed order
-    for (int j = tid; j < U; j += nthreads) {
-        const int e0 = b_off[j], e1 = b_off[j + 1];
-        double sum[NC];
+    // 4. sum the cell vectors into the patch's nodes
+    if constexpr (SUM == SUM_ELEMENT) {
+        if (active) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sum[c] = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            const int sl = b_slot[e];
-            const int an = sl >> 8, sc = sl & 255;
+            for (int n = 0; n < NLOC; ++n)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sum[c] += lds[(an * NC + c) * P + sc];
+                for (int c = 0; c < CW; ++c) lds[(n * NC + c + comp) * P + cl] = yl[n][c];
         }
-        const int dest = b_dest[j];
-        if (dest < 0) {
+        __syncthreads();
+    } else {
+        // reloaded after the barriers rather than kept live through the quadrature loop
+        const int col = active ? a.colour[s] : -1;
+        int lid2[NLOC];
+        if (active) {
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) lid2[n] = a.lidx[n * a.stride + s];
+        }
+        const int ncol = a.patch_ncol[p];
+        __syncthreads();                      // the accumulator is zero everywhere
+        for (int k = 0; k < ncol; ++k) {
+            if (col == k) {
+#pragma unroll
+                for (int n = 0; n < NLOC; ++n)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) lds[lid2[n] * NC + c + comp] += yl[n][c];
+            }
+            __syncthreads();
+        }
+    }
+
+    // 5. each distinct node stored once: interior nodes into y, shared ones as partials
+    for (int j = tid; j < U; j += nthreads) {
+        double sum[NC];
+        if constexpr (SUM == SUM_ELEMENT) {
+            const int e0 = b_off[j], e1 = b_off[j + 1];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sum[c] = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int sl = b_slot[e];
+                const int an = sl >> 8, sc = sl & 255;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sum[c] += lds[(an * NC + c) * P + sc];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sum[c] = lds[j * NC + c];
+        }
+        if (j < nint) {
             const int64_t nd = b_node[j];
 #pragma unroll
             for (int c = 0; c < NC; ++c) a.y[nd * NC + c] = sum[c];
         } else {
+            const int64_t dest = pbase + (j - nint);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a.partial[(int64_t)dest * NC + c] = sum[c];
+            for (int c = 0; c < NC; ++c) a.partial[dest * NC + c] = sum[c];
         }
     }
 }
 
-template <int FORM, int DIM, int K, bool VJP, int LPC>
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
 __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
     patch_kernel(const PatchArgs a, int P)
 {
-    patch_body<FORM, DIM, K, VJP, LPC>(a, blockIdx.x, P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM>(a, blockIdx.x, P);
 }
 
 // Many meshes of one kernel variant in one launch: workgroup b works on patch
 // b - desc[m].first_patch of mesh m = patch_mesh[b].
-template <int FORM, int DIM, int K, bool VJP, int LPC>
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
 __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
     batch_patch_kernel(const BatchDesc *__restrict__ desc, const int32_t *__restrict__ patch_mesh,
@@ -251,7 +287,7 @@ __global__ void __launch_bounds__(kMaxBlock)
 {
     const int m = patch_mesh[blockIdx.x];
     const BatchDesc &d = desc[m];
-    patch_body<FORM, DIM, K, VJP, LPC>(d.args, (int64_t)blockIdx.x - d.first_patch, P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM>(d.args, (int64_t)blockIdx.x - d.first_patch, P);
 }
 
 // Shared-node sums of many meshes: thread i sums shared node i - fix[m].first of the mesh m
@@ -273,14 +309,15 @@ __global__ void batch_fixup_kernel(const FixDesc *__restrict__ fix, int n_mesh, 
     const int64_t nd = f.fix_node[k];
     const int o0 = f.fix_off[k], o1 = f.fix_off[k + 1];
     double s = 0.0;
-    for (int o = o0; o < o1; ++o) s += f.partial[(int64_t)o * f.ncomp + c];
+    for (int o = o0; o < o1; ++o) s += f.partial[(int64_t)f.fix_slot[o] * f.ncomp + c];
     f.y[nd * f.ncomp + c] = s;
 }
 
-// thread i sums component i % ncomp of shared node i / ncomp over its partials, in patch order
+// thread i sums component i % ncomp of shared node i / ncomp over its partials (slots
+// listed in patch order)
 __global__ void fixup_kernel(const int32_t *__restrict__ fix_node, const int32_t *__restrict__ fix_off,
-                             int64_t n, const double *__restrict__ partial, int ncomp,
-                             double *__restrict__ y)
+                             const int32_t *__restrict__ fix_slot, int64_t n,
+                             const double *__restrict__ partial, int ncomp, double *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * ncomp) return;
@@ -289,7 +326,7 @@ __global__ void fixup_kernel(const int32_t *__restrict__ fix_node, const int32_t
     const int64_t nd = fix_node[k];
     const int o0 = fix_off[k], o1 = fix_off[k + 1];
     double s = 0.0;
-    for (int o = o0; o < o1; ++o) s += partial[(int64_t)o * ncomp + c];
+    for (int o = o0; o < o1; ++o) s += partial[(int64_t)fix_slot[o] * ncomp + c];
     y[nd * ncomp + c] = s;
 }
 
@@ -309,25 +346,27 @@ using BatchFn = void (*)(const BatchDesc *, const int32_t *, int);
 
 struct Kernels {
     ColourFn colour;
-    PatchFn patch[4];     // by lanes per cell (index 1..3), null where the split is absent
-    BatchFn batch[4];
+    PatchFn patch[4][3];  // [lanes per cell 1..3][sum mode 1..2], null where absent
+    BatchFn batch[4][3];
 };
+
+template <int FORM, int DIM, int K, bool VJP, int LPC>
+void fill_lanes(Kernels &k)
+{
+    k.patch[LPC][SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
+    k.patch[LPC][SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+    k.batch[LPC][SUM_ELEMENT] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
+    k.batch[LPC][SUM_COLOURED] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+}
 
 template <int FORM, int DIM, int K, bool VJP>
 Kernels entry()
 {
     Kernels k{};
     k.colour = colour_kernel<FORM, DIM, K, VJP>;
-    k.patch[1] = patch_kernel<FORM, DIM, K, VJP, 1>;
-    k.batch[1] = batch_patch_kernel<FORM, DIM, K, VJP, 1>;
-    if constexpr (DIM == 2 && FORM != FEM_MASS) {
-        k.patch[2] = patch_kernel<FORM, DIM, K, VJP, 2>;
-        k.batch[2] = batch_patch_kernel<FORM, DIM, K, VJP, 2>;
-    }
-    if constexpr (DIM == 3 && FORM != FEM_MASS) {
-        k.patch[3] = patch_kernel<FORM, DIM, K, VJP, 3>;
-        k.batch[3] = batch_patch_kernel<FORM, DIM, K, VJP, 3>;
-    }
+    fill_lanes<FORM, DIM, K, VJP, 1>(k);
+    if constexpr (DIM == 2 && FORM != FEM_MASS) fill_lanes<FORM, DIM, K, VJP, 2>(k);
+    if constexpr (DIM == 3 && FORM != FEM_MASS) fill_lanes<FORM, DIM, K, VJP, 3>(k);
     return k;
 }
 
@@ -386,30 +425,37 @@ hipError_t launch_action(const fem_plan &p, const LaunchArgs &a, int block, bool
     return hipGetLastError();
 }
 
-size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes)
+// LDS region A (doubles): the staged nodal values, then the element buffer (SUM_ELEMENT)
+// or the node accumulator (SUM_COLOURED), which fits in the staging space.
+size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode)
 {
     const int nloc = nloc_of(dim, degree);
     const int nc = form == FEM_MASS ? 1 : dim;
     const size_t stage = (size_t)max_nodes * nc * (vjp ? 2 : 1);
+    if (sum_mode == SUM_COLOURED) return stage;
     const size_t elem = (size_t)patch * nloc * nc;
-    return stage > elem ? stage : elem;   // doubles
+    return stage > elem ? stage : elem;
 }
 
-size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes)
+// Region B (bytes): node ids, plus for the element buffer the relative sum offsets and slots.
+size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes,
+                       int sum_mode)
 {
     const int nloc = nloc_of(dim, degree);
-    const size_t b = 4 * (3 * (size_t)max_nodes + 1) + 2 * (size_t)patch * nloc;
-    return 8 * patch_lds_a(form, dim, degree, vjp, patch, max_nodes) + ((b + 7) & ~(size_t)7);
+    size_t b = 4 * (size_t)max_nodes;
+    if (sum_mode == SUM_ELEMENT) b += 4 * ((size_t)max_nodes + 1) + 2 * (size_t)patch * nloc;
+    return 8 * patch_lds_a(form, dim, degree, vjp, patch, max_nodes, sum_mode) +
+           ((b + 7) & ~(size_t)7);
 }
 
 bool pair_available(int form, int dim, int degree)
 {
-    return lookup(form, dim, degree, false).patch[2] != nullptr;
+    return lookup(form, dim, degree, false).patch[2][SUM_ELEMENT] != nullptr;
 }
 
 bool triple_available(int form, int dim, int degree)
 {
-    return lookup(form, dim, degree, false).patch[3] != nullptr;
+    return lookup(form, dim, degree, false).patch[3][SUM_ELEMENT] != nullptr;
 }
 
 // threads of a patch workgroup: P * lanes, or 64 per 21 cells for lane triples
@@ -430,13 +476,14 @@ hipError_t allow_lds(const void *fn, size_t lds)
     return e;
 }
 
-hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch,
+hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch, int sum_mode,
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
                               size_t lds, hipStream_t s)
 {
-    if (lanes < 1 || lanes > 3) return hipErrorInvalidConfiguration;
+    if (lanes < 1 || lanes > 3 || (sum_mode != SUM_ELEMENT && sum_mode != SUM_COLOURED))
+        return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(form, dim, degree, false);
-    BatchFn fn = ks.batch[lanes];
+    BatchFn fn = ks.batch[lanes][sum_mode];
     if (!fn) return hipErrorInvalidDeviceFunction;
     const int threads = patch_threads(patch, lanes);
     if (patch < 1 || patch > 256 || threads > kMaxBlock || lds > 160 * 1024 || n_patch > 0x7fffffff)
@@ -457,13 +504,15 @@ hipError_t launch_batch_fixup(const FixDesc *fix, int n_mesh, int64_t n, hipStre
 
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s)
 {
-    if (p.lanes < 1 || p.lanes > 3) return hipErrorInvalidConfiguration;
+    if (p.lanes < 1 || p.lanes > 3 || (p.sum_mode != SUM_ELEMENT && p.sum_mode != SUM_COLOURED))
+        return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(p.form, p.dim, p.degree, vjp);
-    PatchFn fn = ks.patch[p.lanes];
+    PatchFn fn = ks.patch[p.lanes][p.sum_mode];
     if (!fn) return hipErrorInvalidDeviceFunction;
     const int threads = patch_threads(p.patch, p.lanes);
     if (p.patch < 1 || p.patch > 256 || threads > kMaxBlock) return hipErrorInvalidConfiguration;
-    const size_t lds = patch_lds_bytes(p.form, p.dim, p.degree, vjp, p.patch, p.max_patch_nodes);
+    const size_t lds = patch_lds_bytes(p.form, p.dim, p.degree, vjp, p.patch, p.max_patch_nodes,
+                                       p.sum_mode);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
     hipError_t e = allow_lds((const void *)fn, lds);
     if (e != hipSuccess) return e;
@@ -472,13 +521,14 @@ hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t n_shared,
-                        const double *partial, int ncomp, double *y, hipStream_t s)
+hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, const int32_t *fix_slot,
+                        int64_t n_shared, const double *partial, int ncomp, double *y,
+                        hipStream_t s)
 {
     const int block = 256;
     const int64_t grid = (n_shared * ncomp + block - 1) / block;
     hipLaunchKernelGGL(fixup_kernel, dim3((unsigned)grid), dim3(block), 0, s, fix_node, fix_off,
-                       n_shared, partial, ncomp, y);
+                       fix_slot, n_shared, partial, ncomp, y);
     return hipGetLastError();
 }
 

@@ -80,7 +80,11 @@ void free_patch_memory(fem_plan *p)
     (void)hipFree(p->d_lidx);
     (void)hipFree(p->d_patch_off);
     (void)hipFree(p->d_patch_nodes);
-    (void)hipFree(p->d_patch_dest);
+    (void)hipFree(p->d_patch_nint);
+    (void)hipFree(p->d_patch_pbase);
+    (void)hipFree(p->d_patch_ncol);
+    (void)hipFree(p->d_colour);
+    (void)hipFree(p->d_fix_slot);
     (void)hipFree(p->d_csr_off);
     (void)hipFree(p->d_csr_slots);
     (void)hipFree(p->d_fix_node);
@@ -88,7 +92,10 @@ void free_patch_memory(fem_plan *p)
     (void)hipFree(p->d_partial);
     p->d_pverts = nullptr;
     p->d_lidx = nullptr;
-    p->d_patch_off = p->d_patch_nodes = p->d_patch_dest = p->d_csr_off = nullptr;
+    p->d_patch_off = p->d_patch_nodes = p->d_patch_nint = p->d_patch_pbase = p->d_csr_off = nullptr;
+    p->d_patch_ncol = nullptr;
+    p->d_colour = nullptr;
+    p->d_fix_slot = nullptr;
     p->d_csr_slots = nullptr;
     p->d_fix_node = p->d_fix_off = nullptr;
     p->d_partial = nullptr;
@@ -146,6 +153,7 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
                    const int32_t *cell_nodes, int P);
 int default_patch(const fem_plan *p);
 int default_lanes(const fem_plan *p);
+int default_sum_mode(const fem_plan *p);
 
 // Host-side validation of the mesh; runs before any HIP call.
 void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
@@ -237,6 +245,7 @@ void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
     p->d_tab = device_upload(tab, "tables");
     p->d_untouched = device_upload(untouched, "untouched nodes");
     p->lanes = default_lanes(p);
+    p->sum_mode = default_sum_mode(p);
     if (p->n_cell > 0) build_patches(p, coords, cell_verts, cell_nodes, default_patch(p));
     else p->strategy = femx::STRAT_COLOUR;
 }
@@ -295,15 +304,25 @@ std::vector<int64_t> morton_order(const fem_plan *p, const double *coords, const
     return order;
 }
 
-// Patch strategy data: cells along the Morton curve cut into patches of P cells; per patch
-// its distinct nodes (ascending id), the local index of every (cell, a), and for every
-// distinct node the element-buffer slots it sums, in ascending (local cell, a).
+// Patch strategy data: cells along the Morton curve cut into patches of P cells.  Per patch
+// its distinct nodes -- first those no other patch holds (interior, ascending id), then the
+// shared ones (ascending id) -- and per cell the patch-local index of each of its nodes.
+// A shared node's sum leaves the patch as a partial in a slot of the patch's contiguous
+// partial range (base + position among the patch's shared nodes); the fixup kernel adds a
+// node's partials in patch order.
+// Two ways to sum inside a patch:
+//   element buffer: every cell vector goes to LDS and each node sums its slots (the CSR
+//     lists below, in ascending (cell, local node));
+//   coloured: cells are greedily coloured inside the patch (conflict = a shared node) and
+//     accumulate into one LDS node buffer colour by colour, barriers in between.
 struct PatchLayout {
-    int P = 0, max_nodes = 0;
+    int P = 0, max_nodes = 0, max_colours = 0;
     int64_t n_patch = 0, stride = 0;
     std::vector<int64_t> order;
-    std::vector<int32_t> pverts, patch_off, patch_nodes, patch_dest, csr_off, fix_node, fix_off;
+    std::vector<int32_t> pverts, patch_off, patch_nodes, patch_nint, patch_pbase, csr_off;
+    std::vector<int32_t> fix_node, fix_off, fix_slot;
     std::vector<uint16_t> lidx, csr_slots;
+    std::vector<uint8_t> colour, patch_ncol;
 };
 
 PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int32_t *cell_verts,
@@ -318,68 +337,117 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
     L.order = morton_order(p, coords, cell_verts);
     L.n_patch = (p->n_cell + P - 1) / P;
     L.stride = std::max<int64_t>(P, L.n_patch * P);
+    // pass 1: how many patches hold each node
+    std::vector<int32_t> node_count((size_t)p->n_node, 0);
+    std::vector<int32_t> nodes;
+    for (int64_t pt = 0; pt < L.n_patch; ++pt) {
+        const int64_t c0 = pt * P, c1 = std::min<int64_t>(p->n_cell, c0 + P);
+        nodes.clear();
+        for (int64_t s = c0; s < c1; ++s)
+            for (int a = 0; a < nloc; ++a) nodes.push_back(cell_nodes[L.order[s] * nloc + a]);
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        for (int32_t nd : nodes) node_count[nd]++;
+    }
+    // shared nodes: partial ranges in patch order
+    std::vector<int32_t> fix_index((size_t)p->n_node, -1);
+    L.fix_off.assign(1, 0);
+    for (int64_t n = 0; n < p->n_node; ++n)
+        if (node_count[n] > 1) {
+            fix_index[n] = (int32_t)L.fix_node.size();
+            L.fix_node.push_back((int32_t)n);
+            L.fix_off.push_back(L.fix_off.back() + node_count[n]);
+        }
+    L.fix_slot.assign((size_t)L.fix_off.back(), -1);
+    std::vector<int32_t> fix_fill(L.fix_node.size(), 0);
+
+    // pass 2: per patch node order, local indices, CSR, sub-colours
     L.pverts.assign((size_t)nv * L.stride, 0);
     L.lidx.assign((size_t)nloc * L.stride, 0);
+    L.colour.assign((size_t)L.stride, 0);
     L.patch_off.assign((size_t)L.n_patch + 1, 0);
+    L.patch_nint.assign((size_t)L.n_patch, 0);
+    L.patch_pbase.assign((size_t)L.n_patch, 0);
+    L.patch_ncol.assign((size_t)L.n_patch, 0);
     L.csr_off.assign(1, 0);
     L.patch_nodes.reserve((size_t)(p->n_cell * nloc / 2 + 16));
     L.csr_slots.reserve((size_t)(p->n_cell * nloc));
-    std::vector<int32_t> node_count((size_t)p->n_node, 0);
-    std::vector<std::pair<int64_t, int32_t>> pairs;   // ((node*P + cl)*nloc + a, slot = a<<8 | cl)
+    std::vector<std::pair<int64_t, int32_t>> pairs;   // ((rank*P + cl)*nloc + a, slot)
+    std::vector<uint64_t> used;                        // colours held per local node
+    int32_t pbase = 0;
     for (int64_t pt = 0; pt < L.n_patch; ++pt) {
         const int64_t c0 = pt * P, c1 = std::min<int64_t>(p->n_cell, c0 + P);
+        nodes.clear();
+        for (int64_t s = c0; s < c1; ++s)
+            for (int a = 0; a < nloc; ++a) nodes.push_back(cell_nodes[L.order[s] * nloc + a]);
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        // interior nodes first, then shared, each ascending
+        std::stable_partition(nodes.begin(), nodes.end(),
+                              [&](int32_t nd) { return node_count[nd] == 1; });
+        int nint = 0;
+        while (nint < (int)nodes.size() && node_count[nodes[nint]] == 1) ++nint;
+        const int U = (int)nodes.size();
+        L.patch_nint[pt] = nint;
+        L.patch_pbase[pt] = pbase;
+        for (int j = nint; j < U; ++j) {
+            const int32_t k = fix_index[nodes[j]];
+            L.fix_slot[L.fix_off[k] + fix_fill[k]++] = pbase + (j - nint);
+        }
+        pbase += U - nint;
+        // local index of every (cell, a)
+        auto local = [&](int32_t nd) -> int {
+            // nodes is sorted within its two groups
+            auto lo = node_count[nd] == 1 ? nodes.begin() : nodes.begin() + nint;
+            auto hi = node_count[nd] == 1 ? nodes.begin() + nint : nodes.end();
+            return (int)(std::lower_bound(lo, hi, nd) - nodes.begin());
+        };
         pairs.clear();
+        used.assign((size_t)U, 0);
+        int ncol = 0;
         for (int64_t s = c0; s < c1; ++s) {
             const int64_t c = L.order[s];
             const int cl = (int)(s - c0);
             for (int j = 0; j < nv; ++j) L.pverts[(size_t)j * L.stride + s] = cell_verts[c * nv + j];
+            uint64_t forbid = 0;
+            int lids[256];
             for (int a = 0; a < nloc; ++a) {
-                const int64_t nd = cell_nodes[c * nloc + a];
-                pairs.push_back({(nd * P + cl) * nloc + a, (a << 8) | cl});
+                const int l = local(cell_nodes[c * nloc + a]);
+                lids[a] = l;
+                L.lidx[(size_t)a * L.stride + s] = (uint16_t)l;
+                forbid |= used[l];
+                pairs.push_back({((int64_t)l * P + cl) * nloc + a, (a << 8) | cl});
             }
+            if (forbid == ~uint64_t(0)) throw Error(FEM_E_UNSUPPORTED, "a patch needs more than 64 colours");
+            const int col = __builtin_ctzll(~forbid);
+            L.colour[s] = (uint8_t)col;
+            ncol = std::max(ncol, col + 1);
+            for (int a = 0; a < nloc; ++a) used[lids[a]] |= uint64_t(1) << col;
         }
+        L.patch_ncol[pt] = (uint8_t)ncol;
+        L.max_colours = std::max(L.max_colours, ncol);
         std::sort(pairs.begin(), pairs.end());
-        int U = 0;
-        int64_t prev = -1;
-        for (const auto &pr : pairs) {
-            const int64_t nd = pr.first / ((int64_t)P * nloc);
-            const int rem = (int)(pr.first % ((int64_t)P * nloc));
-            const int cl = rem / nloc, a = rem % nloc;
-            if (nd != prev) {
-                if (prev >= 0) L.csr_off.push_back((int32_t)L.csr_slots.size());
-                L.patch_nodes.push_back((int32_t)nd);
-                node_count[nd]++;
-                prev = nd;
-                ++U;
+        for (int j = 0; j < U; ++j) L.patch_nodes.push_back(nodes[j]);
+        size_t k = 0;
+        for (int j = 0; j < U; ++j) {
+            while (k < pairs.size() && pairs[k].first / ((int64_t)P * nloc) == j) {
+                L.csr_slots.push_back((uint16_t)pairs[k].second);
+                ++k;
             }
-            L.lidx[(size_t)a * L.stride + c0 + cl] = (uint16_t)(U - 1);
-            L.csr_slots.push_back((uint16_t)pr.second);
+            L.csr_off.push_back((int32_t)L.csr_slots.size());
         }
-        if (prev >= 0) L.csr_off.push_back((int32_t)L.csr_slots.size());
         L.patch_off[pt + 1] = (int32_t)L.patch_nodes.size();
         L.max_nodes = std::max(L.max_nodes, U);
-    }
-    // nodes held by several patches sum through partial slots, in patch order
-    std::vector<int32_t> fix_base((size_t)p->n_node, -1), rank((size_t)p->n_node, 0);
-    L.fix_off.assign(1, 0);
-    for (int64_t n = 0; n < p->n_node; ++n)
-        if (node_count[n] > 1) {
-            fix_base[n] = L.fix_off.back();
-            L.fix_node.push_back((int32_t)n);
-            L.fix_off.push_back(L.fix_off.back() + node_count[n]);
-        }
-    L.patch_dest.assign(L.patch_nodes.size(), -1);
-    for (size_t j = 0; j < L.patch_nodes.size(); ++j) {
-        const int32_t nd = L.patch_nodes[j];
-        if (fix_base[nd] >= 0) L.patch_dest[j] = fix_base[nd] + rank[nd]++;
     }
     return L;
 }
 
 // Check every index the patch and fixup kernels will follow, on the host: each (cell, a)
 // slot is summed exactly once, into the node the map gives it; every local index points at
-// its node; every partial slot is written once and read by its node's fixup; all indices
-// fall inside their buffers.  Throws on the first violation.
+// its node; interior nodes are held by one patch only; every partial slot is written by
+// exactly one (patch, node) and read by that node's fixup; sub-colours separate every two
+// cells of a patch that share a node; all indices fall inside their buffers.  Throws on
+// the first violation.
 void validate_patch_layout(const fem_plan *p, const PatchLayout &L, const int32_t *cell_nodes)
 {
     using femx::Error;
@@ -389,44 +457,71 @@ void validate_patch_layout(const fem_plan *p, const PatchLayout &L, const int32_
     if (L.csr_off.size() != L.patch_nodes.size() + 1) bad("csr offsets size");
     if ((int64_t)L.csr_slots.size() != p->n_cell * nloc) bad("slot count");
     std::vector<uint8_t> slot_seen((size_t)L.n_patch * P * nloc, 0);
-    std::vector<int32_t> partial_writes((size_t)L.fix_off.back(), 0);
+    std::vector<int32_t> partial_writer((size_t)L.fix_off.back(), -1);
+    std::vector<int32_t> holders((size_t)p->n_node, 0);
     for (int64_t pt = 0; pt < L.n_patch; ++pt) {
-        const int nb = L.patch_off[pt], U = L.patch_off[pt + 1] - nb;
-        if (U < 0 || U > L.max_nodes) bad("node count");
-        const int64_t c0 = pt * P;
+        const int nb = L.patch_off[pt], U = L.patch_off[pt + 1] - nb, nint = L.patch_nint[pt];
+        if (U < 0 || U > L.max_nodes || nint < 0 || nint > U) bad("node counts");
+        const int64_t c0 = pt * P, c1 = std::min<int64_t>(p->n_cell, c0 + P);
         for (int j = 0; j < U; ++j) {
             const int32_t nd = L.patch_nodes[nb + j];
             if (nd < 0 || nd >= p->n_node) bad("node id");
-            if (j > 0 && L.patch_nodes[nb + j - 1] >= nd) bad("node order");
+            holders[nd]++;
             const int e0 = L.csr_off[nb + j], e1 = L.csr_off[nb + j + 1];
             if (e0 < 0 || e1 < e0 || e1 > (int)L.csr_slots.size()) bad("csr range");
             for (int e = e0; e < e1; ++e) {
                 const int sl = L.csr_slots[e], a = sl >> 8, cl = sl & 255;
                 if (a >= nloc || cl >= P) bad("slot index");
                 const int64_t s = c0 + cl;
-                if (s >= p->n_cell) bad("slot of an absent cell");
+                if (s >= c1) bad("slot of an absent cell");
                 if (cell_nodes[L.order[s] * nloc + a] != nd) bad("slot sums into the wrong node");
                 if (L.lidx[(size_t)a * L.stride + s] != j) bad("local index");
                 uint8_t &seen = slot_seen[(size_t)(pt * P + cl) * nloc + a];
                 if (seen) bad("slot summed twice");
                 seen = 1;
             }
-            const int dest = L.patch_dest[nb + j];
-            if (dest >= 0) {
-                if (dest >= (int)partial_writes.size()) bad("partial slot range");
-                partial_writes[dest]++;
-                const auto it = std::lower_bound(L.fix_node.begin(), L.fix_node.end(), nd);
-                if (it == L.fix_node.end() || *it != nd) bad("partial of an unshared node");
-                const size_t k = it - L.fix_node.begin();
-                if (dest < L.fix_off[k] || dest >= L.fix_off[k + 1]) bad("partial outside its node");
+            if (j >= nint) {
+                const int64_t dest = (int64_t)L.patch_pbase[pt] + (j - nint);
+                if (dest >= (int64_t)partial_writer.size()) bad("partial slot range");
+                if (partial_writer[dest] >= 0) bad("partial slot written twice");
+                partial_writer[dest] = nd;
             }
         }
+        // sub-colours: no node twice within a colour of the patch
+        std::vector<uint64_t> held((size_t)U, 0);
+        for (int64_t s = c0; s < c1; ++s) {
+            const int col = L.colour[s];
+            if (col >= L.patch_ncol[pt]) bad("colour beyond the patch's count");
+            for (int a = 0; a < nloc; ++a) {
+                const int l = L.lidx[(size_t)a * L.stride + s];
+                if (l >= U) bad("local index range");
+                if ((held[l] >> col) & 1) bad("two cells of one colour share a node");
+            }
+            for (int a = 0; a < nloc; ++a) held[L.lidx[(size_t)a * L.stride + s]] |= uint64_t(1) << col;
+        }
+        for (int j = 0; j < nint; ++j)
+            if (j > 0 && L.patch_nodes[nb + j - 1] >= L.patch_nodes[nb + j]) bad("interior order");
     }
     for (int64_t s = 0; s < p->n_cell; ++s)
         for (int a = 0; a < nloc; ++a)
             if (!slot_seen[(size_t)s * nloc + a]) bad("slot never summed");
-    for (int32_t w : partial_writes)
-        if (w != 1) bad("partial written " + std::to_string(w) + " times");
+    // every node with several holders is a fixup node whose slots are exactly its writers
+    for (size_t k = 0; k < L.fix_node.size(); ++k) {
+        const int32_t nd = L.fix_node[k];
+        if (holders[nd] != L.fix_off[k + 1] - L.fix_off[k]) bad("fixup count");
+        for (int o = L.fix_off[k]; o < L.fix_off[k + 1]; ++o) {
+            const int32_t sl = L.fix_slot[o];
+            if (sl < 0 || sl >= (int32_t)partial_writer.size() || partial_writer[sl] != nd)
+                bad("fixup reads a foreign partial");
+        }
+    }
+    for (int32_t w : partial_writer)
+        if (w < 0) bad("partial slot never written");
+    for (int64_t pt = 0; pt < L.n_patch; ++pt) {
+        const int nb = L.patch_off[pt];
+        for (int j = 0; j < L.patch_nint[pt]; ++j)
+            if (holders[L.patch_nodes[nb + j]] != 1) bad("interior node held twice");
+    }
 }
 
 void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
@@ -437,7 +532,7 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
     const char *chk = std::getenv("FEM_CHECK");
     if (chk && chk[0] == '1') validate_patch_layout(p, L, cell_nodes);
     const size_t lds = femx::patch_lds_bytes(p->form, p->dim, p->degree, p->form == FEM_NEOHOOKEAN,
-                                             P, L.max_nodes);
+                                             P, L.max_nodes, p->sum_mode);
     if (lds > 160 * 1024)
         throw Error(FEM_E_UNSUPPORTED, "patch of " + std::to_string(P) + " cells needs " +
                                            std::to_string(lds) + " bytes of LDS");
@@ -448,25 +543,40 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
     p->n_partial = L.fix_off.back();
     p->n_shared = (int64_t)L.fix_node.size();
     p->max_patch_nodes = L.max_nodes;
+    p->max_colours = L.max_colours;
     p->pstride = L.stride;
     p->d_pverts = device_upload(L.pverts, "patch cell_verts");
     p->d_lidx = device_upload(L.lidx, "patch local indices");
+    p->d_colour = device_upload(L.colour, "patch colours");
     p->d_patch_off = device_upload(L.patch_off, "patch offsets");
     p->d_patch_nodes = device_upload(L.patch_nodes, "patch nodes");
-    p->d_patch_dest = device_upload(L.patch_dest, "patch destinations");
+    p->d_patch_nint = device_upload(L.patch_nint, "patch interior counts");
+    p->d_patch_pbase = device_upload(L.patch_pbase, "patch partial bases");
+    p->d_patch_ncol = device_upload(L.patch_ncol, "patch colour counts");
     p->d_csr_off = device_upload(L.csr_off, "patch csr offsets");
     p->d_csr_slots = device_upload(L.csr_slots, "patch csr slots");
     p->d_fix_node = device_upload(L.fix_node, "shared nodes");
     p->d_fix_off = device_upload(L.fix_off, "shared offsets");
+    p->d_fix_slot = device_upload(L.fix_slot, "shared slots");
     if (p->n_partial > 0) {
         std::vector<double> zeros((size_t)p->n_partial * p->ncomp, 0.0);
         p->d_partial = device_upload(zeros, "partials");
     }
 }
 
+// Sub-colour phases pay one barrier and one masked pass per colour: cheap next to the
+// quadrature work of the 2D forms (about 7 colours), not next to low-degree 3D cells (about
+// 24 colours), which sum through the element buffer.
+int default_sum_mode(const fem_plan *p)
+{
+    return p->dim == 2 ? femx::SUM_COLOURED : femx::SUM_ELEMENT;
+}
+
+// One lane per cell in 2D: with coloured sums the lane-pair split no longer pays for its
+// shuffles (measured on the P4 neo-Hookean action and VJP); lane triples in 3D from P3 on,
+// where one lane's cell vector would not fit its registers.
 int default_lanes(const fem_plan *p)
 {
-    if (femx::pair_available(p->form, p->dim, p->degree)) return 2;
     if (femx::triple_available(p->form, p->dim, p->degree) && p->degree >= 3) return 3;
     return 1;
 }
@@ -481,7 +591,7 @@ bool patch_allowed(int P, int lanes)
 
 int default_patch_for(const fem_plan *p, int lanes)
 {
-    // the largest allowed patch whose element buffer fits 64 KB of LDS
+    // the largest allowed patch whose element buffer (the larger LDS need) fits 64 KB
     static const int sizes12[] = {256, 128, 64};
     static const int sizes3[] = {84, 63, 42, 21};
     const int *sz = lanes == 3 ? sizes3 : sizes12;
@@ -520,9 +630,12 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         femx::PatchArgs a{};
         a.verts = p->d_pverts;
         a.lidx = p->d_lidx;
+        a.colour = p->d_colour;
         a.patch_off = p->d_patch_off;
         a.patch_nodes = p->d_patch_nodes;
-        a.patch_dest = p->d_patch_dest;
+        a.patch_nint = p->d_patch_nint;
+        a.patch_pbase = p->d_patch_pbase;
+        a.patch_ncol = p->d_patch_ncol;
         a.csr_off = p->d_csr_off;
         a.csr_slots = p->d_csr_slots;
         a.coords = p->d_coords;
@@ -535,13 +648,13 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         a.n_cell = p->n_cell;
         a.nq = p->nq;
         a.lds_a = (int)femx::patch_lds_a(p->form, p->dim, p->degree, nl_vjp, p->patch,
-                                         p->max_patch_nodes);
+                                         p->max_patch_nodes, p->sum_mode);
         a.lam = p->lam;
         a.mu = p->mu;
         femx::check_hip(femx::launch_patch(*p, a, nl_vjp, s), "patch launch");
         if (p->n_shared > 0)
-            femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off, p->n_shared,
-                                               p->d_partial, p->ncomp, y, s),
+            femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off, p->d_fix_slot,
+                                               p->n_shared, p->d_partial, p->ncomp, y, s),
                             "fixup launch");
         return;
     }
@@ -569,32 +682,51 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
 }  // namespace
 
 namespace femx {
-void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell)
+void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell, int sum_mode)
 {
     check_plan(plan);
     if (strategy == FEM_SCATTER_COLOUR) {
-        if (patch_cells != 0 || lanes_per_cell > 1)
-            throw Error(FEM_E_ARG, "the colour strategy takes no patch size or lane split");
+        if (patch_cells != 0 || lanes_per_cell > 1 || sum_mode != 0)
+            throw Error(FEM_E_ARG, "the colour strategy takes no patch size, lane split or sum mode");
         plan->strategy = STRAT_COLOUR;
         return;
     }
     if (strategy != FEM_SCATTER_PATCH) throw Error(FEM_E_ARG, "unknown strategy");
     if (plan->n_cell == 0) throw Error(FEM_E_ARG, "empty mesh has no patches");
-    const int lanes = lanes_per_cell == 0 ? default_lanes(plan) : lanes_per_cell;
+    // with a patch size but no lane split: the default split if it allows that size, else one
+    int lanes = lanes_per_cell;
+    if (lanes == 0) {
+        lanes = default_lanes(plan);
+        if (patch_cells != 0 && !patch_allowed(patch_cells, lanes)) lanes = 1;
+    }
     if (lanes < 1 || lanes > 3) throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1, 2 or 3");
     if (lanes == 2 && !pair_available(plan->form, plan->dim, plan->degree))
         throw Error(FEM_E_UNSUPPORTED, "two lanes per cell exist for the 2D vector forms only");
     if (lanes == 3 && !triple_available(plan->form, plan->dim, plan->degree))
         throw Error(FEM_E_UNSUPPORTED, "three lanes per cell exist for the 3D vector forms only");
+    const int mode = sum_mode == 0 ? default_sum_mode(plan) : sum_mode;
+    if (mode != SUM_ELEMENT && mode != SUM_COLOURED) throw Error(FEM_E_ARG, "unknown sum mode");
     const int P = patch_cells == 0 ? default_patch_for(plan, lanes) : patch_cells;
     if (!patch_allowed(P, lanes))
         throw Error(FEM_E_ARG, "patch_cells must be 64, 128 or 256 (at most 256 lanes) for one or "
                                "two lanes per cell, and 21, 42, 63 or 84 for three");
+    const size_t lds = patch_lds_bytes(plan->form, plan->dim, plan->degree,
+                                       plan->form == FEM_NEOHOOKEAN, P,
+                                       P == plan->patch ? plan->max_patch_nodes : 0, mode);
+    if (P == plan->patch && lds > 160 * 1024)
+        throw Error(FEM_E_UNSUPPORTED, "this sum mode needs more than 160 KB of LDS");
+    const int old_mode = plan->sum_mode;
+    plan->sum_mode = mode;
     if (P != plan->patch) {
         if (plan->h_cell_verts.empty()) throw Error(FEM_E_ARG, "plan keeps no host mesh");
         check_hip(hipDeviceSynchronize(), "synchronise before rebuilding patches");
-        build_patches(plan, plan->h_coords.data(), plan->h_cell_verts.data(),
-                      plan->h_cell_nodes.data(), P);
+        try {
+            build_patches(plan, plan->h_coords.data(), plan->h_cell_verts.data(),
+                          plan->h_cell_nodes.data(), P);
+        } catch (...) {
+            plan->sum_mode = old_mode;
+            throw;
+        }
     }
     plan->lanes = lanes;
     plan->strategy = STRAT_PATCH;
@@ -773,6 +905,7 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
         const double lm[2] = {1.0, 1.0};
         validate_mesh(&p, coords, cell_verts, cell_nodes, lm, 2);
         p.lanes = default_lanes(&p);
+        p.sum_mode = default_sum_mode(&p);
         const int P = patch_cells == 0 ? default_patch(&p) : patch_cells;
         PatchLayout L = make_patch_layout(&p, coords, cell_verts, cell_nodes, P);
         validate_patch_layout(&p, L, cell_nodes);
@@ -784,7 +917,8 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
             stats[4] = (int64_t)L.fix_node.size();
             stats[5] = L.fix_off.back();
             stats[6] = (int64_t)femx::patch_lds_bytes(form, dim, degree, form == FEM_NEOHOOKEAN, P,
-                                                      L.max_nodes);
+                                                      L.max_nodes, p.sum_mode);
+            stats[7] = L.max_colours;
         }
     });
 }
@@ -804,9 +938,10 @@ int fem_plan_set_quadrature(fem_plan *plan, int family)
     });
 }
 
-int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell)
+int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell,
+                          int sum_mode)
 {
-    return guarded([&] { femx::set_strategy(plan, strategy, patch_cells, lanes_per_cell); });
+    return guarded([&] { femx::set_strategy(plan, strategy, patch_cells, lanes_per_cell, sum_mode); });
 }
 
 int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vjp,
@@ -824,7 +959,7 @@ int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vj
 }
 
 int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
-                          int *lanes_per_cell)
+                          int *lanes_per_cell, int *sum_mode)
 {
     return guarded([&] {
         check_plan(plan);
@@ -832,6 +967,7 @@ int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
         if (strategy) *strategy = patch ? FEM_SCATTER_PATCH : FEM_SCATTER_COLOUR;
         if (patch_cells) *patch_cells = patch ? plan->patch : 0;
         if (lanes_per_cell) *lanes_per_cell = patch ? plan->lanes : 1;
+        if (sum_mode) *sum_mode = patch ? plan->sum_mode : 0;
     });
 }
 

@@ -2,7 +2,8 @@
 //
 // Candidates: the colour strategy with 64/128/256 cells per workgroup, and the patch
 // strategy with 64/128/256 cells per patch and one lane per cell, 64/128 with two lanes
-// (2D vector forms), 42/63/84 with three lanes (3D vector forms).  Each candidate is
+// (2D vector forms), 42/63/84 with three lanes (3D vector forms), each with both ways of
+// summing inside a patch.  Each candidate is
 // timed with HIP events on the caller's stream using the paper's protocol (Sec. 6.2.1): five warm-up runs, then timed runs until 15 have been collected
 // or 0.2 s has accumulated, the arithmetic mean being the candidate's time.  Results can
 // be kept in a small JSON cache keyed by device architecture, form, dimension, degree,
@@ -24,7 +25,7 @@
 namespace {
 
 struct Candidate {
-    int strategy, patch, lanes, block;
+    int strategy, patch, lanes, block, sum_mode;
 };
 
 std::string arch_name()
@@ -47,7 +48,8 @@ std::string cache_key(const fem_plan *p)
     return k.str();
 }
 
-// The cache file: one JSON object whose values are [strategy, patch, lanes, block, ms].
+// The cache file: one JSON object whose values are [strategy, patch, lanes, block, sum mode,
+// ms].
 std::map<std::string, std::vector<double>> read_cache(const std::string &path)
 {
     std::map<std::string, std::vector<double>> out;
@@ -67,7 +69,7 @@ std::map<std::string, std::vector<double>> read_cache(const std::string &path)
         std::stringstream vs(s.substr(lb + 1, rb - lb - 1));
         std::string tok;
         while (std::getline(vs, tok, ',')) vals.push_back(std::atof(tok.c_str()));
-        if (vals.size() == 5) out[key] = vals;
+        if (vals.size() == 6) out[key] = vals;
         i = rb + 1;
     }
     return out;
@@ -83,8 +85,9 @@ void write_cache(const std::string &path, const std::map<std::string, std::vecto
         size_t n = 0;
         for (const auto &kv : c) {
             f << "  \"" << kv.first << "\": [" << (int)kv.second[0] << ", " << (int)kv.second[1]
-              << ", " << (int)kv.second[2] << ", " << (int)kv.second[3] << ", " << kv.second[4]
-              << "]" << (++n < c.size() ? "," : "") << "\n";
+              << ", " << (int)kv.second[2] << ", " << (int)kv.second[3] << ", "
+              << (int)kv.second[4] << ", " << kv.second[5] << "]" << (++n < c.size() ? "," : "")
+              << "\n";
         }
         f << "}\n";
     }
@@ -95,10 +98,10 @@ void write_cache(const std::string &path, const std::map<std::string, std::vecto
 void apply(fem_plan *p, const Candidate &c)
 {
     if (c.strategy == FEM_SCATTER_COLOUR) {
-        femx::set_strategy(p, FEM_SCATTER_COLOUR, 0, 0);
+        femx::set_strategy(p, FEM_SCATTER_COLOUR, 0, 0, 0);
         p->block = c.block;
     } else {
-        femx::set_strategy(p, FEM_SCATTER_PATCH, c.patch, c.lanes);
+        femx::set_strategy(p, FEM_SCATTER_PATCH, c.patch, c.lanes, c.sum_mode);
     }
 }
 
@@ -146,7 +149,7 @@ void apply_tuning_cache(fem_plan *p)
     const auto it = cache.find(cache_key(p));
     if (it == cache.end()) return;
     const auto &v = it->second;
-    Candidate c{(int)v[0], (int)v[1], (int)v[2], (int)v[3]};
+    Candidate c{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4]};
     try {
         apply(p, c);
     } catch (const Error &) {
@@ -158,12 +161,18 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
          hipStream_t s, double *results, int max_results, int *n_results)
 {
     std::vector<Candidate> cands;
-    for (int blk : {64, 128, 256}) cands.push_back({FEM_SCATTER_COLOUR, 0, 1, blk});
-    for (int P : {64, 128, 256}) cands.push_back({FEM_SCATTER_PATCH, P, 1, 0});
+    for (int blk : {64, 128, 256}) cands.push_back({FEM_SCATTER_COLOUR, 0, 1, blk, 0});
+    // patch sizes grouped so that one layout build serves both sum modes
+    for (int P : {64, 128, 256})
+        for (int m : {SUM_ELEMENT, SUM_COLOURED}) cands.push_back({FEM_SCATTER_PATCH, P, 1, 0, m});
     if (pair_available(p->form, p->dim, p->degree))
-        for (int P : {64, 128}) cands.push_back({FEM_SCATTER_PATCH, P, 2, 0});
+        for (int P : {64, 128})
+            for (int m : {SUM_ELEMENT, SUM_COLOURED})
+                cands.push_back({FEM_SCATTER_PATCH, P, 2, 0, m});
     if (triple_available(p->form, p->dim, p->degree))
-        for (int P : {42, 63, 84}) cands.push_back({FEM_SCATTER_PATCH, P, 3, 0});
+        for (int P : {42, 63, 84})
+            for (int m : {SUM_ELEMENT, SUM_COLOURED})
+                cands.push_back({FEM_SCATTER_PATCH, P, 3, 0, m});
     double best = 1e300;
     Candidate best_c = cands[0];
     int nres = 0;
@@ -177,12 +186,13 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
             continue;   // e.g. a patch that needs more LDS than a workgroup has
         }
         if (results && nres < max_results) {
-            double *r = results + 5 * nres;
+            double *r = results + 6 * nres;
             r[0] = c.strategy;
             r[1] = c.patch;
             r[2] = c.lanes;
             r[3] = c.block;
-            r[4] = ms;
+            r[4] = c.sum_mode;
+            r[5] = ms;
         }
         ++nres;
         if (ms < best) {
@@ -195,7 +205,7 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
     if (cache && *cache) {
         auto c = read_cache(cache);
         c[cache_key(p)] = {(double)best_c.strategy, (double)best_c.patch, (double)best_c.lanes,
-                           (double)best_c.block, best};
+                           (double)best_c.block, (double)best_c.sum_mode, best};
         write_cache(cache, c);
     }
     return FEM_OK;

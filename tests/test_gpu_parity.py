@@ -67,9 +67,10 @@ CASES = [(f, 2, k) for f in (0, 1, 2) for k in range(1, 7)] + \
         [(f, 3, k) for f in (0, 1, 2) for k in range(1, 5)]
 
 
-STRATS = [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 64, 1), (fx.SCATTER_COLOUR, 0, 0),
-          (fx.SCATTER_PATCH, 42, 3)]
-STRAT_IDS = ["patch", "patch64x1", "colour", "patch42x3"]
+STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_ELEMENT),
+          (fx.SCATTER_PATCH, 128, 1, fx.SUM_COLOURED), (fx.SCATTER_COLOUR, 0, 0, 0),
+          (fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 63, 3, fx.SUM_COLOURED)]
+STRAT_IDS = ["patch", "patch64x1e", "patch128x1c", "colour", "patch42x3e", "patch63x3c"]
 
 
 def apply_strategy(plan, strategy, form, dim):
@@ -270,9 +271,11 @@ def test_tuner_picks_a_candidate_and_keeps_parity(tmp_path):
     cache = tmp_path / "tune.json"
     res = plan.tune(u, cache_path=str(cache))
     assert len(res) >= 6
-    best = min(res, key=lambda r: r[4])
-    st, pc, ln = plan.strategy()
+    best = min(res, key=lambda r: r[5])
+    st, pc, ln, sm = plan.strategy()
     assert st == int(best[0])
+    if st == fx.SCATTER_PATCH:
+        assert (pc, ln, sm) == (int(best[1]), int(best[2]), int(best[4]))
     y = plan.action(u).cpu().numpy()
     ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
     assert rel_err(y, ref)[0] < TOL
