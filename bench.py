@@ -68,23 +68,37 @@ def footprint_bytes(dim, n_vert, n_cell, nloc, n_dof, vectors=2) -> float:
 
 # ----------------------------------------------------------------------- timing
 def time_steps(fn, steps: int, warmup: int):
+    """Mean milliseconds per step over `steps` back-to-back steps: one pair of HIP events
+    brackets the whole run on the current stream (per-step events would put their own
+    packets and gaps between the steps).  Also returns the host wall time of the run."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for i in range(steps):
-        starts[i].record(stream)
+    start.record(stream)
+    for _ in range(steps):
         fn()
-        ends[i].record(stream)
+    end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-    return ms, wall
+    return start.elapsed_time(end) / steps, wall
+
+
+def time_kernel(plan, fn, steps: int):
+    """Mean duration of the plan's main kernel (the patch kernel, without the shared-node
+    fixup), from HIP events the library records around that launch on the same stream."""
+    import torch
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms, n = plan.timing()
+    plan.set_timing(False)
+    return ms / max(n, 1)
 
 
 def kernel_source_hash() -> str:
@@ -97,9 +111,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(workload: str):
+def recorded_traffic(workload: str, kernel: str):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json), or None
-    when the kernel sources changed since they were taken."""
+    when the kernel sources changed since they were taken or another kernel ran."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -109,6 +123,8 @@ def recorded_traffic(workload: str):
     if rec.get("kernel_source_sha256") != kernel_source_hash() or workload not in rec:
         return None
     r = rec[workload]
+    if r.get("kernel") != kernel:
+        return None
     return r["fetch_kib"] * 1024 * r["fetch_scale"] + r["write_kib"] * 1024 * r["write_scale"]
 
 
@@ -170,6 +186,9 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
         del flush
     else:
         ms, wall = time_steps(fn, steps, warmup)
+        ms = np.array([ms])
+    kernel_ms = time_kernel(plan, fn, steps)
+    st = plan.strategy()
     nv = w.mesh.n_vert
     if vjp and w.form == 2:
         fl = vjp_flops_per_cell(w.mesh.dim, plan.n_loc, plan.n_quad)
@@ -180,14 +199,18 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
                 flops_per_cell=fl, flops=fl * w.mesh.n_cell,
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
                                       3 if vjp and w.form == 2 else 2),
-                ms_mean=float(ms.mean()), ms_median=float(np.median(ms)), ms_min=float(ms.min()),
-                wall_s=wall)
+                ms_mean=float(ms.mean()), kernel_ms=kernel_ms, wall_s=wall,
+                launch={"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
+                        "lanes_per_cell": st[2],
+                        "sum_mode": {1: "element", 2: "coloured"}.get(st[3], "-")})
     t = info["ms_mean"] / 1e3
     info["dof_per_s"] = w.n_dof / t
     info["tflops"] = info["flops"] / t / 1e12
     info["hbm_gbs_footprint"] = info["bytes"] / t / 1e9
     info["hbm_frac_footprint"] = info["hbm_gbs_footprint"] / HBM_PEAK_GBS
     info["fp64_frac"] = info["tflops"] / FP64_PEAK_TFLOPS
+    info["kernel_tflops"] = info["flops"] / (kernel_ms / 1e3) / 1e12
+    info["kernel_hbm_frac_footprint"] = info["bytes"] / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS
     del plan
     return info, w
 
@@ -231,7 +254,7 @@ def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
     alone = []
     for p, u, y in zip(plans, us, ys):
         m, _ = time_steps(lambda p=p, u=u, y=y: p.action(u, out=y), max(5, steps // 3), 2)
-        alone.append(float(m.mean()))
+        alone.append(m)
     batch = fx.Batch(plans, us, ys)
     ms_graph, _ = time_steps(lambda: batch.run(graph=True), steps, warmup)
     ms_eager, _ = time_steps(lambda: batch.run(graph=False), steps, warmup)
@@ -239,9 +262,9 @@ def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
     n_cell = sum(w.mesh.n_cell for w in ws)
     out = dict(n_mesh=len(ws), n_cell=n_cell, n_dof=n_dof, groups=batch.n_groups, tuned=tuned,
                patches=batch.n_patches,
-               per_mesh_loop_ms=float(ms_each.mean()), sum_of_alone_ms=float(np.sum(alone)),
-               batch_graph_ms=float(ms_graph.mean()), batch_eager_ms=float(ms_eager.mean()),
-               dof_per_s=n_dof / (ms_graph.mean() / 1e3))
+               per_mesh_loop_ms=ms_each, sum_of_alone_ms=float(np.sum(alone)),
+               batch_graph_ms=ms_graph, batch_eager_ms=ms_eager,
+               dof_per_s=n_dof / (ms_graph / 1e3))
     out["speedup_vs_per_mesh"] = out["per_mesh_loop_ms"] / out["batch_graph_ms"]
     batch.close()
     return out
@@ -326,7 +349,14 @@ def main():
         extras["batch"] = run_batch(args.steps, args.warmup, tune=tune)
         note(f"batch: {extras['batch']}")
 
-    achieved = main_info["tflops"]
+    # the dominant kernel alone (its own HIP-event duration); the step adds the fixup
+    achieved = main_info["kernel_tflops"]
+    lanes, mode = main_info["launch"]["lanes_per_cell"], main_info["launch"]["sum_mode"]
+    if main_info["launch"]["strategy"] == "patch":
+        kname = (f"patch_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {lanes}, "
+                 f"{ {'element': 1, 'coloured': 2}.get(mode, 0) }>")
+    else:
+        kname = f"colour_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false>"
     out = {
         "metric": "FP64 FE action DoF/s",
         "value": main_info["dof_per_s"],
@@ -342,13 +372,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_cell": main_info["n_cell"],
                    "n_dof": main_info["n_dof"], "n_quad": main_info["n_quad"],
-                   "launch": main_info["tuned"]},
+                   "launch": main_info["launch"], "tuner": main_info["tuned"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": recorded_traffic(args.workload),
-                     "kernel": "patch_kernel (neo-Hookean, 2D, P4) + fixup_kernel",
+                     "traffic": recorded_traffic(args.workload, kname),
+                     "kernel": kname,
                      "flops_per_launch": main_info["flops"],
+                     "avg_kernel_ms": main_info["kernel_ms"],
                      "avg_step_ms": main_info["ms_mean"],
+                     "step_tflops": main_info["tflops"],
                      "footprint_gbs": main_info["hbm_gbs_footprint"]},
         "extras": extras,
     }

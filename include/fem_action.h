@@ -179,9 +179,10 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *                   cells greedily coloured inside the patch accumulate into an LDS node
  *                   buffer colour by colour (smaller LDS, one barrier per colour).
  *   0 for lanes_per_cell, patch_cells or sum_mode picks the plan's default (three lanes
- *   for 3D vector forms of degree >= 3 when the patch size allows it, one otherwise; the
- *   largest patch whose element buffer fits 64 KB; coloured sums in 2D, element buffer in
- *   3D).
+ *   for 3D vector forms of degree >= 3 when the patch size allows it, one otherwise;
+ *   coloured sums in 2D and in 3D from degree 3 on, the element buffer for P1/P2
+ *   tetrahedra; 42 cells for lane triples with coloured sums, else the largest patch whose
+ *   element buffer fits 64 KB).
  * Rebuilding patches synchronises the device.  Errors: FEM_E_ARG, FEM_E_UNSUPPORTED (a lane
  * split the form lacks, or more than 160 KB of LDS), FEM_E_HIP, FEM_E_NOMEM.
  */
@@ -193,6 +194,18 @@ int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lan
                           int sum_mode);
 int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
                           int *lanes_per_cell, int *sum_mode);
+
+/*
+ * Kernel timing, a measurement aid.  With timing on, every fem_action / fem_action_vjp
+ * call on the plan brackets its main kernel launches (the patch kernel, or the run of
+ * colour launches) with a pair of HIP events on the caller's stream; the shared-node fixup
+ * and the zeroing of untouched nodes fall outside the bracket.  fem_plan_get_timing waits
+ * for the recorded events and returns the summed milliseconds and the number of bracketed
+ * calls since timing was last switched on or off (either resets both).  The events are the
+ * plan's and are destroyed with it.  Errors: FEM_E_ARG, FEM_E_HIP.
+ */
+int fem_plan_set_timing(fem_plan *plan, int enable);
+int fem_plan_get_timing(fem_plan *plan, double *kernel_ms, int64_t *calls);
 
 /*
  * Autotuner: time every launch configuration of the plan on the caller's vectors and keep

@@ -72,6 +72,10 @@ def lib() -> ctypes.CDLL:
     L.fem_reference_tables.restype = i32
     L.fem_plan_set_block.argtypes = [P, i32]
     L.fem_plan_set_block.restype = i32
+    L.fem_plan_set_timing.argtypes = [P, i32]
+    L.fem_plan_set_timing.restype = i32
+    L.fem_plan_get_timing.argtypes = [P, P, P]
+    L.fem_plan_get_timing.restype = i32
     L.fem_plan_set_strategy.argtypes = [P, i32, i32, i32, i32]
     L.fem_plan_set_strategy.restype = i32
     L.fem_plan_get_strategy.argtypes = [P, P, P, P, P]
@@ -236,6 +240,16 @@ class Plan:
                      sum_mode: int = 0):
         _check(lib().fem_plan_set_strategy(self.handle, strategy, patch_cells, lanes_per_cell,
                                            sum_mode))
+
+    def set_timing(self, enable: bool = True):
+        """Bracket the main kernel of every later call with HIP events (resets totals)."""
+        _check(lib().fem_plan_set_timing(self.handle, int(bool(enable))))
+
+    def timing(self):
+        """(summed kernel milliseconds, bracketed calls) since timing was last switched."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().fem_plan_get_timing(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def strategy(self):
         st, pc, ln, sm = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

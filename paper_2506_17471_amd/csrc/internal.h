@@ -146,6 +146,12 @@ struct fem_plan {
     int64_t pstride = 0;
     std::vector<double> h_coords;        // host copies, to rebuild patches on request
     std::vector<int32_t> h_cell_verts, h_cell_nodes;
+    // optional event timing of the main kernel launches (fem_plan_set_timing); mutable
+    // because the action itself takes a const plan
+    bool timing = false;
+    mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_pending, timing_free;
+    mutable double timing_ms = 0.0;
+    mutable int64_t timing_calls = 0;
 };
 
 namespace femx {

@@ -269,12 +269,26 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     }
 }
 
+// The dispatcher deals workgroups to the 8 XCDs in turn (workgroup b to XCD b mod 8), and
+// each XCD has its own L2.  Renumbering so that XCD x works through one contiguous run of
+// the n patches -- runs of n/8 patches, the first n mod 8 runs one longer -- keeps Morton
+// neighbours, which share nodes and vertices, in one L2.  A bijection of [0, n) whatever
+// the dispatch order, so only locality depends on the dealing rule.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n)
+{
+    const int64_t q = n / kXcds, r = n % kXcds;
+    const int64_t x = b % kXcds, i = b / kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
 __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
     patch_kernel(const PatchArgs a, int P)
 {
-    patch_body<FORM, DIM, K, VJP, LPC, SUM>(a, blockIdx.x, P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM>(a, xcd_order(blockIdx.x, gridDim.x), P);
 }
 
 // Many meshes of one kernel variant in one launch: workgroup b works on patch
@@ -285,9 +299,10 @@ __global__ void __launch_bounds__(kMaxBlock)
     batch_patch_kernel(const BatchDesc *__restrict__ desc, const int32_t *__restrict__ patch_mesh,
                        int P)
 {
-    const int m = patch_mesh[blockIdx.x];
+    const int64_t b = xcd_order(blockIdx.x, gridDim.x);
+    const int m = patch_mesh[b];
     const BatchDesc &d = desc[m];
-    patch_body<FORM, DIM, K, VJP, LPC, SUM>(d.args, (int64_t)blockIdx.x - d.first_patch, P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM>(d.args, b - d.first_patch, P);
 }
 
 // Shared-node sums of many meshes: thread i sums shared node i - fix[m].first of the mesh m

@@ -102,9 +102,52 @@ void free_patch_memory(fem_plan *p)
     p->patch = 0;
 }
 
+// Wait for every recorded timing pair, add its time up and keep the events for reuse.
+void drain_timing(const fem_plan *p)
+{
+    for (auto &ev : p->timing_pending) {
+        femx::check_hip(hipEventSynchronize(ev.second), "hipEventSynchronize");
+        float ms = 0.f;
+        femx::check_hip(hipEventElapsedTime(&ms, ev.first, ev.second), "hipEventElapsedTime");
+        p->timing_ms += ms;
+        p->timing_calls += 1;
+        p->timing_free.push_back(ev);
+    }
+    p->timing_pending.clear();
+}
+
+std::pair<hipEvent_t, hipEvent_t> timing_pair(const fem_plan *p)
+{
+    if (p->timing_pending.size() >= 1024) drain_timing(p);
+    if (!p->timing_free.empty()) {
+        auto ev = p->timing_free.back();
+        p->timing_free.pop_back();
+        return ev;
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    femx::check_hip(hipEventCreate(&ev.first), "hipEventCreate");
+    if (hipEventCreate(&ev.second) != hipSuccess) {
+        (void)hipEventDestroy(ev.first);
+        femx::check_hip(hipErrorOutOfMemory, "hipEventCreate");
+    }
+    return ev;
+}
+
+void destroy_timing_events(fem_plan *p)
+{
+    for (auto *v : {&p->timing_pending, &p->timing_free})
+        for (auto &ev : *v) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+    p->timing_pending.clear();
+    p->timing_free.clear();
+}
+
 void free_plan_memory(fem_plan *p)
 {
     if (!p) return;
+    destroy_timing_events(p);
     (void)hipFree(p->d_coords);
     (void)hipFree(p->d_verts);
     (void)hipFree(p->d_nodes);
@@ -565,11 +608,11 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
 }
 
 // Sub-colour phases pay one barrier and one masked pass per colour: cheap next to the
-// quadrature work of the 2D forms (about 7 colours), not next to low-degree 3D cells (about
-// 24 colours), which sum through the element buffer.
+// quadrature work of the 2D forms (about 7 colours) and of 3D cells from P3 on, not next to
+// P1/P2 tetrahedra (about 24 colours), which sum through the element buffer.
 int default_sum_mode(const fem_plan *p)
 {
-    return p->dim == 2 ? femx::SUM_COLOURED : femx::SUM_ELEMENT;
+    return (p->dim == 2 || p->degree >= 3) ? femx::SUM_COLOURED : femx::SUM_ELEMENT;
 }
 
 // One lane per cell in 2D: with coloured sums the lane-pair split no longer pays for its
@@ -589,8 +632,10 @@ bool patch_allowed(int P, int lanes)
     return (P == 64 || P == 128 || P == 256) && P * lanes <= 256;
 }
 
-int default_patch_for(const fem_plan *p, int lanes)
+int default_patch_for(const fem_plan *p, int lanes, int sum_mode)
 {
+    // lane triples with coloured sums: two wavefronts per patch measured best (P4 elasticity)
+    if (lanes == 3 && sum_mode == femx::SUM_COLOURED) return 42;
     // the largest allowed patch whose element buffer (the larger LDS need) fits 64 KB
     static const int sizes12[] = {256, 128, 64};
     static const int sizes3[] = {84, 63, 42, 21};
@@ -602,7 +647,7 @@ int default_patch_for(const fem_plan *p, int lanes)
     return sz[n - 1];
 }
 
-int default_patch(const fem_plan *p) { return default_patch_for(p, p->lanes); }
+int default_patch(const fem_plan *p) { return default_patch_for(p, p->lanes, p->sum_mode); }
 
 void check_plan(const fem_plan *p)
 {
@@ -651,7 +696,16 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
                                          p->max_patch_nodes, p->sum_mode);
         a.lam = p->lam;
         a.mu = p->mu;
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (p->timing) {
+            ev = timing_pair(p);
+            femx::check_hip(hipEventRecord(ev.first, s), "hipEventRecord");
+        }
         femx::check_hip(femx::launch_patch(*p, a, nl_vjp, s), "patch launch");
+        if (p->timing) {
+            femx::check_hip(hipEventRecord(ev.second, s), "hipEventRecord");
+            p->timing_pending.push_back(ev);
+        }
         if (p->n_shared > 0)
             femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off, p->d_fix_slot,
                                                p->n_shared, p->d_partial, p->ncomp, y, s),
@@ -671,11 +725,20 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
     a.y = y;
     a.u = in;
     a.v = nl_vjp ? v : nullptr;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (p->timing) {
+        ev = timing_pair(p);
+        femx::check_hip(hipEventRecord(ev.first, s), "hipEventRecord");
+    }
     for (int c = 0; c < p->n_colours; ++c) {
         a.begin = p->colour_off[c];
         a.count = p->colour_off[c + 1] - p->colour_off[c];
         if (a.count == 0) continue;
         femx::check_hip(femx::launch_action(*p, a, p->block, nl_vjp, s), "action launch");
+    }
+    if (p->timing) {
+        femx::check_hip(hipEventRecord(ev.second, s), "hipEventRecord");
+        p->timing_pending.push_back(ev);
     }
 }
 
@@ -706,7 +769,7 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
         throw Error(FEM_E_UNSUPPORTED, "three lanes per cell exist for the 3D vector forms only");
     const int mode = sum_mode == 0 ? default_sum_mode(plan) : sum_mode;
     if (mode != SUM_ELEMENT && mode != SUM_COLOURED) throw Error(FEM_E_ARG, "unknown sum mode");
-    const int P = patch_cells == 0 ? default_patch_for(plan, lanes) : patch_cells;
+    const int P = patch_cells == 0 ? default_patch_for(plan, lanes, mode) : patch_cells;
     if (!patch_allowed(P, lanes))
         throw Error(FEM_E_ARG, "patch_cells must be 64, 128 or 256 (at most 256 lanes) for one or "
                                "two lanes per cell, and 21, 42, 63 or 84 for three");
@@ -804,6 +867,27 @@ void fem_plan_destroy(fem_plan *plan)
     (void)hipDeviceSynchronize();
     free_plan_memory(plan);
     delete plan;
+}
+
+int fem_plan_set_timing(fem_plan *plan, int enable)
+{
+    return guarded([&] {
+        check_plan(plan);
+        drain_timing(plan);
+        plan->timing = enable != 0;
+        plan->timing_ms = 0.0;
+        plan->timing_calls = 0;
+    });
+}
+
+int fem_plan_get_timing(fem_plan *plan, double *kernel_ms, int64_t *calls)
+{
+    return guarded([&] {
+        check_plan(plan);
+        drain_timing(plan);
+        if (kernel_ms) *kernel_ms = plan->timing_ms;
+        if (calls) *calls = plan->timing_calls;
+    });
 }
 
 int fem_action(const fem_plan *plan, const double *u, double *y, void *stream)

@@ -105,6 +105,8 @@ def test_error_paths_from_host():
     assert L.fem_action(None, None, None, None) == -1
     assert L.fem_action_vjp(None, None, None, None, None) == -1
     assert L.fem_plan_info(None, None, None, None, None, None) == -1
+    assert L.fem_plan_set_timing(None, 1) == -1
+    assert L.fem_plan_get_timing(None, None, None) == -1
 
 
 def test_plan_without_device_reports_hip_error():

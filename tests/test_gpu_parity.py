@@ -112,6 +112,25 @@ def test_vjp_small_meshes(form, dim, k, strategy):
     assert emax < TOL and el2 < TOL, (emax, el2)
 
 
+@pytest.mark.parametrize("strategy", [fx.SCATTER_PATCH, fx.SCATTER_COLOUR])
+def test_kernel_timing_counts_calls_and_leaves_results(strategy):
+    w = meshgen.workload("nh_p4_2d", n=24)
+    say(f"[timing] nh_p4_2d n=24 strategy={strategy}")
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    plan.set_strategy(strategy)
+    u = gpu(w.u)
+    y0 = plan.action(u)
+    plan.set_timing(True)
+    for _ in range(5):
+        y1 = plan.action(u)
+    ms, n = plan.timing()
+    assert n == 5 and ms > 0.0
+    assert torch.equal(y0, y1)
+    plan.set_timing(False)
+    plan.action(u)
+    assert plan.timing() == (0.0, 0)
+
+
 @pytest.mark.parametrize("block", [64, 128, 256])
 def test_block_sizes_bitwise_identical(block):
     w = meshgen.workload("nh_p4_2d", n=24)
