@@ -255,6 +255,21 @@ def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
     for p, u, y in zip(plans, us, ys):
         m, _ = time_steps(lambda p=p, u=u, y=y: p.action(u, out=y), max(5, steps // 3), 2)
         alone.append(m)
+    # the same per-mesh launches captured in one graph: isolates launch overhead from the
+    # grouping of meshes into few launches; its replays must give the eager results bitwise
+    y_eager = [y.clone() for y in ys]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        per_mesh()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        per_mesh()
+    ms_pm_graph, _ = time_steps(g.replay, steps, warmup)
+    torch.cuda.synchronize()
+    pm_graph_ok = all(torch.equal(a, b) for a, b in zip(ys, y_eager))
+    del g
     batch = fx.Batch(plans, us, ys)
     ms_graph, _ = time_steps(lambda: batch.run(graph=True), steps, warmup)
     ms_eager, _ = time_steps(lambda: batch.run(graph=False), steps, warmup)
@@ -263,9 +278,11 @@ def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
     out = dict(n_mesh=len(ws), n_cell=n_cell, n_dof=n_dof, groups=batch.n_groups, tuned=tuned,
                patches=batch.n_patches,
                per_mesh_loop_ms=ms_each, sum_of_alone_ms=float(np.sum(alone)),
+               per_mesh_graph_ms=ms_pm_graph, per_mesh_graph_matches_eager=pm_graph_ok,
                batch_graph_ms=ms_graph, batch_eager_ms=ms_eager,
                dof_per_s=n_dof / (ms_graph / 1e3))
     out["speedup_vs_per_mesh"] = out["per_mesh_loop_ms"] / out["batch_graph_ms"]
+    out["speedup_vs_per_mesh_graph"] = out["per_mesh_graph_ms"] / out["batch_graph_ms"]
     batch.close()
     return out
 

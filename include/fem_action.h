@@ -120,6 +120,18 @@ int fem_action(const fem_plan *plan, const double *u, double *y, void *stream);
 int fem_action_vjp(const fem_plan *plan, const double *u, const double *v, double *g,
                    void *stream);
 
+/*
+ * One-shot y = A(u) from the mesh arrays alone: builds a temporary plan with the
+ * arguments of fem_plan_create (default launch configuration), runs fem_action on
+ * `stream`, waits for it and destroys the plan.  Synchronous and slow (plan building
+ * dominates); for repeated actions on one mesh create a plan once.  Errors: those of
+ * fem_plan_create and fem_action.
+ */
+int fem_action_once(int form, int dim, int degree, int quad_degree, int64_t n_vert,
+                    const double *coords, int64_t n_cell, const int32_t *cell_verts,
+                    const int32_t *cell_nodes, int64_t n_node, const double *params,
+                    int n_params, const double *u, double *y, void *stream);
+
 /* Plan properties (all outputs optional, pass NULL to skip). */
 int fem_plan_info(const fem_plan *plan, int *n_loc, int *ncomp, int *n_quad, int *n_colours,
                   int64_t *n_dof);

@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
     L.fem_reference_tables.restype = i32
     L.fem_plan_set_block.argtypes = [P, i32]
     L.fem_plan_set_block.restype = i32
+    L.fem_action_once.argtypes = [i32, i32, i32, i32, i64, P, i64, P, P, i64, P, i32, P, P, P]
+    L.fem_action_once.restype = i32
     L.fem_plan_set_timing.argtypes = [P, i32]
     L.fem_plan_set_timing.restype = i32
     L.fem_plan_get_timing.argtypes = [P, P, P]
@@ -297,6 +299,26 @@ class Plan:
                                     _dev_ptr(v, self.n_dof, "v"),
                                     _dev_ptr(out, self.n_dof, "g"), _stream_handle(stream)))
         return out
+
+
+def action_once(form: int, dim: int, degree: int, quad_degree: int, coords, cell_verts,
+                cell_nodes, n_node: int, params, u, out=None, stream=None):
+    """y = A(u) straight from the mesh arrays (a temporary plan; synchronous, slow)."""
+    import torch
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cell_verts = np.ascontiguousarray(cell_verts, dtype=np.int32)
+    cell_nodes = np.ascontiguousarray(cell_nodes, dtype=np.int32)
+    prm = np.ascontiguousarray(params, dtype=np.float64)
+    n = int(n_node) * (1 if form == FORM_MASS else dim)
+    if out is None:
+        out = torch.empty_like(u)
+    _check(lib().fem_action_once(form, dim, degree, quad_degree, coords.shape[0],
+                                 _np_ptr(coords), cell_verts.shape[0], _np_ptr(cell_verts),
+                                 _np_ptr(cell_nodes), int(n_node),
+                                 _np_ptr(prm) if prm.size else None, int(prm.size),
+                                 _dev_ptr(u, n, "u"), _dev_ptr(out, n, "y"),
+                                 _stream_handle(stream)))
+    return out
 
 
 class Batch:

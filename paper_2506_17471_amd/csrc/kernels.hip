@@ -95,6 +95,68 @@ __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
 }
 
 // ------------------------------------------------------------------- patch strategy
+// Stage the patch's node ids (region B) and nodal values (region A) in LDS.  Each thread
+// takes B nodes per round and issues all their id loads, then all their value loads,
+// before the first wait: a few memory round trips per workgroup instead of one per node a
+// thread stages.  Indices past the end are clamped to the last node (U >= 1 for every
+// patch), so the loads need no branches; only the LDS stores are guarded.  B = 8, or 4
+// for the mass form, whose patches hold about 2.5 nodes per lane and whose occupancy is
+// set by registers.
+
+template <int NC, bool VJP, int B>
+__device__ __forceinline__ void stage_nodes(const PatchArgs &a, int nb, int U, int tid,
+                                            int nthreads, double *lds, int32_t *b_node)
+{
+    for (int j0 = tid; j0 < U; j0 += B * nthreads) {
+        int32_t nd[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = min(j0 + b * nthreads, U - 1);
+            nd[b] = a.patch_nodes[nb + j];
+        }
+        double uv[B][NC], vv[VJP ? B : 1][NC];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                uv[b][c] = a.u[(int64_t)nd[b] * NC + c];
+                if constexpr (VJP) vv[b][c] = a.v[(int64_t)nd[b] * NC + c];
+            }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = j0 + b * nthreads;
+            if (j < U) {
+                b_node[j] = nd[b];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    lds[j * NC + c] = uv[b][c];
+                    if constexpr (VJP) lds[(U + j) * NC + c] = vv[b][c];
+                }
+            }
+        }
+    }
+}
+
+// Copy n consecutive elements from global memory to LDS, kStageBatch loads in flight per
+// thread (indices clamped as in stage_nodes; n >= 1).
+constexpr int kStageBatch = 8;
+
+template <typename T>
+__device__ __forceinline__ void stage_copy(const T *__restrict__ src, int n, int tid,
+                                           int nthreads, T *dst)
+{
+    for (int j0 = tid; j0 < n; j0 += kStageBatch * nthreads) {
+        T val[kStageBatch];
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) val[b] = src[min(j0 + b * nthreads, n - 1)];
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) {
+            const int j = j0 + b * nthreads;
+            if (j < n) dst[j] = val[b];
+        }
+    }
+}
+
 // LPC lanes per cell: 1; 2 for the 2D vector forms (lane c of a pair owns component c);
 // 3 for the 3D vector forms (lane c of a triple owns component c; a wavefront holds 21
 // triples and leaves its last lane idle).  SUM: SUM_ELEMENT (LDS element buffer and fixed-
@@ -146,20 +208,13 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     uint16_t *b_slot = reinterpret_cast<uint16_t *>(b_off + U + 1);
     int e_base = 0;
     if constexpr (SUM == SUM_ELEMENT) {
+        // slot lists: b_off holds global CSR offsets, rebased by e_base when read
         e_base = a.csr_off[nb];
         const int n_slots = a.csr_off[nb + U] - e_base;
-        for (int j = tid; j <= U; j += nthreads) b_off[j] = a.csr_off[nb + j] - e_base;
-        for (int e = tid; e < n_slots; e += nthreads) b_slot[e] = a.csr_slots[e_base + e];
+        stage_copy(a.csr_off + nb, U + 1, tid, nthreads, b_off);
+        stage_copy(a.csr_slots + e_base, n_slots, tid, nthreads, b_slot);
     }
-    for (int j = tid; j < U; j += nthreads) {
-        const int32_t nd = a.patch_nodes[nb + j];
-        b_node[j] = nd;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            lds[j * NC + c] = a.u[(int64_t)nd * NC + c];
-            if constexpr (VJP) lds[(U + j) * NC + c] = a.v[(int64_t)nd * NC + c];
-        }
-    }
+    stage_nodes<NC, VJP, FORM == FEM_MASS ? 4 : 8>(a, nb, U, tid, nthreads, lds, b_node);
     __syncthreads();
 
     // 2. the cell's values from LDS
@@ -229,12 +284,17 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
         }
         const int ncol = a.patch_ncol[p];
         __syncthreads();                      // the accumulator is zero everywhere
+        // no two cells of a colour share a node, so within a phase each address has one
+        // writer: the LDS atomic add (no return) is only a read-modify-write without the
+        // round trip, and the sum order stays fixed (colour order)
         for (int k = 0; k < ncol; ++k) {
             if (col == k) {
 #pragma unroll
                 for (int n = 0; n < NLOC; ++n)
 #pragma unroll
-                    for (int c = 0; c < CW; ++c) lds[lid2[n] * NC + c + comp] += yl[n][c];
+                    for (int c = 0; c < CW; ++c)
+                        __hip_atomic_fetch_add(&lds[lid2[n] * NC + c + comp], yl[n][c],
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             __syncthreads();
         }
@@ -244,7 +304,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     for (int j = tid; j < U; j += nthreads) {
         double sum[NC];
         if constexpr (SUM == SUM_ELEMENT) {
-            const int e0 = b_off[j], e1 = b_off[j + 1];
+            const int e0 = b_off[j] - e_base, e1 = b_off[j + 1] - e_base;
 #pragma unroll
             for (int c = 0; c < NC; ++c) sum[c] = 0.0;
             for (int e = e0; e < e1; ++e) {

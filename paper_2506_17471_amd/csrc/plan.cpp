@@ -869,6 +869,23 @@ void fem_plan_destroy(fem_plan *plan)
     delete plan;
 }
 
+int fem_action_once(int form, int dim, int degree, int quad_degree, int64_t n_vert,
+                    const double *coords, int64_t n_cell, const int32_t *cell_verts,
+                    const int32_t *cell_nodes, int64_t n_node, const double *params,
+                    int n_params, const double *u, double *y, void *stream)
+{
+    fem_plan *p = nullptr;
+    int st = fem_plan_create(&p, form, dim, degree, quad_degree, n_vert, coords, n_cell,
+                             cell_verts, cell_nodes, n_node, params, n_params);
+    if (st != FEM_OK) return st;
+    st = guarded([&] {
+        run(p, u, nullptr, y, stream, false);
+        femx::check_hip(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    });
+    fem_plan_destroy(p);
+    return st;
+}
+
 int fem_plan_set_timing(fem_plan *plan, int enable)
 {
     return guarded([&] {

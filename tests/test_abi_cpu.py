@@ -105,6 +105,9 @@ def test_error_paths_from_host():
     assert L.fem_action(None, None, None, None) == -1
     assert L.fem_action_vjp(None, None, None, None, None) == -1
     assert L.fem_plan_info(None, None, None, None, None, None) == -1
+    # the one-shot entry fails in plan creation, before touching the vectors
+    st1 = L.fem_action_once(7, 2, 2, 4, 0, None, 0, None, None, 0, None, 0, None, None, None)
+    assert st1 == -2
     assert L.fem_plan_set_timing(None, 1) == -1
     assert L.fem_plan_get_timing(None, None, None) == -1
 

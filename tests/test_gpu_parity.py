@@ -112,6 +112,18 @@ def test_vjp_small_meshes(form, dim, k, strategy):
     assert emax < TOL and el2 < TOL, (emax, el2)
 
 
+@pytest.mark.parametrize("name", ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d"])
+def test_action_once_matches_oracle(name):
+    w = meshgen.workload(name, n=8 if name != "elast_p2_3d" else 3)
+    say(f"[once] {name} cells={w.mesh.n_cell}")
+    m = w.mesh
+    y = fx.action_once(w.form, m.dim, m.k, w.quad_degree, m.coords, m.cell_verts, m.cell_nodes,
+                       m.n_node, w.params, gpu(w.u)).cpu().numpy()
+    ref = oracle.action(w.form, m, w.u, w.quad_degree, w.params)
+    emax, el2 = rel_err(y, ref)
+    assert emax < TOL and el2 < TOL, (emax, el2)
+
+
 @pytest.mark.parametrize("strategy", [fx.SCATTER_PATCH, fx.SCATTER_COLOUR])
 def test_kernel_timing_counts_calls_and_leaves_results(strategy):
     w = meshgen.workload("nh_p4_2d", n=24)
