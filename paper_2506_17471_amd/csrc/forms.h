@@ -277,8 +277,7 @@ __device__ __forceinline__ void cell_quadrature(
         for (int n = 0; n < NLOC; ++n)
 #pragma unroll
             for (int c = 0; c < DIM; ++c) yl[n][c] = 0.0;
-#pragma unroll 1
-        for (int q = 0; q < nq; ++q) {
+        auto point = [&](int q) {
             const FEMX_CONSTANT double *t = tab + q * REC;
             double gu[DIM][DIM], gv[DIM][DIM];
 #pragma unroll
@@ -319,6 +318,17 @@ __device__ __forceinline__ void cell_quadrature(
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) yl[n][c] = fma(tr, T[c][r], yl[n][c]);
                 }
+        };
+        // Two points per trip give the scheduler two independent pointwise chains (the
+        // log and reciprocal sequences are long serial dependences) where the cell's
+        // values and outputs leave room: forward actions with at most 42 of them.
+        // Larger cells and the VJP run one point per trip.
+        if constexpr (!VJP && NLOC * DIM <= 42) {
+#pragma unroll 2
+            for (int q = 0; q < nq; ++q) point(q);
+        } else {
+#pragma unroll 1
+            for (int q = 0; q < nq; ++q) point(q);
         }
     }
 }
