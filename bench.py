@@ -133,10 +133,12 @@ def cold_flush(buf):
     buf.add_(1.0)
 
 
-def make_plan(w, tune: bool, vjp: bool = False):
+def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default"):
     import torch
     import paper_2506_17471_amd as fx
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    if rule != "default":
+        plan.set_quadrature(fx.QUAD_CONICAL if rule == "conical" else fx.QUAD_SYMMETRIC)
     u = torch.as_tensor(w.u, device="cuda")
     y = torch.empty_like(u)
     v = None
@@ -155,12 +157,12 @@ def make_plan(w, tune: bool, vjp: bool = False):
 
 
 def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bool = False,
-                 tune: bool = True):
+                 tune: bool = True, rule: str = "default"):
     import torch
     import meshgen
 
     w = meshgen.workload(name, with_v=vjp)
-    plan, u, v, y, tuned = make_plan(w, tune, vjp)
+    plan, u, v, y, tuned = make_plan(w, tune, vjp, rule)
     if vjp:
         fn = lambda: plan.vjp(u, v, out=y)  # noqa: E731
     else:
@@ -195,7 +197,8 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
     else:
         fl = flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad)
     info = dict(workload=name, vjp=vjp, cold=cold, n_cell=w.mesh.n_cell, n_dof=w.n_dof,
-                n_loc=plan.n_loc, n_quad=plan.n_quad, tuned=tuned,
+                n_loc=plan.n_loc, n_quad=plan.n_quad, quad_family=plan.quad_family_name,
+                tuned=tuned,
                 flops_per_cell=fl, flops=fl * w.mesh.n_cell,
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
                                       3 if vjp and w.form == 2 else 2),
@@ -287,18 +290,19 @@ def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
     return out
 
 
-def cpu_baseline(w, max_cells: int = 65536):
-    """The oracle (single thread) on the first `max_cells` cells of the same mesh."""
+def cpu_baseline(w, family: str, max_cells: int = 65536):
+    """The oracle (single thread) on the first `max_cells` cells of the same mesh, with the
+    quadrature rule the GPU plan used."""
     import oracle
     import meshgen
     m = w.mesh
     nc = min(max_cells, m.n_cell)
     sub = meshgen.Mesh(m.dim, m.n, m.k, m.coords, m.cell_verts[:nc], m.cell_nodes[:nc], m.n_node, m.h)
-    oracle.action(w.form, sub, w.u, w.quad_degree, w.params)     # warm (tables, library)
+    oracle.action(w.form, sub, w.u, w.quad_degree, w.params, family=family)   # warm (tables, library)
     t0 = time.perf_counter()
     reps = 0
     while True:
-        oracle.action(w.form, sub, w.u, w.quad_degree, w.params)
+        oracle.action(w.form, sub, w.u, w.quad_degree, w.params, family=family)
         reps += 1
         if time.perf_counter() - t0 > 10.0:
             break
@@ -318,6 +322,8 @@ def main():
     ap.add_argument("--all", action="store_true", help="also time the other workloads and the batch")
     ap.add_argument("--batch", action="store_true", help="also time the 64-mesh batch")
     ap.add_argument("--no-tune", action="store_true", help="use the plans' default launch configuration")
+    ap.add_argument("--rule", choices=["default", "conical", "symmetric"], default="default",
+                    help="quadrature rule family of the timed workload (default: the plan's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate the "
@@ -345,11 +351,12 @@ def main():
     def note(msg):
         print(f"# {msg}", file=sys.stderr, flush=True)
 
-    main_info, w = run_workload(args.workload, args.steps, args.warmup, tune=tune)
+    main_info, w = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule=args.rule)
     note(f"{args.workload}: {main_info['ms_mean']:.4f} ms/step, tuned {main_info['tuned']}")
     extras = {}
     if w.form == 2:
-        vinfo, _ = run_workload(args.workload, args.steps, args.warmup, vjp=True, tune=tune)
+        vinfo, _ = run_workload(args.workload, args.steps, args.warmup, vjp=True, tune=tune,
+                                rule=args.rule)
         extras["vjp"] = vinfo
         extras["adjoint_forward_time_ratio"] = vinfo["ms_mean"] / main_info["ms_mean"]
         note(f"vjp: {vinfo['ms_mean']:.4f} ms/step")
@@ -358,6 +365,11 @@ def main():
             info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
             extras[name] = info
             note(f"{name}: {info['ms_mean']:.4f} ms/step")
+        if w.form == 2 and args.rule == "default":
+            # the same operator family with the conical-product rule (more points)
+            info, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule="conical")
+            extras[args.workload + "_conical"] = info
+            note(f"{args.workload} conical rule: {info['ms_mean']:.4f} ms/step")
         for name in ("mass_p2_2d_1024", "nh_p4_2d", "elast_p2_3d"):
             info, _ = run_workload(name, args.steps, args.warmup, cold=True, tune=tune)
             extras[name + "_cold"] = info
@@ -389,6 +401,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_cell": main_info["n_cell"],
                    "n_dof": main_info["n_dof"], "n_quad": main_info["n_quad"],
+                   "quad_rule": main_info["quad_family"],
                    "launch": main_info["launch"], "tuner": main_info["tuned"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
@@ -402,7 +415,7 @@ def main():
         "extras": extras,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, main_info["quad_family"])
     print(json.dumps(out))
 
 

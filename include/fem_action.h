@@ -19,11 +19,16 @@
  *   cell_verts order; integrals use |det J| (cells with det J < 0 in 3D are valid).
  * - Quadrature: a rule exact to quad_degree on the reference simplex, from one of two
  *   families: FEM_QUAD_CONICAL, the conical-product (collapsed Gauss-Jacobi) rule with
- *   ceil((quad_degree + 1)/2) points per direction (any degree); FEM_QUAD_SYMMETRIC, the
- *   fully symmetric rules with fewest points, built for quad_degree <= 2 (1 point, or 3 /
- *   4 points on the orbit of (a, b, b[, b])).  A plan of the mass or elasticity form uses
- *   the symmetric rule when one exists (their integrands are polynomials, so the operator
- *   does not depend on the exact rule); the neo-Hookean form uses the conical rule.
+ *   ceil((quad_degree + 1)/2) points per direction (any degree); FEM_QUAD_SYMMETRIC, fully
+ *   symmetric rules (points on orbits of the simplex's symmetry group, one weight per
+ *   orbit, positive weights, points inside), each an isolated root of its moment
+ *   equations solved by Newton's method at plan creation: triangles of degree <= 2, 4, 6,
+ *   8, 10 (1, 3, 6, 12, 16, 25 points), tetrahedra of degree <= 2, 5, 6 (1, 4, 14, 24
+ *   points);
+ *   a degree without its own rule takes the next tabulated one.  A plan uses the
+ *   symmetric rule when one is built for its degree, else the conical rule
+ *   (fem_plan_set_quadrature switches).  The mass and elasticity operators do not depend
+ *   on the rule (polynomial integrands); the neo-Hookean operator does.
  * - Vectors are node-major interleaved: component c of node n at index n * ncomp + c,
  *   ncomp = 1 for the mass form and d for the vector forms.
  * - Host arrays are read during the call only.  Device arrays (u, v, y, g) are caller-
@@ -206,6 +211,9 @@ int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lan
                           int sum_mode);
 int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
                           int *lanes_per_cell, int *sum_mode);
+
+/* The plan's quadrature family (FEM_QUAD_*) and number of points.  Errors: FEM_E_ARG. */
+int fem_plan_get_quadrature(const fem_plan *plan, int *family, int *n_points);
 
 /*
  * Kernel timing, a measurement aid.  With timing on, every fem_action / fem_action_vjp

@@ -6,7 +6,8 @@ import it; the GPU library never does, and the two share no code (basis, quadrat
 geometry, forms, colouring are all written separately here).
 
 Pieces:
-* ``quadrature.stroud``  -- reference-simplex rule (scipy Gauss-Jacobi roots);
+* ``quadrature.stroud``  -- conical-product rule (scipy Gauss-Jacobi roots);
+* ``quadrature.symmetric`` -- fully symmetric rules (moment equations, scipy least squares);
 * ``basis.tabulate``     -- Silvester-formula P_k Lagrange values and reference gradients;
 * ``fem_oracle.c``       -- the per-cell loop of the paper's generic action kernel
   (Sec. 2.3) for the mass, linear elasticity and neo-Hookean forms (App. A), the
@@ -93,11 +94,16 @@ def _ptr(a: np.ndarray):
 
 
 class Tables:
-    """Quadrature rule and tabulation for (dim, k, quadrature degree)."""
+    """Quadrature rule and tabulation for (dim, k, quadrature degree, rule family)."""
 
-    def __init__(self, dim: int, k: int, quad_degree: int):
-        self.dim, self.k, self.quad_degree = dim, k, quad_degree
-        self.points, self.weights = quadrature.stroud(dim, quad_degree)
+    def __init__(self, dim: int, k: int, quad_degree: int, family: str = "conical"):
+        self.dim, self.k, self.quad_degree, self.family = dim, k, quad_degree, family
+        if family == "conical":
+            self.points, self.weights = quadrature.stroud(dim, quad_degree)
+        elif family == "symmetric":
+            self.points, self.weights = quadrature.symmetric(dim, quad_degree)
+        else:
+            raise ValueError(family)
         phi, dphi = basis.tabulate(dim, k, self.points)
         self.phi = np.ascontiguousarray(phi, dtype=np.float64)
         self.dphi = np.ascontiguousarray(dphi, dtype=np.float64)
@@ -109,10 +115,10 @@ class Tables:
 _tables_cache: dict = {}
 
 
-def tables(dim: int, k: int, quad_degree: int) -> Tables:
-    key = (dim, k, quad_degree)
+def tables(dim: int, k: int, quad_degree: int, family: str = "conical") -> Tables:
+    key = (dim, k, quad_degree, family)
     if key not in _tables_cache:
-        _tables_cache[key] = Tables(dim, k, quad_degree)
+        _tables_cache[key] = Tables(dim, k, quad_degree, family)
     return _tables_cache[key]
 
 
@@ -129,10 +135,11 @@ def _lam_mu(params):
     return float(params[0]), float(params[1])
 
 
-def action(form: int, mesh, u: np.ndarray, quad_degree: int, params=()) -> np.ndarray:
+def action(form: int, mesh, u: np.ndarray, quad_degree: int, params=(),
+           family: str = "conical") -> np.ndarray:
     """y = A(u) by the plain per-cell loop."""
     lib = _load()
-    t = tables(mesh.dim, mesh.k, quad_degree)
+    t = tables(mesh.dim, mesh.k, quad_degree, family)
     cv, cn, xy = _mesh_arrays(mesh)
     ncomp = 1 if form == FORM_MASS else mesh.dim
     n_dof = mesh.n_node * ncomp
@@ -145,10 +152,11 @@ def action(form: int, mesh, u: np.ndarray, quad_degree: int, params=()) -> np.nd
     return y
 
 
-def vjp(form: int, mesh, u: np.ndarray, v: np.ndarray, quad_degree: int, params=()) -> np.ndarray:
+def vjp(form: int, mesh, u: np.ndarray, v: np.ndarray, quad_degree: int, params=(),
+        family: str = "conical") -> np.ndarray:
     """g = (dA/du)^T v."""
     lib = _load()
-    t = tables(mesh.dim, mesh.k, quad_degree)
+    t = tables(mesh.dim, mesh.k, quad_degree, family)
     cv, cn, xy = _mesh_arrays(mesh)
     ncomp = 1 if form == FORM_MASS else mesh.dim
     n_dof = mesh.n_node * ncomp
@@ -163,10 +171,10 @@ def vjp(form: int, mesh, u: np.ndarray, v: np.ndarray, quad_degree: int, params=
     return g
 
 
-def nh_energy(mesh, u: np.ndarray, quad_degree: int, params) -> float:
+def nh_energy(mesh, u: np.ndarray, quad_degree: int, params, family: str = "conical") -> float:
     """Discrete neo-Hookean energy Pi_h(u)."""
     lib = _load()
-    t = tables(mesh.dim, mesh.k, quad_degree)
+    t = tables(mesh.dim, mesh.k, quad_degree, family)
     cv, cn, xy = _mesh_arrays(mesh)
     u = np.ascontiguousarray(u, dtype=np.float64)
     lam, mu = _lam_mu(params)
@@ -174,9 +182,9 @@ def nh_energy(mesh, u: np.ndarray, quad_degree: int, params) -> float:
                                 cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u))
 
 
-def min_det_f(mesh, u: np.ndarray, quad_degree: int) -> float:
+def min_det_f(mesh, u: np.ndarray, quad_degree: int, family: str = "conical") -> float:
     lib = _load()
-    t = tables(mesh.dim, mesh.k, quad_degree)
+    t = tables(mesh.dim, mesh.k, quad_degree, family)
     cv, cn, xy = _mesh_arrays(mesh)
     u = np.ascontiguousarray(u, dtype=np.float64)
     return lib.oracle_min_det_f(mesh.dim, t.nloc, t.nq, _ptr(t.dphi), cv.shape[0], _ptr(cv),

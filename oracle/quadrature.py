@@ -12,12 +12,23 @@ Reference simplex: {xi >= 0, sum xi <= 1}, measure 1/d!.
 Point order: the innermost direction (s) fastest.
 
 The 1D rules come from ``scipy.special.roots_jacobi`` (a library primitive).
+
+The second family, ``symmetric``: fully symmetric rules, whose points lie on orbits of the
+simplex's symmetry group with one weight per orbit, with as many unknowns as there are
+independent symmetric moment conditions up to the degree (so each rule is an isolated root
+of its moment equations).  The paper's table of kernel parameters lists point counts that
+match rules of this kind; it prints no rule.  Here each rule is the root of the moment
+equations nearest to a few-digit approximation of its orbit parameters, found by scipy's
+least-squares solver (a library primitive) and accepted only if it integrates every
+monomial up to the degree exactly (to rounding), has positive weights and points inside.
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
+from scipy.optimize import least_squares
 from scipy.special import roots_jacobi
 
 
@@ -57,3 +68,113 @@ def stroud(dim: int, degree: int) -> tuple[np.ndarray, np.ndarray]:
                     wts.append(ws[i] * wt[j] * wz[l])
         return np.asarray(pts), np.asarray(wts)
     raise ValueError("dim must be 2 or 3")
+
+
+# --------------------------------------------------------------------- symmetric rules
+# Orbits in barycentric coordinates.  Triangle: "c" centroid, "aab" = perms of (a, a, 1-2a),
+# "abc" = perms of (a, b, 1-a-b).  Tetrahedron: "c", "aaab" = perms of (a, a, a, 1-3a),
+# "aabb" = perms of (a, a, 1/2-a, 1/2-a), "aabc" = perms of (a, a, b, 1-2a-b).
+# Each entry: (orbit, approximate parameters, approximate weight); weights sum to 1/d!.
+SYMMETRIC_APPROX = {
+    (2, 4): [("aab", (0.445948,), 0.111691), ("aab", (0.0915762,), 0.0549759)],
+    (2, 6): [("aab", (0.249287,), 0.0583931), ("aab", (0.0630890,), 0.0254225),
+             ("abc", (0.310352, 0.0531450), 0.0414255)],
+    (2, 8): [("c", (), 0.0721578), ("aab", (0.0505472,), 0.0162292),
+             ("aab", (0.459293,), 0.0475458), ("aab", (0.170569,), 0.0516087),
+             ("abc", (0.263113, 0.00839478), 0.0136152)],
+    (2, 10): [("c", (), 0.0416099), ("aab", (0.0285035,), 0.00547564),
+              ("aab", (0.162913,), 0.0263260), ("abc", (0.153303, 0.0336857), 0.0146614),
+              ("abc", (0.363363, 0.607330), 0.0176975), ("abc", (0.336696, 0.146812), 0.0281386)],
+    (3, 5): [("aaab", (0.310886,), 0.0187813), ("aaab", (0.0927353,), 0.0122488),
+             ("aabb", (0.0455037,), 0.00709100)],
+    (3, 6): [("aaab", (0.214603,), 0.00665379), ("aaab", (0.0406740,), 0.00167954),
+             ("aaab", (0.322338,), 0.00922620), ("aabc", (0.0636610, 0.269672), 0.00803571)],
+}
+
+
+def _orbit(dim: int, kind: str, prm) -> list[tuple]:
+    """Barycentric points of one orbit: the distinct arrangements of its symbol pattern."""
+    if kind == "c":
+        return [tuple([1.0 / (dim + 1)] * (dim + 1))]
+    if dim == 2 and kind == "aab":
+        value = {"a": prm[0], "b": 1.0 - 2.0 * prm[0]}
+    elif dim == 2 and kind == "abc":
+        value = {"a": prm[0], "b": prm[1], "c": 1.0 - prm[0] - prm[1]}
+    elif dim == 3 and kind == "aaab":
+        value = {"a": prm[0], "b": 1.0 - 3.0 * prm[0]}
+    elif dim == 3 and kind == "aabb":
+        value = {"a": prm[0], "b": 0.5 - prm[0]}
+    elif dim == 3 and kind == "aabc":
+        value = {"a": prm[0], "b": prm[1], "c": 1.0 - 2.0 * prm[0] - prm[1]}
+    else:
+        raise ValueError(kind)
+    return [tuple(value[ch] for ch in arr) for arr in sorted(set(itertools.permutations(kind)))]
+
+
+def _rule_degree(dim: int, degree: int):
+    """The smallest tabulated symmetric degree >= degree, or None."""
+    cands = [m for (d, m) in SYMMETRIC_APPROX if d == dim and m >= degree]
+    return min(cands) if cands else None
+
+
+def _expand(dim: int, structure, x):
+    pts, wts, i = [], [], 0
+    for kind, prm0, _ in structure:
+        k = len(prm0)
+        prm, w = x[i:i + k], x[i + k]
+        i += k + 1
+        for lam in _orbit(dim, kind, prm):
+            pts.append(lam[1:])
+            wts.append(w)
+    return np.asarray(pts), np.asarray(wts)
+
+
+def _monomial_exponents(dim: int, m: int):
+    return [e for e in itertools.product(range(m + 1), repeat=dim) if sum(e) <= m]
+
+
+def _monomial_integral(e) -> float:
+    """Exact integral of prod xi_r^e_r over the reference simplex: prod e_r! / (|e| + d)!."""
+    return math.prod(math.factorial(k) for k in e) / math.factorial(sum(e) + len(e))
+
+
+def has_symmetric(dim: int, degree: int) -> bool:
+    return degree <= 2 or _rule_degree(dim, degree) is not None
+
+
+def symmetric(dim: int, degree: int) -> tuple[np.ndarray, np.ndarray]:
+    """Fully symmetric rule exact to `degree`: (points [Q, dim], weights [Q])."""
+    vol = 1.0 / math.factorial(dim)
+    if degree <= 1:
+        return np.full((1, dim), 1.0 / (dim + 1)), np.array([vol])
+    if degree == 2:
+        # orbit of (1 - d b, b, ..., b); the second moment of a barycentric coordinate,
+        # int lambda^2 = 2 vol / ((d + 1)(d + 2)), fixes b:
+        #   triangle: 6 b^2 - 4 b + 1/2 = 0 -> b = 1/6;  tet: 12 b^2 - 6 b + 3/5 = 0
+        b = 1.0 / 6.0 if dim == 2 else (5.0 - math.sqrt(5.0)) / 20.0
+        a = 1.0 - dim * b
+        pts = [tuple(a if r + 1 == k else b for r in range(dim)) for k in range(dim + 1)]
+        return np.asarray(pts), np.full(dim + 1, vol / (dim + 1))
+    m = _rule_degree(dim, degree)
+    if m is None:
+        raise ValueError(f"no symmetric rule of degree {degree} in {dim}D")
+    structure = SYMMETRIC_APPROX[(dim, m)]
+    mons = np.array(_monomial_exponents(dim, m))
+    exact = np.array([_monomial_integral(e) for e in mons])
+
+    def residual(x):
+        pts, wts = _expand(dim, structure, x)
+        vals = np.prod(pts[:, None, :] ** mons[None, :, :], axis=2)
+        return (wts @ vals - exact) / exact
+
+    x0 = []
+    for _, prm, w in structure:
+        x0 += list(prm) + [w]
+    sol = least_squares(residual, np.asarray(x0), xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    pts, wts = _expand(dim, structure, sol.x)
+    if np.max(np.abs(residual(sol.x))) > 1e-14 or np.any(wts <= 0):
+        raise RuntimeError(f"symmetric rule {dim}D degree {m} did not converge")
+    lam0 = 1.0 - pts.sum(axis=1)
+    if np.any(pts < -1e-15) or np.any(lam0 < -1e-15):
+        raise RuntimeError(f"symmetric rule {dim}D degree {m} has a point outside")
+    return pts, wts

@@ -74,6 +74,8 @@ def lib() -> ctypes.CDLL:
     L.fem_plan_set_block.restype = i32
     L.fem_action_once.argtypes = [i32, i32, i32, i32, i64, P, i64, P, P, i64, P, i32, P, P, P]
     L.fem_action_once.restype = i32
+    L.fem_plan_get_quadrature.argtypes = [P, P, P]
+    L.fem_plan_get_quadrature.restype = i32
     L.fem_plan_set_timing.argtypes = [P, i32]
     L.fem_plan_set_timing.restype = i32
     L.fem_plan_get_timing.argtypes = [P, P, P]
@@ -206,6 +208,17 @@ class Plan:
                                ctypes.byref(ncol), ctypes.byref(nd)))
         self.n_loc, self.ncomp, self.n_quad, self.n_colours, self.n_dof = (
             nl.value, nc.value, nq.value, ncol.value, nd.value)
+        self._read_quadrature()
+
+    def _read_quadrature(self):
+        fam, nq = ctypes.c_int(), ctypes.c_int()
+        _check(lib().fem_plan_get_quadrature(self.handle, ctypes.byref(fam), ctypes.byref(nq)))
+        self.quad_family, self.n_quad = fam.value, nq.value
+
+    @property
+    def quad_family_name(self) -> str:
+        """'symmetric' or 'conical' (the oracle's names for the two rule families)."""
+        return "symmetric" if self.quad_family == QUAD_SYMMETRIC else "conical"
 
     @classmethod
     def from_mesh(cls, form: int, mesh, quad_degree: int, params=()):
@@ -231,9 +244,7 @@ class Plan:
 
     def set_quadrature(self, family: int):
         _check(lib().fem_plan_set_quadrature(self.handle, family))
-        nq = ctypes.c_int()
-        _check(lib().fem_plan_info(self.handle, None, None, ctypes.byref(nq), None, None))
-        self.n_quad = nq.value
+        self._read_quadrature()
 
     def set_block(self, cells_per_block: int):
         _check(lib().fem_plan_set_block(self.handle, cells_per_block))

@@ -240,11 +240,11 @@ void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
 {
     const int d = p->dim, nv = d + 1, nloc = p->nloc;
     // --- reference tables
-    // the linear forms integrate polynomials exactly, so the rule with fewest points that
-    // has the requested degree gives the same operator; the neo-Hookean integrand is not
-    // polynomial and keeps the conical rule
-    p->quad_family = (p->form != FEM_NEOHOOKEAN && femx::has_symmetric_rule(d, p->quad_degree))
-                         ? FEM_QUAD_SYMMETRIC : FEM_QUAD_CONICAL;
+    // the fully symmetric rule (fewest points) wherever one is built for the degree, else
+    // the conical rule; for the linear forms both give the same operator, the neo-Hookean
+    // integrand is not polynomial and its operator depends on the rule
+    p->quad_family = femx::has_symmetric_rule(d, p->quad_degree) ? FEM_QUAD_SYMMETRIC
+                                                                  : FEM_QUAD_CONICAL;
     femx::RefTables t = femx::reference_tables(d, p->degree, p->quad_degree, p->quad_family);
     p->nq = t.nq;
     std::vector<double> tab = femx::kernel_table(p->form, t);
@@ -884,6 +884,15 @@ int fem_action_once(int form, int dim, int degree, int quad_degree, int64_t n_ve
     });
     fem_plan_destroy(p);
     return st;
+}
+
+int fem_plan_get_quadrature(const fem_plan *plan, int *family, int *n_points)
+{
+    return guarded([&] {
+        check_plan(plan);
+        if (family) *family = plan->quad_family;
+        if (n_points) *n_points = plan->nq;
+    });
 }
 
 int fem_plan_set_timing(fem_plan *plan, int enable)

@@ -10,7 +10,10 @@
 //
 // Basis: equispaced P_k Lagrange in barycentric product form; the derivative of each
 // factor product is carried along the product recurrence.
+#include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -122,12 +125,249 @@ void conical_rule(int dim, int degree, std::vector<double> &pts, std::vector<dou
     }
 }
 
+// Fully symmetric rules: points on orbits of the simplex's symmetry group, the points of
+// an orbit sharing one weight.  Barycentric orbits of the triangle: S3 (centroid), S21(a)
+// = perms of (a, a, 1-2a), S111(a, b) = perms of (a, b, 1-a-b); of the tetrahedron: S4,
+// S31(a) = perms of (a, a, a, 1-3a), S22(a) = perms of (a, a, 1/2-a, 1/2-a), S211(a, b) =
+// perms of (a, a, b, 1-2a-b).
+enum OrbitKind { S3, S21, S111, S4, S31, S22, S211 };
+
+int orbit_params(int kind)
+{
+    return (kind == S111 || kind == S211) ? 2 : (kind == S3 || kind == S4) ? 0 : 1;
+}
+
+// barycentric coordinates of an orbit's points, appended to lam (dim + 1 per point)
+void orbit_points(int kind, const double *prm, std::vector<double> &lam)
+{
+    auto put = [&](std::initializer_list<double> l) { lam.insert(lam.end(), l); };
+    const double a = prm ? prm[0] : 0.0, b = (prm && orbit_params(kind) == 2) ? prm[1] : 0.0;
+    switch (kind) {
+    case S3: put({1.0 / 3, 1.0 / 3, 1.0 / 3}); break;
+    case S21: {
+        const double c = 1.0 - 2.0 * a;
+        put({a, a, c}); put({a, c, a}); put({c, a, a});
+        break;
+    }
+    case S111: {
+        const double v[3] = {a, b, 1.0 - a - b};
+        const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        for (auto &pm : perm) put({v[pm[0]], v[pm[1]], v[pm[2]]});
+        break;
+    }
+    case S4: put({0.25, 0.25, 0.25, 0.25}); break;
+    case S31: {
+        const double c = 1.0 - 3.0 * a;
+        for (int k = 0; k < 4; ++k)
+            for (int i = 0; i < 4; ++i) lam.push_back(i == k ? c : a);
+        break;
+    }
+    case S22: {
+        const double c = 0.5 - a;
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j)
+                for (int l = 0; l < 4; ++l) lam.push_back(l == i || l == j ? a : c);
+        break;
+    }
+    case S211: {
+        const double c = 1.0 - 2.0 * a - b;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                if (j == i) continue;
+                for (int l = 0; l < 4; ++l) lam.push_back(l == i ? b : l == j ? c : a);
+            }
+        break;
+    }
+    default: break;
+    }
+}
+
+// A rule's orbit structure and approximate parameters: per orbit its parameters, then its
+// weight (weights sum to the reference volume).  Five or more significant digits select
+// the root of the moment equations that Newton's method then solves to full precision.
+struct SymmetricSpec {
+    int dim, degree;
+    std::vector<int> kinds;
+    std::vector<double> guess;
+};
+
+const std::vector<SymmetricSpec> &symmetric_specs()
+{
+    static const std::vector<SymmetricSpec> specs = {
+        // triangle, degree 4: 6 points
+        {2, 4, {S21, S21}, {0.445948, 0.111691, 0.0915762, 0.0549759}},
+        // triangle, degree 6: 12 points
+        {2, 6, {S21, S21, S111}, {0.249287, 0.0583931, 0.0630890, 0.0254225, 0.310352, 0.0531450,
+                                  0.0414255}},
+        // triangle, degree 8: 16 points
+        {2, 8, {S3, S21, S21, S21, S111}, {0.0721578, 0.0505472, 0.0162292, 0.459293, 0.0475458,
+                                           0.170569, 0.0516087, 0.263113, 0.00839478,
+                                           0.0136152}},
+        // triangle, degree 10: 25 points
+        {2, 10, {S3, S21, S21, S111, S111, S111},
+         {0.0416099, 0.0285035, 0.00547564, 0.162913, 0.0263260, 0.153303, 0.0336857, 0.0146614,
+          0.363363, 0.607330, 0.0176975, 0.336696, 0.146812, 0.0281386}},
+        // tetrahedron, degree 5: 14 points
+        {3, 5, {S31, S31, S22}, {0.310886, 0.0187813, 0.0927353, 0.0122488, 0.0455037, 0.00709100}},
+        // tetrahedron, degree 6: 24 points
+        {3, 6, {S31, S31, S31, S211}, {0.214603, 0.00665379, 0.0406740, 0.00167954, 0.322338,
+                                       0.00922620, 0.0636610, 0.269672, 0.00803571}},
+    };
+    return specs;
+}
+
+// exact integral of xi^e over the reference simplex: prod e_i! / (|e| + dim)!
+double monomial_integral(int dim, const int *e)
+{
+    double num = 1.0;
+    int tot = 0;
+    for (int r = 0; r < dim; ++r) {
+        num *= std::tgamma(e[r] + 1.0);
+        tot += e[r];
+    }
+    return num / std::tgamma(tot + dim + 1.0);
+}
+
+void expand(const SymmetricSpec &sp, const std::vector<double> &x, std::vector<double> &pts,
+            std::vector<double> &wts)
+{
+    pts.clear();
+    wts.clear();
+    std::vector<double> lam;
+    size_t i = 0;
+    for (int kind : sp.kinds) {
+        const int np = orbit_params(kind);
+        lam.clear();
+        orbit_points(kind, np ? &x[i] : nullptr, lam);
+        i += np;
+        const double w = x[i++];
+        const int npt = (int)lam.size() / (sp.dim + 1);
+        for (int q = 0; q < npt; ++q) {
+            for (int r = 1; r <= sp.dim; ++r) pts.push_back(lam[q * (sp.dim + 1) + r]);
+            wts.push_back(w);
+        }
+    }
+}
+
+// relative moment errors of the rule x over all monomials of degree <= sp.degree
+void moment_residual(const SymmetricSpec &sp, const std::vector<std::array<int, 3>> &mons,
+                     const std::vector<double> &exact, const std::vector<double> &x,
+                     std::vector<double> &res)
+{
+    std::vector<double> pts, wts;
+    expand(sp, x, pts, wts);
+    res.assign(mons.size(), 0.0);
+    for (size_t m = 0; m < mons.size(); ++m) {
+        double s = 0.0;
+        for (size_t q = 0; q < wts.size(); ++q) {
+            double v = wts[q];
+            for (int r = 0; r < sp.dim; ++r) v *= std::pow(pts[q * sp.dim + r], mons[m][r]);
+            s += v;
+        }
+        res[m] = (s - exact[m]) / exact[m];
+    }
+}
+
+// least-squares solve of the m x n system A dx = b (m >= n) by Householder QR
+std::vector<double> lstsq(std::vector<double> A, std::vector<double> b, int m, int n)
+{
+    for (int k = 0; k < n; ++k) {
+        double nrm = 0.0;
+        for (int i = k; i < m; ++i) nrm += A[i * n + k] * A[i * n + k];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const double alpha = A[k * n + k] > 0 ? -nrm : nrm;
+        std::vector<double> v(m - k);
+        for (int i = k; i < m; ++i) v[i - k] = A[i * n + k];
+        v[0] -= alpha;
+        double vv = 0.0;
+        for (double t : v) vv += t * t;
+        if (vv == 0.0) continue;
+        for (int j = k; j < n; ++j) {
+            double d = 0.0;
+            for (int i = k; i < m; ++i) d += v[i - k] * A[i * n + j];
+            d *= 2.0 / vv;
+            for (int i = k; i < m; ++i) A[i * n + j] -= d * v[i - k];
+        }
+        double d = 0.0;
+        for (int i = k; i < m; ++i) d += v[i - k] * b[i];
+        d *= 2.0 / vv;
+        for (int i = k; i < m; ++i) b[i] -= d * v[i - k];
+    }
+    std::vector<double> x(n, 0.0);
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * x[j];
+        x[k] = A[k * n + k] != 0.0 ? s / A[k * n + k] : 0.0;
+    }
+    return x;
+}
+
+// Solve the moment equations from the spec's approximate parameters by Gauss-Newton
+// (central-difference Jacobian); accept the root only if every monomial of degree <= the
+// rule's degree is integrated to 1e-14 relative, all weights are positive and all points
+// lie in the closed simplex.
+bool solve_symmetric(const SymmetricSpec &sp, std::vector<double> &pts, std::vector<double> &wts)
+{
+    std::vector<std::array<int, 3>> mons;
+    for (int i = 0; i <= sp.degree; ++i)
+        for (int j = 0; i + j <= sp.degree; ++j)
+            if (sp.dim == 2) {
+                mons.push_back({i, j, 0});
+            } else {
+                for (int l = 0; i + j + l <= sp.degree; ++l) mons.push_back({i, j, l});
+            }
+    std::vector<double> exact(mons.size());
+    for (size_t m = 0; m < mons.size(); ++m) exact[m] = monomial_integral(sp.dim, mons[m].data());
+    std::vector<double> x = sp.guess, r, rp, rm;
+    const int n = (int)x.size(), m = (int)mons.size();
+    double prev = 1e300;
+    for (int it = 0; it < 60; ++it) {
+        moment_residual(sp, mons, exact, x, r);
+        double err = 0.0;
+        for (double t : r) err = std::max(err, std::fabs(t));
+        if (err < 1e-15 || (err >= prev && it > 8)) break;
+        prev = err;
+        std::vector<double> J((size_t)m * n);
+        for (int k = 0; k < n; ++k) {
+            const double h = 1e-7 * std::max(1e-2, std::fabs(x[k]));
+            std::vector<double> xp = x, xm = x;
+            xp[k] += h;
+            xm[k] -= h;
+            moment_residual(sp, mons, exact, xp, rp);
+            moment_residual(sp, mons, exact, xm, rm);
+            for (int i = 0; i < m; ++i) J[(size_t)i * n + k] = (rp[i] - rm[i]) / (2.0 * h);
+        }
+        std::vector<double> negr(m);
+        for (int i = 0; i < m; ++i) negr[i] = -r[i];
+        const std::vector<double> dx = lstsq(J, negr, m, n);
+        for (int k = 0; k < n; ++k) x[k] += dx[k];
+    }
+    moment_residual(sp, mons, exact, x, r);
+    for (double t : r)
+        if (!(std::fabs(t) < 1e-14)) return false;
+    expand(sp, x, pts, wts);
+    for (double w : wts)
+        if (!(w > 0.0)) return false;
+    for (size_t q = 0; q < wts.size(); ++q) {
+        double s = 0.0;
+        for (int r2 = 0; r2 < sp.dim; ++r2) {
+            const double xi = pts[q * sp.dim + r2];
+            if (xi < -1e-15) return false;
+            s += xi;
+        }
+        if (s > 1.0 + 1e-15) return false;
+    }
+    return true;
+}
+
 // Fully symmetric rules of degree <= 2 from their moment equations (closed form).
 //   degree <= 1: the centroid, weight |T|.
 //   degree 2, triangle: the orbit of (a, b, b), a = 1 - 2b, weight |T|/3 each; matching
 //     int lambda_1^2 = |T|/6 gives 6b^2 - 4b + 1/2 = 0, b = 1/6 (the interior root).
 //   degree 2, tetrahedron: the orbit of (a, b, b, b), a = 1 - 3b, weight |T|/4 each;
 //     int lambda_1^2 = |T|/10 gives 12b^2 - 6b + 3/5 = 0, b = (5 - sqrt 5)/20.
+// Higher degrees: the solved orbit rule of the smallest tabulated degree >= degree.
 // Returns false when no such rule is built for (dim, degree).
 bool symmetric_rule(int dim, int degree, std::vector<double> &pts, std::vector<double> &wts)
 {
@@ -139,18 +379,37 @@ bool symmetric_rule(int dim, int degree, std::vector<double> &pts, std::vector<d
         wts.push_back(vol);
         return true;
     }
-    if (degree != 2) return false;
-    double b;
-    if (dim == 2) {
-        b = (4.0 - std::sqrt(16.0 - 12.0)) / 12.0;            // roots of 6b^2 - 4b + 1/2
-    } else {
-        b = (6.0 - std::sqrt(36.0 - 4.0 * 12.0 * 0.6)) / 24.0; // roots of 12b^2 - 6b + 3/5
+    if (degree == 2) {
+        double b;
+        if (dim == 2) {
+            b = (4.0 - std::sqrt(16.0 - 12.0)) / 12.0;            // roots of 6b^2 - 4b + 1/2
+        } else {
+            b = (6.0 - std::sqrt(36.0 - 4.0 * 12.0 * 0.6)) / 24.0; // roots of 12b^2 - 6b + 3/5
+        }
+        const double a = 1.0 - dim * b;
+        for (int k = 0; k <= dim; ++k) {          // the point with barycentric a in slot k
+            for (int r = 0; r < dim; ++r) pts.push_back(r + 1 == k ? a : b);
+            wts.push_back(vol / (dim + 1));
+        }
+        return true;
     }
-    const double a = 1.0 - dim * b;
-    for (int k = 0; k <= dim; ++k) {          // the point with barycentric a in slot k
-        for (int r = 0; r < dim; ++r) pts.push_back(r + 1 == k ? a : b);
-        wts.push_back(vol / (dim + 1));
+    // solved rules are cached: plan creation may ask for one many times
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, std::pair<std::vector<double>, std::vector<double>>> cache;
+    const SymmetricSpec *spec = nullptr;
+    for (const auto &sp : symmetric_specs())
+        if (sp.dim == dim && sp.degree >= degree && (!spec || sp.degree < spec->degree)) spec = &sp;
+    if (!spec) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dim, spec->degree);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        std::vector<double> p, w;
+        if (!solve_symmetric(*spec, p, w)) return false;
+        it = cache.emplace(key, std::make_pair(p, w)).first;
     }
+    pts = it->second.first;
+    wts = it->second.second;
     return true;
 }
 

@@ -7,7 +7,7 @@
 // timed with HIP events on the caller's stream using the paper's protocol (Sec. 6.2.1): five warm-up runs, then timed runs until 15 have been collected
 // or 0.2 s has accumulated, the arithmetic mean being the candidate's time.  Results can
 // be kept in a small JSON cache keyed by device architecture, form, dimension, degree,
-// quadrature degree and log2 of the cell count, which fem_plan_create consults when the
+// quadrature degree and rule family, and log2 of the cell count, which fem_plan_create consults when the
 // environment variable FEM_TUNE_CACHE names the file.
 #include <hip/hip_runtime_api.h>
 
@@ -44,7 +44,7 @@ std::string cache_key(const fem_plan *p)
     const int bucket = p->n_cell > 0 ? (int)std::lround(std::log2((double)p->n_cell)) : 0;
     std::ostringstream k;
     k << arch_name() << "/f" << p->form << "/d" << p->dim << "/k" << p->degree << "/q"
-      << p->quad_degree << "/c" << bucket;
+      << p->quad_degree << (p->quad_family == FEM_QUAD_SYMMETRIC ? "s" : "c") << "/c" << bucket;
     return k.str();
 }
 

@@ -143,20 +143,34 @@ def test_patch_layout_rejects_bad_size():
         fx.check_patch_layout(0, m, 300)
 
 
-@pytest.mark.parametrize("dim,deg", [(2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2)])
+SYM_DEGREES = [(2, d) for d in range(0, 11)] + [(3, d) for d in range(0, 7)]
+
+
+@pytest.mark.parametrize("dim,deg", SYM_DEGREES)
 def test_symmetric_rules_exact(dim, deg):
+    """The library's symmetric rules: exact on every monomial up to the degree, positive
+    weights, points inside, and the same point set as the oracle's independently solved
+    rule (both solve the moment equations; the NH operator depends on the rule)."""
     import itertools
     import math
     pts, w, phi, dphi = fx.reference_tables(dim, 2, deg, fx.QUAD_SYMMETRIC)
-    assert len(w) == {0: 1, 1: 1, 2: dim + 1}[deg]
     assert np.all(w > 0) and np.all(pts > 0) and np.all(pts.sum(1) < 1)
     for b in itertools.product(range(deg + 1), repeat=dim):
         if sum(b) > deg:
             continue
         ref = math.prod(math.factorial(x) for x in b) / math.factorial(sum(b) + dim)
-        assert abs(np.sum(w * np.prod(pts ** np.asarray(b), axis=1)) - ref) <= 1e-15 * ref
+        assert abs(np.sum(w * np.prod(pts ** np.asarray(b), axis=1)) - ref) <= 2e-14 * ref
+    opts, ow = quadrature.symmetric(dim, deg)
+    assert len(ow) == len(w)
+    ka, kb = np.lexsort(np.c_[pts, w].T[::-1]), np.lexsort(np.c_[opts, ow].T[::-1])
+    # the same root to the conditioning of the moment equations (~1e-13 at degree 10)
+    assert np.max(np.abs(pts[ka] - opts[kb])) < 5e-13 and np.max(np.abs(w[ka] - ow[kb])) < 5e-14
     # tabulation at the symmetric points agrees with the oracle's basis at the same points
     ophi, odphi = basis.tabulate(dim, 2, pts)
     assert np.max(np.abs(phi - ophi)) < 1e-14 and np.max(np.abs(dphi - odphi)) < 1e-13
+
+
+@pytest.mark.parametrize("dim,deg", [(2, 30), (3, 30)])
+def test_symmetric_rule_missing_degree_is_unsupported(dim, deg):
     with pytest.raises(fx.FemError):
-        fx.reference_tables(dim, 2, 3, fx.QUAD_SYMMETRIC)
+        fx.reference_tables(dim, 2, deg, fx.QUAD_SYMMETRIC)

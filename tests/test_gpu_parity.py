@@ -67,6 +67,12 @@ CASES = [(f, 2, k) for f in (0, 1, 2) for k in range(1, 7)] + \
         [(f, 3, k) for f in (0, 1, 2) for k in range(1, 5)]
 
 
+def plan_family(w):
+    """The rule family a plan picks for this workload: the symmetric rule where one is
+    built for the degree (the library's documented default), else the conical rule."""
+    return "symmetric" if oracle.quadrature.has_symmetric(w.mesh.dim, w.quad_degree) else "conical"
+
+
 STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_ELEMENT),
           (fx.SCATTER_PATCH, 128, 1, fx.SUM_COLOURED), (fx.SCATTER_COLOUR, 0, 0, 0),
           (fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 63, 3, fx.SUM_COLOURED)]
@@ -91,7 +97,7 @@ def test_action_small_meshes(form, dim, k, strategy):
     plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
     apply_strategy(plan, strategy, form, dim)
     y = plan.action(gpu(u)).cpu().numpy()
-    ref = oracle.action(form, mesh, u, qd, params_for(form))
+    ref = oracle.action(form, mesh, u, qd, params_for(form), family=plan.quad_family_name)
     emax, el2 = rel_err(y, ref)
     assert emax < TOL and el2 < TOL, (emax, el2)
 
@@ -107,7 +113,7 @@ def test_vjp_small_meshes(form, dim, k, strategy):
     plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
     apply_strategy(plan, strategy, form, dim)
     g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
-    ref = oracle.vjp(form, mesh, u, v, qd, params_for(form))
+    ref = oracle.vjp(form, mesh, u, v, qd, params_for(form), family=plan.quad_family_name)
     emax, el2 = rel_err(g, ref)
     assert emax < TOL and el2 < TOL, (emax, el2)
 
@@ -119,7 +125,7 @@ def test_action_once_matches_oracle(name):
     m = w.mesh
     y = fx.action_once(w.form, m.dim, m.k, w.quad_degree, m.coords, m.cell_verts, m.cell_nodes,
                        m.n_node, w.params, gpu(w.u)).cpu().numpy()
-    ref = oracle.action(w.form, m, w.u, w.quad_degree, w.params)
+    ref = oracle.action(w.form, m, w.u, w.quad_degree, w.params, family=plan_family(w))
     emax, el2 = rel_err(y, ref)
     assert emax < TOL and el2 < TOL, (emax, el2)
 
@@ -141,6 +147,22 @@ def test_kernel_timing_counts_calls_and_leaves_results(strategy):
     plan.set_timing(False)
     plan.action(u)
     assert plan.timing() == (0.0, 0)
+
+
+@pytest.mark.parametrize("form,dim,k", [c for c in CASES if c[0] == fx.FORM_NEOHOOKEAN])
+def test_conical_rule_parity(form, dim, k):
+    """The neo-Hookean operator depends on the rule: both families against the oracle."""
+    n = 7 if dim == 2 else 2
+    mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(300 + k))
+    u, v = inputs(form, mesh, 70 + k)
+    qd = qdeg(form, k)
+    plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    plan.set_quadrature(fx.QUAD_CONICAL)
+    say(f"[conical] form={form} dim={dim} k={k} nq={plan.n_quad}")
+    y = plan.action(gpu(u)).cpu().numpy()
+    g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
+    assert max(rel_err(y, oracle.action(form, mesh, u, qd, params_for(form), family="conical"))) < TOL
+    assert max(rel_err(g, oracle.vjp(form, mesh, u, v, qd, params_for(form), family="conical"))) < TOL
 
 
 @pytest.mark.parametrize("block", [64, 128, 256])
@@ -196,7 +218,7 @@ def test_empty_mesh_and_unused_nodes():
     plan.action(gpu(u), out=out)
     y = out.cpu().numpy()
     assert np.all(y[-2 * extra:] == 0)
-    ref = oracle.action(1, mesh, u[:-2 * extra], 2, LAME)
+    ref = oracle.action(1, mesh, u[:-2 * extra], 2, LAME, family=plan.quad_family_name)
     assert rel_err(y[:-2 * extra], ref)[0] < TOL
 
 
@@ -210,7 +232,7 @@ def test_single_cell_and_ragged_counts():
         say(f"[ragged] mass P3 n={n} cells={mesh.n_cell}")
         plan = fx.Plan.from_mesh(0, mesh, 6)
         y = plan.action(gpu(u)).cpu().numpy()
-        ref = oracle.action(0, mesh, u, 6)
+        ref = oracle.action(0, mesh, u, 6, family=plan.quad_family_name)
         assert rel_err(y, ref)[0] < TOL
 
 
@@ -227,16 +249,18 @@ def test_full_size_against_oracle(name, strategy):
     if name not in _ref_cache:
         _ref_cache.clear()
         w = meshgen.workload(name)
+        fam = plan_family(w)
         if w.form == fx.FORM_NEOHOOKEAN:
-            assert oracle.min_det_f(w.mesh, w.u, w.quad_degree) > 0.5
+            assert oracle.min_det_f(w.mesh, w.u, w.quad_degree, family=fam) > 0.5
         if w.v is not None:
-            ref = oracle.vjp(w.form, w.mesh, w.u, w.v, w.quad_degree, w.params)
+            ref = oracle.vjp(w.form, w.mesh, w.u, w.v, w.quad_degree, w.params, family=fam)
         else:
-            ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
+            ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params, family=fam)
         _ref_cache[name] = (w, ref)
     w, ref = _ref_cache[name]
     say(f"[full] {name} cells={w.mesh.n_cell} dofs={w.n_dof} {strategy}")
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    assert plan.quad_family_name == plan_family(w)
     apply_strategy(plan, strategy, w.form, w.mesh.dim)
     if w.v is not None:
         out = plan.vjp(gpu(w.u), gpu(w.v)).cpu().numpy()
@@ -256,10 +280,11 @@ def test_autograd_function_matches_oracle_vjp():
     v = rng.uniform(-1, 1, w.n_dof)
     y = fx.FemAction.apply(u, plan)
     (y * gpu(v)).sum().backward()
-    ref = oracle.vjp(w.form, w.mesh, w.u, v, w.quad_degree, w.params)
+    fam = plan.quad_family_name
+    ref = oracle.vjp(w.form, w.mesh, w.u, v, w.quad_degree, w.params, family=fam)
     assert rel_err(u.grad.cpu().numpy(), ref)[0] < TOL
     assert rel_err(y.detach().cpu().numpy(),
-                   oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params))[0] < TOL
+                   oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params, family=fam))[0] < TOL
 
 
 def test_autograd_gradcheck_tiny():
@@ -308,7 +333,7 @@ def test_tuner_picks_a_candidate_and_keeps_parity(tmp_path):
     if st == fx.SCATTER_PATCH:
         assert (pc, ln, sm) == (int(best[1]), int(best[2]), int(best[4]))
     y = plan.action(u).cpu().numpy()
-    ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
+    ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params, family=plan.quad_family_name)
     assert rel_err(y, ref)[0] < TOL
     assert cache.exists() and "f2/d2/k4/q8" in cache.read_text()
 
@@ -332,7 +357,8 @@ def test_batch_matches_oracle_and_per_mesh():
         b.run(graph=graph)
         torch.cuda.synchronize()
         for w, p, u, y in zip(ws, plans, us, ys):
-            ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params)
+            ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params,
+                                family=p.quad_family_name)
             assert rel_err(y.cpu().numpy(), ref)[0] < TOL, w.name
             assert torch.equal(y, p.action(u)), w.name        # bitwise the per-mesh result
     b.close()

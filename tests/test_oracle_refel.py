@@ -50,6 +50,45 @@ def test_stroud_not_exact_beyond_degree(dim, degree):
     assert max(errs) > 1e-8
 
 
+SYM = [(2, m) for m in range(0, 11)] + [(3, m) for m in range(0, 7)]
+
+
+@pytest.mark.parametrize("dim,degree", SYM)
+def test_symmetric_exactness_and_orbits(dim, degree):
+    """Pin of the symmetric rules: exact on every monomial up to the degree against the
+    closed-form simplex moments, positive weights, points inside, total weight 1/d!, and
+    the point set (with its weights) invariant under every permutation of the barycentric
+    coordinates -- what makes the rule fully symmetric."""
+    pts, w = quadrature.symmetric(dim, degree)
+    assert np.all(w > 0)
+    lam = np.c_[1.0 - pts.sum(1), pts]
+    assert np.all(lam > 0)
+    assert abs(w.sum() - 1.0 / math.factorial(dim)) < 1e-15
+    for b in monomials(dim, degree):
+        val = np.sum(w * np.prod(pts ** np.asarray(b), axis=1))
+        assert abs(val - dirichlet(b)) <= 2e-14 * dirichlet(b), b
+    key = sorted(tuple(np.round(np.r_[l, wq], 12)) for l, wq in zip(lam, w))
+    for perm in itertools.permutations(range(dim + 1)):
+        key_p = sorted(tuple(np.round(np.r_[l[list(perm)], wq], 12)) for l, wq in zip(lam, w))
+        assert key_p == key, perm
+
+
+@pytest.mark.parametrize("dim,degree", [(2, 4), (2, 8), (3, 5)])
+def test_symmetric_not_exact_beyond_degree(dim, degree):
+    pts, w = quadrature.symmetric(dim, degree)
+    errs = [abs(np.sum(w * np.prod(pts ** np.asarray(b), axis=1)) - dirichlet(b))
+            for b in monomials(dim, degree + 2) if sum(b) > degree]
+    assert max(errs) > 1e-10
+
+
+def test_symmetric_point_counts():
+    # fewer points than the conical rule of the same degree, as the paper's tables suggest
+    counts = {(2, 4): 6, (2, 6): 12, (2, 8): 16, (2, 10): 25, (3, 2): 4, (3, 5): 14, (3, 6): 24}
+    for (dim, deg), n in counts.items():
+        assert len(quadrature.symmetric(dim, deg)[1]) == n
+        assert n < len(quadrature.stroud(dim, deg)[1])
+
+
 def _vandermonde_basis(dim, k):
     nodes = np.asarray(basis.lattice(dim, k), dtype=float) / k
     mons = [b for b in monomials(dim, k)]
