@@ -148,11 +148,14 @@ def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default"):
     tuned = None
     if tune:
         res = plan.tune(u, y=y, v=v)
-        best = min(res, key=lambda r: r[5])
-        tuned = {"strategy": "patch" if best[0] == 1 else "colour", "cells_per_patch": int(best[1]),
-                 "lanes_per_cell": int(best[2]), "block": int(best[3]),
-                 "sum_mode": {1: "element", 2: "coloured"}.get(int(best[4]), "-"),
-                 "tuner_ms": best[5], "candidates": len(res)}
+        st = plan.strategy()          # what the tuner applied (the entry config wins ties)
+        mine = [r for r in res if int(r[0]) == st[0] and (st[0] == 0 or (int(r[1]), int(r[2]),
+                int(r[4])) == (st[1], st[2], st[3]))]
+        tuned = {"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
+                 "lanes_per_cell": st[2],
+                 "sum_mode": {1: "element", 2: "coloured"}.get(st[3], "-"),
+                 "tuner_ms": float(min(r[5] for r in mine)) if mine else None,
+                 "fastest_candidate_ms": float(min(r[5] for r in res)), "candidates": len(res)}
     return plan, u, v, y, tuned
 
 
@@ -241,16 +244,15 @@ def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
             if k not in kinds or w.mesh.n_cell > ws[kinds[k]].mesh.n_cell:
                 kinds[k] = i
         for k, i in kinds.items():
-            res = plans[i].tune(us[i], y=ys[i])
-            best = min(res, key=lambda r: r[5])
-            tuned[k] = [int(best[0]), int(best[1]), int(best[2]), int(best[3]), int(best[4])]
+            plans[i].tune(us[i], y=ys[i])
+            st = plans[i].strategy()
+            tuned[k] = list(st)
             for j, w in enumerate(ws):
                 if w.name.split("_", 1)[1] == k and j != i:
-                    if best[0] == 1:
-                        plans[j].set_strategy(1, int(best[1]), int(best[2]), int(best[4]))
+                    if st[0] == 1:
+                        plans[j].set_strategy(1, st[1], st[2], st[3])
                     else:
                         plans[j].set_strategy(0)
-                        plans[j].set_block(int(best[3]))
     per_mesh = lambda: [p.action(u, out=y) for p, u, y in zip(plans, us, ys)]  # noqa: E731
     ms_each, _ = time_steps(per_mesh, steps, warmup)
     # each mesh alone, to split out launch overhead

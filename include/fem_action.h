@@ -230,16 +230,18 @@ int fem_plan_get_timing(fem_plan *plan, double *kernel_ms, int64_t *calls);
 /*
  * Autotuner: time every launch configuration of the plan on the caller's vectors and keep
  * the fastest on the plan.  Candidates: the colour strategy with 64/128/256 cells per
- * workgroup; the patch strategy with 64/128/256 cells per patch and 1 or (2D vector forms)
- * 2 lanes per cell.  Timing follows the paper's protocol (Sec. 6.2.1): 5 warm-up runs,
+ * workgroup; the patch strategy with 64/128/256 cells per patch and one lane per cell,
+ * 64/128 with lane pairs (2D vector forms), 42/63/84 with lane triples (3D vector forms),
+ * each with both sum modes.  The configuration the plan had on entry is kept unless a
+ * candidate is more than 3% faster.  Timing follows the paper's protocol (Sec. 6.2.1): 5 warm-up runs,
  * then timed runs until 15 are collected or 0.2 s accumulates, arithmetic mean, HIP
  * events on `stream`.  Synchronises; may rebuild the plan's patches (host work).
  *   u, v   DEVICE inputs (v only for vjp != 0, which tunes fem_action_vjp instead)
  *   y      DEVICE scratch output of n_dof doubles (overwritten)
  *   cache_path  HOST path of a JSON cache to update (NULL: none).  fem_plan_create applies
  *          a cached configuration when the environment variable FEM_TUNE_CACHE names the
- *          file.  Keys: device architecture, form, dimension, degree, quadrature degree,
- *          round(log2(cell count)).
+ *          file.  Keys: device architecture, form, dimension, degree, quadrature degree
+ *          and rule family, round(log2(cell count)).
  *   results HOST f64 [max_results][6] out: strategy, cells per patch, lanes per cell,
  *          cells per workgroup (colour), sum mode, mean milliseconds; n_results HOST out.
  * Errors: FEM_E_ARG, FEM_E_HIP, FEM_E_NOMEM.
