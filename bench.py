@@ -346,7 +346,9 @@ def main():
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 5}))
+        ms, _ = time_steps(lambda: dst.copy_(src), 20, 0)
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 25,
+                          "copy_gbs_read_plus_write": 2 * n * 8 / (ms / 1e3) / 1e9}))
         return
     tune = not args.no_tune
 

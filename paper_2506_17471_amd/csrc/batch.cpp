@@ -82,6 +82,7 @@ femx::PatchArgs patch_args(const fem_plan *p, const double *u, double *y)
     a.patch_nodes = p->d_patch_nodes;
     a.patch_nint = p->d_patch_nint;
     a.patch_pbase = p->d_patch_pbase;
+    a.pdest = p->d_pdest;
     a.patch_ncol = p->d_patch_ncol;
     a.csr_off = p->d_csr_off;
     a.csr_slots = p->d_csr_slots;
@@ -221,7 +222,6 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
                 femx::FixDesc f{};
                 f.fix_node = p->d_fix_node;
                 f.fix_off = p->d_fix_off;
-                f.fix_slot = p->d_fix_slot;
                 f.partial = p->d_partial;
                 f.first = b->n_fix;
                 f.ncomp = p->ncomp;

@@ -69,7 +69,8 @@ struct PatchArgs {
     const int32_t *patch_off;   // [n_patch + 1] into the (patch, node) list
     const int32_t *patch_nodes; // global node id of each (patch, node): interior ones first
     const int32_t *patch_nint;  // [n_patch] interior (unshared) nodes of each patch
-    const int32_t *patch_pbase; // [n_patch] first partial slot of each patch's shared nodes
+    const int32_t *patch_pbase; // [n_patch] first entry of each patch's shared nodes in pdest
+    const int32_t *pdest;       // [n_partial] node-major partial slot of (patch, shared node)
     const uint8_t *patch_ncol;  // [n_patch] sub-colours of each patch
     const int32_t *csr_off;     // [n_pn + 1] element-buffer slots summed into (patch, node)
     const uint16_t *csr_slots;  // slot = a << 8 | local cell, in ascending (cell, a)
@@ -99,7 +100,6 @@ struct BatchDesc {
 struct FixDesc {
     const int32_t *fix_node;
     const int32_t *fix_off;
-    const int32_t *fix_slot;
     const double *partial;
     double *y;
     int64_t first;           // index of the mesh's first (shared node, component) item
@@ -141,7 +141,8 @@ struct fem_plan {
     int32_t *d_patch_nint = nullptr, *d_patch_pbase = nullptr;
     int32_t *d_csr_off = nullptr;
     uint16_t *d_csr_slots = nullptr;
-    int32_t *d_fix_node = nullptr, *d_fix_off = nullptr, *d_fix_slot = nullptr;
+    int32_t *d_fix_node = nullptr, *d_fix_off = nullptr;
+    int32_t *d_pdest = nullptr;          // node-major partial slot of each (patch, shared node)
     double *d_partial = nullptr;
     int64_t pstride = 0;
     std::vector<double> h_coords;        // host copies, to rebuild patches on request
@@ -181,7 +182,7 @@ void run_action(const fem_plan *p, const double *u, const double *v, double *y, 
 void apply_tuning_cache(fem_plan *p);
 int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
          hipStream_t s, double *results, int max_results, int *n_results);
-hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, const int32_t *fix_slot,
+hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off,
                         int64_t n_shared, const double *partial, int ncomp, double *y,
                         hipStream_t s);
 }  // namespace femx

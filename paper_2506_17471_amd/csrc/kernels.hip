@@ -322,7 +322,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 #pragma unroll
             for (int c = 0; c < NC; ++c) a.y[nd * NC + c] = sum[c];
         } else {
-            const int64_t dest = pbase + (j - nint);
+            const int64_t dest = a.pdest[pbase + (j - nint)];
 #pragma unroll
             for (int c = 0; c < NC; ++c) a.partial[dest * NC + c] = sum[c];
         }
@@ -384,15 +384,15 @@ __global__ void batch_fixup_kernel(const FixDesc *__restrict__ fix, int n_mesh, 
     const int64_t nd = f.fix_node[k];
     const int o0 = f.fix_off[k], o1 = f.fix_off[k + 1];
     double s = 0.0;
-    for (int o = o0; o < o1; ++o) s += f.partial[(int64_t)f.fix_slot[o] * f.ncomp + c];
+    for (int o = o0; o < o1; ++o) s += f.partial[(int64_t)o * f.ncomp + c];
     f.y[nd * f.ncomp + c] = s;
 }
 
-// thread i sums component i % ncomp of shared node i / ncomp over its partials (slots
-// listed in patch order)
+// thread i sums component i % ncomp of shared node i / ncomp over its partials, which lie
+// contiguously in node-major order (one per holding patch, in patch order)
 __global__ void fixup_kernel(const int32_t *__restrict__ fix_node, const int32_t *__restrict__ fix_off,
-                             const int32_t *__restrict__ fix_slot, int64_t n,
-                             const double *__restrict__ partial, int ncomp, double *__restrict__ y)
+                             int64_t n, const double *__restrict__ partial, int ncomp,
+                             double *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * ncomp) return;
@@ -401,7 +401,7 @@ __global__ void fixup_kernel(const int32_t *__restrict__ fix_node, const int32_t
     const int64_t nd = fix_node[k];
     const int o0 = fix_off[k], o1 = fix_off[k + 1];
     double s = 0.0;
-    for (int o = o0; o < o1; ++o) s += partial[(int64_t)fix_slot[o] * ncomp + c];
+    for (int o = o0; o < o1; ++o) s += partial[(int64_t)o * ncomp + c];
     y[nd * ncomp + c] = s;
 }
 
@@ -596,14 +596,13 @@ hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, const int32_t *fix_slot,
-                        int64_t n_shared, const double *partial, int ncomp, double *y,
-                        hipStream_t s)
+hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t n_shared,
+                        const double *partial, int ncomp, double *y, hipStream_t s)
 {
     const int block = 256;
     const int64_t grid = (n_shared * ncomp + block - 1) / block;
     hipLaunchKernelGGL(fixup_kernel, dim3((unsigned)grid), dim3(block), 0, s, fix_node, fix_off,
-                       fix_slot, n_shared, partial, ncomp, y);
+                       n_shared, partial, ncomp, y);
     return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ void free_patch_memory(fem_plan *p)
     (void)hipFree(p->d_patch_pbase);
     (void)hipFree(p->d_patch_ncol);
     (void)hipFree(p->d_colour);
-    (void)hipFree(p->d_fix_slot);
+    (void)hipFree(p->d_pdest);
     (void)hipFree(p->d_csr_off);
     (void)hipFree(p->d_csr_slots);
     (void)hipFree(p->d_fix_node);
@@ -95,7 +95,7 @@ void free_patch_memory(fem_plan *p)
     p->d_patch_off = p->d_patch_nodes = p->d_patch_nint = p->d_patch_pbase = p->d_csr_off = nullptr;
     p->d_patch_ncol = nullptr;
     p->d_colour = nullptr;
-    p->d_fix_slot = nullptr;
+    p->d_pdest = nullptr;
     p->d_csr_slots = nullptr;
     p->d_fix_node = p->d_fix_off = nullptr;
     p->d_partial = nullptr;
@@ -350,9 +350,10 @@ std::vector<int64_t> morton_order(const fem_plan *p, const double *coords, const
 // Patch strategy data: cells along the Morton curve cut into patches of P cells.  Per patch
 // its distinct nodes -- first those no other patch holds (interior, ascending id), then the
 // shared ones (ascending id) -- and per cell the patch-local index of each of its nodes.
-// A shared node's sum leaves the patch as a partial in a slot of the patch's contiguous
-// partial range (base + position among the patch's shared nodes); the fixup kernel adds a
-// node's partials in patch order.
+// A shared node's sum leaves the patch as a partial.  Partial slots are node-major: the
+// holders of shared node k fill slots fix_off[k] .. fix_off[k+1] in patch order, so the
+// fixup kernel reads each node's partials contiguously; the patch finds the slot of its
+// j-th shared node in pdest[base + j].
 // Two ways to sum inside a patch:
 //   element buffer: every cell vector goes to LDS and each node sums its slots (the CSR
 //     lists below, in ascending (cell, local node));
@@ -363,7 +364,7 @@ struct PatchLayout {
     int64_t n_patch = 0, stride = 0;
     std::vector<int64_t> order;
     std::vector<int32_t> pverts, patch_off, patch_nodes, patch_nint, patch_pbase, csr_off;
-    std::vector<int32_t> fix_node, fix_off, fix_slot;
+    std::vector<int32_t> fix_node, fix_off, pdest;
     std::vector<uint16_t> lidx, csr_slots;
     std::vector<uint8_t> colour, patch_ncol;
 };
@@ -401,7 +402,7 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
             L.fix_node.push_back((int32_t)n);
             L.fix_off.push_back(L.fix_off.back() + node_count[n]);
         }
-    L.fix_slot.assign((size_t)L.fix_off.back(), -1);
+    L.pdest.assign((size_t)L.fix_off.back(), -1);
     std::vector<int32_t> fix_fill(L.fix_node.size(), 0);
 
     // pass 2: per patch node order, local indices, CSR, sub-colours
@@ -435,7 +436,7 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
         L.patch_pbase[pt] = pbase;
         for (int j = nint; j < U; ++j) {
             const int32_t k = fix_index[nodes[j]];
-            L.fix_slot[L.fix_off[k] + fix_fill[k]++] = pbase + (j - nint);
+            L.pdest[pbase + (j - nint)] = L.fix_off[k] + fix_fill[k]++;
         }
         pbase += U - nint;
         // local index of every (cell, a)
@@ -524,8 +525,10 @@ void validate_patch_layout(const fem_plan *p, const PatchLayout &L, const int32_
                 seen = 1;
             }
             if (j >= nint) {
-                const int64_t dest = (int64_t)L.patch_pbase[pt] + (j - nint);
-                if (dest >= (int64_t)partial_writer.size()) bad("partial slot range");
+                const int64_t e = (int64_t)L.patch_pbase[pt] + (j - nint);
+                if (e >= (int64_t)L.pdest.size()) bad("partial entry range");
+                const int64_t dest = L.pdest[e];
+                if (dest < 0 || dest >= (int64_t)partial_writer.size()) bad("partial slot range");
                 if (partial_writer[dest] >= 0) bad("partial slot written twice");
                 partial_writer[dest] = nd;
             }
@@ -552,11 +555,8 @@ void validate_patch_layout(const fem_plan *p, const PatchLayout &L, const int32_
     for (size_t k = 0; k < L.fix_node.size(); ++k) {
         const int32_t nd = L.fix_node[k];
         if (holders[nd] != L.fix_off[k + 1] - L.fix_off[k]) bad("fixup count");
-        for (int o = L.fix_off[k]; o < L.fix_off[k + 1]; ++o) {
-            const int32_t sl = L.fix_slot[o];
-            if (sl < 0 || sl >= (int32_t)partial_writer.size() || partial_writer[sl] != nd)
-                bad("fixup reads a foreign partial");
-        }
+        for (int o = L.fix_off[k]; o < L.fix_off[k + 1]; ++o)
+            if (partial_writer[o] != nd) bad("fixup reads a foreign partial");
     }
     for (int32_t w : partial_writer)
         if (w < 0) bad("partial slot never written");
@@ -600,7 +600,7 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
     p->d_csr_slots = device_upload(L.csr_slots, "patch csr slots");
     p->d_fix_node = device_upload(L.fix_node, "shared nodes");
     p->d_fix_off = device_upload(L.fix_off, "shared offsets");
-    p->d_fix_slot = device_upload(L.fix_slot, "shared slots");
+    p->d_pdest = device_upload(L.pdest, "partial destinations");
     if (p->n_partial > 0) {
         std::vector<double> zeros((size_t)p->n_partial * p->ncomp, 0.0);
         p->d_partial = device_upload(zeros, "partials");
@@ -680,6 +680,7 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         a.patch_nodes = p->d_patch_nodes;
         a.patch_nint = p->d_patch_nint;
         a.patch_pbase = p->d_patch_pbase;
+        a.pdest = p->d_pdest;
         a.patch_ncol = p->d_patch_ncol;
         a.csr_off = p->d_csr_off;
         a.csr_slots = p->d_csr_slots;
@@ -707,7 +708,7 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
             p->timing_pending.push_back(ev);
         }
         if (p->n_shared > 0)
-            femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off, p->d_fix_slot,
+            femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off,
                                                p->n_shared, p->d_partial, p->ncomp, y, s),
                             "fixup launch");
         return;

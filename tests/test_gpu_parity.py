@@ -183,7 +183,7 @@ def test_determinism_and_stream(strategy):
     w = meshgen.workload("elast_p2_3d", n=6)
     say(f"[determinism] elast_p2_3d n=6 {strategy}")
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
-    plan.set_strategy(*strategy)
+    apply_strategy(plan, strategy, w.form, w.mesh.dim)
     u = gpu(w.u)
     y0 = plan.action(u)
     torch.cuda.synchronize()
