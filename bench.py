@@ -44,20 +44,28 @@ def flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
     geo_q = 2 * d ** 3 + (2 * d ** 3 + d * d) + 1   # G = gref K, T = W S K^T, W
     if form == 1:
         pw = d + 3 * d * d + d           # trace, mu (G + G^T), lam tr on diagonal
-    else:
+    elif form == 2:
         inv = 3 + 1 + 4 if d == 2 else 17 + 1 + 45
         pw = d + inv + 1 + 2 + 2 * d * d  # F = I + G, inverse, log, lam ln J - mu, P
+    else:
+        # SVK: F = I + G, F^T F (sym), tr E, S = lam trE I + 2 mu E, P = F S
+        pw = d + d * (d + 1) * d + 2 * d + d * (d + 1) + 2 * d ** 3
     return geo + nq * (ev + ct + geo_q + pw)
 
 
-def vjp_flops_per_cell(dim: int, nloc: int, nq: int) -> float:
+def vjp_flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
+    """The tangent contracted with grad v: neo-Hookean (2) or St Venant-Kirchhoff (3)."""
     d = dim
     geo = 4 + 3 + 1 + 4 + 1 if d == 2 else 9 + 17 + 1 + 45 + 1
     ev = 2 * (2 * d * d * nloc)          # gradients of u and v
     ct = 2 * d * d * nloc
     geo_q = 2 * (2 * d ** 3) + (2 * d ** 3 + d * d) + 1
-    inv = 3 + 1 + 4 if d == 2 else 17 + 1 + 45
-    pw = d + inv + 1 + 2 + 2 * d ** 3 + d + 2 * d ** 3 + 4 * d * d
+    if form == 2:
+        inv = 3 + 1 + 4 if d == 2 else 17 + 1 + 45
+        pw = d + inv + 1 + 2 + 2 * d ** 3 + d + 2 * d ** 3 + 4 * d * d
+    else:
+        # F^T F, F^T H (sym), traces, S and dS, H S + F dS
+        pw = d + 2 * d * (d + 1) * d + 4 * d + 2 * d * (d + 1) + 4 * d ** 3
     return geo + nq * (ev + ct + geo_q + pw)
 
 
@@ -105,7 +113,8 @@ def kernel_source_hash() -> str:
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in ("paper_2506_17471_amd/csrc/forms.h", "paper_2506_17471_amd/csrc/kernels.hip"):
+    for f in ("paper_2506_17471_amd/csrc/forms.h", "paper_2506_17471_amd/csrc/kernel_templates.h",
+              "paper_2506_17471_amd/csrc/kernels.hip"):
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -195,8 +204,8 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
     kernel_ms = time_kernel(plan, fn, steps)
     st = plan.strategy()
     nv = w.mesh.n_vert
-    if vjp and w.form == 2:
-        fl = vjp_flops_per_cell(w.mesh.dim, plan.n_loc, plan.n_quad)
+    if vjp and w.form in (2, 3):
+        fl = vjp_flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad)
     else:
         fl = flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad)
     info = dict(workload=name, vjp=vjp, cold=cold, n_cell=w.mesh.n_cell, n_dof=w.n_dof,
@@ -204,7 +213,7 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
                 tuned=tuned,
                 flops_per_cell=fl, flops=fl * w.mesh.n_cell,
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
-                                      3 if vjp and w.form == 2 else 2),
+                                      3 if vjp and w.form in (2, 3) else 2),
                 ms_mean=float(ms.mean()), kernel_ms=kernel_ms, wall_s=wall,
                 launch={"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
                         "lanes_per_cell": st[2],
@@ -369,6 +378,13 @@ def main():
             info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
             extras[name] = info
             note(f"{name}: {info['ms_mean']:.4f} ms/step")
+        # the paper's hyperelastic law (St Venant-Kirchhoff): residual and tangent action
+        info, _ = run_workload("svk_p4_2d", args.steps, args.warmup, tune=tune)
+        extras["svk_p4_2d"] = info
+        note(f"svk_p4_2d: {info['ms_mean']:.4f} ms/step")
+        info, _ = run_workload("svk_p4_2d", args.steps, args.warmup, vjp=True, tune=tune)
+        extras["svk_p4_2d_tangent"] = info
+        note(f"svk_p4_2d tangent: {info['ms_mean']:.4f} ms/step")
         if w.form == 2 and args.rule == "default":
             # the same operator family with the conical-product rule (more points)
             info, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule="conical")

@@ -64,6 +64,10 @@ extern "C" {
                              P = mu (F - F^{-T}) + lambda ln(det F) F^{-T}
                              (energy mu/2 (tr F^T F - d) - mu ln J + lambda/2 ln^2 J),
                              params {lambda, mu}                                     */
+#define FEM_SVK 3         /* St Venant-Kirchhoff residual (paper App. A hyperelastic law):
+                             r(u; v) = int F S : grad v,  E = (F^T F - I)/2,
+                             S = lambda tr(E) I + 2 mu E  (energy lambda/2 tr^2 E + mu E:E),
+                             params {lambda, mu}                                     */
 
 /* status codes */
 #define FEM_OK 0
@@ -83,7 +87,7 @@ typedef struct fem_plan fem_plan;
  * and uploads colour-sorted copies of the maps and the coordinates to the current HIP
  * device.  Synchronous; allocates device memory owned by the plan.
  *
- *   form         FEM_MASS, FEM_ELASTICITY or FEM_NEOHOOKEAN
+ *   form         FEM_MASS, FEM_ELASTICITY, FEM_NEOHOOKEAN or FEM_SVK
  *   dim          2 (triangles) or 3 (tetrahedra)
  *   degree       polynomial degree k: 1..6 in 2D, 1..4 in 3D
  *   quad_degree  degree the rule integrates exactly: 0..20
@@ -106,7 +110,7 @@ void fem_plan_destroy(fem_plan *plan);
 
 /*
  * y = A(u): the operator action (paper Sec. 2.3, generic action kernel; App. A forms).
- * For FEM_NEOHOOKEAN this is the nonlinear residual r(u).
+ * For FEM_NEOHOOKEAN and FEM_SVK this is the nonlinear residual r(u).
  *   u  DEVICE f64 [n_node * ncomp]  input
  *   y  DEVICE f64 [n_node * ncomp]  output, overwritten (not accumulated); must not alias u
  * Asynchronous on `stream`.  Errors: FEM_E_ARG (null plan/pointer), FEM_E_HIP (launch).
@@ -115,14 +119,24 @@ void fem_plan_destroy(fem_plan *plan);
 int fem_action(const fem_plan *plan, const double *u, double *y, void *stream);
 
 /*
- * g = (dA/du)^T v: vector-Jacobian product of the action at u.  For FEM_NEOHOOKEAN the
- * tangent of the residual is contracted with grad v at every quadrature point, F being
- * recomputed from u (nothing is stored between the forward and this call).  For the
- * linear forms A is symmetric and independent of u, so g = A v and u is ignored.
+ * g = (dA/du)^T v: vector-Jacobian product of the action at u.  For the hyperelastic forms
+ * (FEM_NEOHOOKEAN, FEM_SVK) the tangent of the residual is contracted with grad v at every
+ * quadrature point, F being recomputed from u (nothing is stored between the forward and
+ * this call).  For the linear forms A is symmetric and independent of u, so g = A v and u
+ * is ignored.
  *   u, v  DEVICE f64 [n_node * ncomp] inputs;  g DEVICE f64 [n_node * ncomp] output,
  *   overwritten; g must alias neither u nor v.  Asynchronous.  Errors as fem_action.
  */
 int fem_action_vjp(const fem_plan *plan, const double *u, const double *v, double *g,
+                   void *stream);
+
+/*
+ * (dA/du) w: the tangent (linearised) action at u applied to w -- the operator the paper
+ * times for its hyperelastic cases.  The hyperelastic tangents have major symmetry, so
+ * this equals fem_action_vjp(plan, u, w) and runs the same kernels; for the linear forms
+ * it is A w.  Arguments and errors as fem_action_vjp.
+ */
+int fem_action_jvp(const fem_plan *plan, const double *u, const double *w, double *out,
                    void *stream);
 
 /*

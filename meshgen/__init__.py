@@ -182,7 +182,7 @@ def nh_displacement(rng, mesh: Mesh, amplitude: float = 0.01) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # The named workloads.  Form ids: 0 mass, 1 linear elasticity, 2 neo-Hookean.
 # ---------------------------------------------------------------------------
-FORM_MASS, FORM_ELAST, FORM_NH = 0, 1, 2
+FORM_MASS, FORM_ELAST, FORM_NH, FORM_SVK = 0, 1, 2, 3
 
 
 def lame_from_young(E: float, nu: float) -> tuple[float, float]:
@@ -222,6 +222,9 @@ _SPECS = {
     "elast_p2_3d": (FORM_ELAST, 3, 64, 2, 2, 0.05, 2, lame_from_young(1.0, 0.3)),
     # VJP of the neo-Hookean residual on the 512^2 P4 mesh
     "nh_vjp_p4_2d": (FORM_NH, 2, 512, 4, 8, 0.1, 3, (10.0, 1.0)),
+    # St Venant-Kirchhoff residual and tangent on the same mesh and rule degree (the
+    # paper's hyperelastic law; its benchmark times the tangent action)
+    "svk_p4_2d": (FORM_SVK, 2, 512, 4, 8, 0.1, 5, (10.0, 1.0)),
 }
 
 
@@ -233,7 +236,7 @@ def workload(name: str, n: int | None = None, seed: int | None = None,
     rng = np.random.default_rng(seed0 if seed is None else seed)
     mesh = make_mesh(dim, n, k, jit, rng)
     ncomp = 1 if form == FORM_MASS else dim
-    if form == FORM_NH:
+    if form in (FORM_NH, FORM_SVK):
         u = nh_displacement(rng, mesh)
     else:
         u = rng.uniform(-1.0, 1.0, size=mesh.n_node * ncomp)

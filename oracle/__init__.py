@@ -10,9 +10,9 @@ Pieces:
 * ``quadrature.symmetric`` -- fully symmetric rules (moment equations, scipy least squares);
 * ``basis.tabulate``     -- Silvester-formula P_k Lagrange values and reference gradients;
 * ``fem_oracle.c``       -- the per-cell loop of the paper's generic action kernel
-  (Sec. 2.3) for the mass, linear elasticity and neo-Hookean forms (App. A), the
-  neo-Hookean VJP written as the literal transpose of the tangent, the discrete
-  energy, and greedy first-fit colouring;
+  (Sec. 2.3) for the mass, linear elasticity, neo-Hookean and St Venant-Kirchhoff forms
+  (App. A), the hyperelastic VJPs written as the literal transpose of the tangent, the
+  discrete energies, and greedy first-fit colouring;
 * ``exact``              -- quadrature-free assembly of mass and elasticity matrices by
   exact integration of barycentric monomials (the brute-force pin).
 
@@ -34,7 +34,7 @@ _SRC = os.path.join(_HERE, "fem_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-FORM_MASS, FORM_ELAST, FORM_NH = 0, 1, 2
+FORM_MASS, FORM_ELAST, FORM_NH, FORM_SVK = 0, 1, 2, 3
 
 
 def build() -> str:
@@ -80,8 +80,8 @@ def _bind(lib):
     lib.oracle_action.restype = None
     lib.oracle_vjp.argtypes = [i32, i32, i32, i32, P, P, P, i64, P, P, P, f64, f64, P, P, P, i64]
     lib.oracle_vjp.restype = None
-    lib.oracle_nh_energy.argtypes = [i32, i32, i32, P, P, i64, P, P, P, f64, f64, P]
-    lib.oracle_nh_energy.restype = f64
+    lib.oracle_energy.argtypes = [i32, i32, i32, i32, P, P, i64, P, P, P, f64, f64, P]
+    lib.oracle_energy.restype = f64
     lib.oracle_min_det_f.argtypes = [i32, i32, i32, P, i64, P, P, P, P]
     lib.oracle_min_det_f.restype = f64
     lib.oracle_colouring.argtypes = [i64, i32, P, i32, P, P]
@@ -171,15 +171,21 @@ def vjp(form: int, mesh, u: np.ndarray, v: np.ndarray, quad_degree: int, params=
     return g
 
 
-def nh_energy(mesh, u: np.ndarray, quad_degree: int, params, family: str = "conical") -> float:
-    """Discrete neo-Hookean energy Pi_h(u)."""
+def energy(form: int, mesh, u: np.ndarray, quad_degree: int, params,
+           family: str = "conical") -> float:
+    """Discrete energy Pi_h(u) of a hyperelastic form (neo-Hookean or St Venant-Kirchhoff)."""
     lib = _load()
     t = tables(mesh.dim, mesh.k, quad_degree, family)
     cv, cn, xy = _mesh_arrays(mesh)
     u = np.ascontiguousarray(u, dtype=np.float64)
     lam, mu = _lam_mu(params)
-    return lib.oracle_nh_energy(mesh.dim, t.nloc, t.nq, _ptr(t.dphi), _ptr(t.weights),
-                                cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u))
+    return lib.oracle_energy(form, mesh.dim, t.nloc, t.nq, _ptr(t.dphi), _ptr(t.weights),
+                             cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u))
+
+
+def nh_energy(mesh, u: np.ndarray, quad_degree: int, params, family: str = "conical") -> float:
+    """Discrete neo-Hookean energy Pi_h(u)."""
+    return energy(FORM_NH, mesh, u, quad_degree, params, family)
 
 
 def min_det_f(mesh, u: np.ndarray, quad_degree: int, family: str = "conical") -> float:

@@ -20,7 +20,9 @@
  *   2 compressible neo-Hookean residual (the paper's hyperelastic residual with the
  *     neo-Hookean energy Psi = mu/2 (tr F^T F - d) - mu ln J + lam/2 (ln J)^2 in place of
  *     St Venant-Kirchhoff, body force 0):  r = int P(F) : grad v,
- *     F = I + grad u,  P = dPsi/dF = mu (F - F^{-T}) + lam ln(det F) F^{-T}.
+ *     F = I + grad u,  P = dPsi/dF = mu (F - F^{-T}) + lam ln(det F) F^{-T};
+ *   3 St Venant-Kirchhoff residual (the paper's hyperelastic law, App. A): E = (F^T F - I)/2,
+ *     S = lam tr(E) I + 2 mu E, P = F S (energy Psi = lam/2 tr(E)^2 + mu E:E).
  *
  * Layouts: coords [n_vert][d]; cell_verts [n_cell][d+1]; cell_nodes [n_cell][nloc];
  * vectors node-major interleaved, value (node, c) at node*ncomp + c;
@@ -30,7 +32,7 @@
 #include <stdint.h>
 #include <string.h>
 
-enum { OR_MASS = 0, OR_ELAST = 1, OR_NH = 2 };
+enum { OR_MASS = 0, OR_ELAST = 1, OR_NH = 2, OR_SVK = 3 };
 
 /* largest local node count handled (P8 triangle: 45, P6 tetrahedron: 84) */
 #define ORACLE_MAX_NLOC 128
@@ -124,7 +126,7 @@ static void stress(int form, int d, double lam, double mu, const double G[3][3],
                 double eps = 0.5 * (G[i][j] + G[j][i]);
                 S[i][j] = 2.0 * mu * eps + (i == j ? lam * tr : 0.0);
             }
-    } else { /* neo-Hookean */
+    } else if (form == OR_NH) {
         double F[3][3], Fi[3][3];
         for (int i = 0; i < d; ++i)
             for (int j = 0; j < d; ++j)
@@ -136,16 +138,55 @@ static void stress(int form, int d, double lam, double mu, const double G[3][3],
                 double FiT = Fi[j][i];
                 S[i][j] = mu * (F[i][j] - FiT) + lam * lnJ * FiT;
             }
+    } else { /* St Venant-Kirchhoff */
+        double F[3][3], E[3][3], S2[3][3], trE = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j)
+                F[i][j] = (i == j ? 1.0 : 0.0) + G[i][j];
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                double c = 0.0;
+                for (int k = 0; k < d; ++k)
+                    c += F[k][i] * F[k][j];
+                E[i][j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
+            }
+        for (int i = 0; i < d; ++i)
+            trE += E[i][i];
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j)
+                S2[i][j] = 2.0 * mu * E[i][j] + (i == j ? lam * trE : 0.0);
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                S[i][j] = 0.0;
+                for (int k = 0; k < d; ++k)
+                    S[i][j] += F[i][k] * S2[k][j];
+            }
     }
 }
 
-/* neo-Hookean strain energy density */
-static double energy_density(int d, double lam, double mu, const double G[3][3])
+/* strain energy density of the hyperelastic forms */
+static double energy_density(int form, int d, double lam, double mu, const double G[3][3])
 {
     double F[3][3], Fi[3][3];
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j)
             F[i][j] = (i == j ? 1.0 : 0.0) + G[i][j];
+    if (form == OR_SVK) {
+        double E[3][3], trE = 0.0, EE = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                double c = 0.0;
+                for (int k = 0; k < d; ++k)
+                    c += F[k][i] * F[k][j];
+                E[i][j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
+            }
+        for (int i = 0; i < d; ++i) {
+            trE += E[i][i];
+            for (int j = 0; j < d; ++j)
+                EE += E[i][j] * E[i][j];
+        }
+        return 0.5 * lam * trE * trE + mu * EE;
+    }
     double detF = inverse(d, F, Fi);
     double lnJ = log(detF);
     double trC = 0.0;
@@ -217,10 +258,12 @@ void oracle_action(int form, int d, int nloc, int nq, const double *phi, const d
 }
 
 /*
- * g = (dA/du)^T v for the neo-Hookean residual, overwriting g.
+ * g = (dA/du)^T v for the hyperelastic residuals, overwriting g.
  * Written literally as the transpose: with the tangent C_ijkl = dP_ij / dF_kl,
  * g_(b,k) = sum_q W_q sum_l dphi_l(b) sum_ij H_ij C_ijkl,   H = grad v_h,
- *   C_ijkl = mu d_ik d_jl + (mu - lam ln J) Finv_jk Finv_li + lam Finv_ji Finv_lk.
+ *   neo-Hookean:  C_ijkl = mu d_ik d_jl + (mu - lam ln J) Finv_jk Finv_li + lam Finv_ji Finv_lk;
+ *   St Venant-Kirchhoff (P = F S):  C_ijkl = d_ik S_lj + lam F_ij F_kl + mu F_il F_kj
+ *                                            + mu (F F^T)_ik d_jl.
  * For the linear forms (mass, elasticity) A is symmetric and linear: g = A v.
  */
 void oracle_vjp(int form, int d, int nloc, int nq, const double *phi, const double *dphi,
@@ -228,7 +271,7 @@ void oracle_vjp(int form, int d, int nloc, int nq, const double *phi, const doub
                 const double *coords, const int32_t *cell_nodes, double lam, double mu,
                 const double *u, const double *v, double *g, int64_t n_dof)
 {
-    if (form != OR_NH) {
+    if (form != OR_NH && form != OR_SVK) {
         oracle_action(form, d, nloc, nq, phi, dphi, w, n_cell, cell_verts, coords,
                       cell_nodes, lam, mu, v, g, n_dof);
         return;
@@ -251,15 +294,39 @@ void oracle_vjp(int form, int d, int nloc, int nq, const double *phi, const doub
             for (int i = 0; i < d; ++i)
                 for (int j = 0; j < d; ++j)
                     F[i][j] = (i == j ? 1.0 : 0.0) + G[i][j];
-            double lnJ = log(inverse(d, F, Fi));
+            double lnJ = 0.0, S2[3][3], FFt[3][3];
+            if (form == OR_NH) {
+                lnJ = log(inverse(d, F, Fi));
+            } else {
+                double trE = 0.0;
+                for (int i = 0; i < d; ++i)
+                    for (int j = 0; j < d; ++j) {
+                        double c = 0.0, b = 0.0;
+                        for (int k = 0; k < d; ++k) {
+                            c += F[k][i] * F[k][j];
+                            b += F[i][k] * F[j][k];
+                        }
+                        S2[i][j] = mu * (c - (i == j ? 1.0 : 0.0));   /* 2 mu E */
+                        FFt[i][j] = b;
+                        if (i == j)
+                            trE += 0.5 * (c - 1.0);
+                    }
+                for (int i = 0; i < d; ++i)
+                    S2[i][i] += lam * trE;
+            }
             for (int k = 0; k < d; ++k)
                 for (int l = 0; l < d; ++l) {
                     double s = 0.0;
                     for (int i = 0; i < d; ++i)
                         for (int j = 0; j < d; ++j) {
-                            double C = ((i == k && j == l) ? mu : 0.0)
-                                     + (mu - lam * lnJ) * Fi[j][k] * Fi[l][i]
-                                     + lam * Fi[j][i] * Fi[l][k];
+                            double C;
+                            if (form == OR_NH)
+                                C = ((i == k && j == l) ? mu : 0.0)
+                                  + (mu - lam * lnJ) * Fi[j][k] * Fi[l][i]
+                                  + lam * Fi[j][i] * Fi[l][k];
+                            else
+                                C = (i == k ? S2[l][j] : 0.0) + lam * F[i][j] * F[k][l]
+                                  + mu * F[i][l] * F[k][j] + (j == l ? mu * FFt[i][k] : 0.0);
                             s += H[i][j] * C;
                         }
                     D[k][l] = s;
@@ -282,8 +349,8 @@ void oracle_vjp(int form, int d, int nloc, int nq, const double *phi, const doub
     }
 }
 
-/* discrete neo-Hookean energy  Pi_h(u) = sum_T sum_q w_q |det J| Psi(F_q) */
-double oracle_nh_energy(int d, int nloc, int nq, const double *dphi, const double *w,
+/* discrete energy of a hyperelastic form  Pi_h(u) = sum_T sum_q w_q |det J| Psi(F_q) */
+double oracle_energy(int form, int d, int nloc, int nq, const double *dphi, const double *w,
                         int64_t n_cell, const int32_t *cell_verts, const double *coords,
                         const int32_t *cell_nodes, double lam, double mu, const double *u)
 {
@@ -295,7 +362,7 @@ double oracle_nh_energy(int d, int nloc, int nq, const double *dphi, const doubl
         for (int q = 0; q < nq; ++q) {
             double G[3][3];
             physical_gradient(d, nloc, dphi + (int64_t)q * nloc * d, K, uloc, G);
-            total += w[q] * detJ * energy_density(d, lam, mu, G);
+            total += w[q] * detJ * energy_density(form, d, lam, mu, G);
         }
     }
     return total;

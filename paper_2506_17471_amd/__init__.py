@@ -23,7 +23,7 @@ __all__ = ["FORM_MASS", "FORM_ELASTICITY", "FORM_NEOHOOKEAN", "FemError", "Plan"
            "lib", "reference_tables", "colouring", "check_patch_layout", "LIB_PATH", "Batch",
            "SCATTER_COLOUR", "SCATTER_PATCH"]
 
-FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN = 0, 1, 2
+FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN, FORM_SVK = 0, 1, 2, 3
 QUAD_CONICAL, QUAD_SYMMETRIC = 0, 1
 SCATTER_COLOUR, SCATTER_PATCH = 0, 1
 SUM_ELEMENT, SUM_COLOURED = 1, 2
@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
     L.fem_reference_tables.restype = i32
     L.fem_plan_set_block.argtypes = [P, i32]
     L.fem_plan_set_block.restype = i32
+    L.fem_action_jvp.argtypes = [P, P, P, P, P]
+    L.fem_action_jvp.restype = i32
     L.fem_action_once.argtypes = [i32, i32, i32, i32, i64, P, i64, P, P, i64, P, i32, P, P, P]
     L.fem_action_once.restype = i32
     L.fem_plan_get_quadrature.argtypes = [P, P, P]
@@ -299,6 +301,16 @@ class Plan:
             out = torch.empty_like(u)
         _check(lib().fem_action(self.handle, _dev_ptr(u, self.n_dof, "u"),
                                 _dev_ptr(out, self.n_dof, "y"), _stream_handle(stream)))
+        return out
+
+    def jvp(self, u, w, out=None, stream=None):
+        """(dA/du) w, the tangent action at u, on the current stream (asynchronous)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(w)
+        _check(lib().fem_action_jvp(self.handle, _dev_ptr(u, self.n_dof, "u"),
+                                    _dev_ptr(w, self.n_dof, "w"),
+                                    _dev_ptr(out, self.n_dof, "out"), _stream_handle(stream)))
         return out
 
     def vjp(self, u, v, out=None, stream=None):

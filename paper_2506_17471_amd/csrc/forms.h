@@ -245,6 +245,112 @@ __device__ __forceinline__ void tangent_neohookean(const double (&G)[DIM][DIM],
         }
 }
 
+// St Venant-Kirchhoff: E = (F^T F - I)/2, S = lam tr(E) I + 2 mu E, P = F S,  F = I + G
+template <int DIM>
+__device__ __forceinline__ void stress_svk(const double (&G)[DIM][DIM], double lam, double mu,
+                                           double (&P)[DIM][DIM])
+{
+    double F[DIM][DIM], S[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) F[i][j] = G[i][j] + (i == j ? 1.0 : 0.0);
+    double trE = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) trE = fma(F[i][j], F[i][j], trE);
+    trE = 0.5 * (trE - DIM);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = i; j < DIM; ++j) {
+            double c = 0.0;                          // (F^T F)_ij
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) c = fma(F[k][i], F[k][j], c);
+            const double e = 0.5 * (c - (i == j ? 1.0 : 0.0));
+            S[i][j] = 2.0 * mu * e + (i == j ? lam * trE : 0.0);
+            S[j][i] = S[i][j];
+        }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) s = fma(F[i][k], S[k][j], s);
+            P[i][j] = s;
+        }
+}
+
+// dP[H] = H S + F dS,  dS = lam tr(dE) I + 2 mu dE,  dE = sym(F^T H): the St Venant-
+// Kirchhoff tangent contracted with H (major symmetry: also the transposed contraction)
+template <int DIM>
+__device__ __forceinline__ void tangent_svk(const double (&G)[DIM][DIM],
+                                            const double (&H)[DIM][DIM], double lam, double mu,
+                                            double (&dP)[DIM][DIM])
+{
+    double F[DIM][DIM], S[DIM][DIM], dS[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) F[i][j] = G[i][j] + (i == j ? 1.0 : 0.0);
+    double trE = 0.0, trdE = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            trE = fma(F[i][j], F[i][j], trE);
+            trdE = fma(F[i][j], H[i][j], trdE);     // tr(F^T H)
+        }
+    trE = 0.5 * (trE - DIM);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = i; j < DIM; ++j) {
+            double c = 0.0, fh = 0.0, hf = 0.0;     // (F^T F)_ij, (F^T H)_ij, (F^T H)_ji
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                c = fma(F[k][i], F[k][j], c);
+                fh = fma(F[k][i], H[k][j], fh);
+                hf = fma(F[k][j], H[k][i], hf);
+            }
+            const double e = 0.5 * (c - (i == j ? 1.0 : 0.0));
+            const double de = 0.5 * (fh + hf);
+            S[i][j] = 2.0 * mu * e + (i == j ? lam * trE : 0.0);
+            dS[i][j] = 2.0 * mu * de + (i == j ? lam * trdE : 0.0);
+            S[j][i] = S[i][j];
+            dS[j][i] = dS[i][j];
+        }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) s = fma(H[i][k], S[k][j], fma(F[i][k], dS[k][j], s));
+            dP[i][j] = s;
+        }
+}
+
+// The pointwise map of a form at one quadrature point: the stress of G, or with VJP the
+// tangent of the stress at G contracted with H.
+template <int FORM, int DIM, bool VJP>
+__device__ __forceinline__ void pointwise(const double (&G)[DIM][DIM], const double (&H)[DIM][DIM],
+                                          double lam, double mu, double (&S)[DIM][DIM])
+{
+    if constexpr (FORM == FEM_ELASTICITY) {
+        stress_elasticity<DIM>(G, lam, mu, S);
+    } else if constexpr (FORM == FEM_NEOHOOKEAN) {
+        if constexpr (VJP) tangent_neohookean<DIM>(G, H, lam, mu, S);
+        else stress_neohookean<DIM>(G, lam, mu, S);
+    } else {
+        static_assert(FORM == FEM_SVK, "vector form");
+        if constexpr (VJP) tangent_svk<DIM>(G, H, lam, mu, S);
+        else stress_svk<DIM>(G, lam, mu, S);
+    }
+}
+
 // The quadrature loop of one cell: evaluation of u (and v) at each point from the
 // tabulation, the pointwise form, and accumulation into yl against the test functions.
 // The tabulation address is uniform across the wavefront (constant address space), so its
@@ -298,17 +404,10 @@ __device__ __forceinline__ void cell_quadrature(
                         if constexpr (VJP) gv[c][r] = fma(tr, vl[n][c], gv[c][r]);
                     }
                 }
-            double G[DIM][DIM], S[DIM][DIM], T[DIM][DIM];
+            double G[DIM][DIM], H[DIM][DIM], S[DIM][DIM], T[DIM][DIM];
             to_physical<DIM>(gu, Kinv, G);
-            if constexpr (VJP) {
-                double H[DIM][DIM];
-                to_physical<DIM>(gv, Kinv, H);
-                tangent_neohookean<DIM>(G, H, lam, mu, S);
-            } else if constexpr (FORM == FEM_ELASTICITY) {
-                stress_elasticity<DIM>(G, lam, mu, S);
-            } else {
-                stress_neohookean<DIM>(G, lam, mu, S);
-            }
+            if constexpr (VJP) to_physical<DIM>(gv, Kinv, H);
+            pointwise<FORM, DIM, VJP>(G, H, lam, mu, S);
             pull_back<DIM>(S, Kinv, t[DIM * NLOC] * adet, T);
 #pragma unroll
             for (int n = 0; n < NLOC; ++n)
@@ -436,15 +535,9 @@ __device__ __forceinline__ void cell_quadrature_triple(
                 if constexpr (VJP) gv[row][r] = __shfl(h[r], base + row);
             }
         to_physical<3>(gu, Kinv, G);
-        if constexpr (VJP) {
-            double H[3][3];
-            to_physical<3>(gv, Kinv, H);
-            tangent_neohookean<3>(G, H, lam, mu, S);
-        } else if constexpr (FORM == FEM_ELASTICITY) {
-            stress_elasticity<3>(G, lam, mu, S);
-        } else {
-            stress_neohookean<3>(G, lam, mu, S);
-        }
+        double H[3][3];
+        if constexpr (VJP) to_physical<3>(gv, Kinv, H);
+        pointwise<FORM, 3, VJP>(G, H, lam, mu, S);
         pull_back<3>(S, Kinv, t[3 * NLOC] * adet, T);
         double tc[3];
 #pragma unroll

@@ -168,6 +168,8 @@ size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int m
                        int sum_mode);
 size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode);
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
+// the hyperelastic forms: nonlinear residuals whose VJP is a tangent action at u
+inline bool nonlinear_form(int form) { return form == FEM_NEOHOOKEAN || form == FEM_SVK; }
 bool pair_available(int form, int dim, int degree);
 bool triple_available(int form, int dim, int degree);
 hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch, int sum_mode,

@@ -1,0 +1,443 @@
+// Kernel templates of the matrix-free action (included by the per-form translation
+// units, which instantiate them; kernels.hip holds the launchers).
+//
+// One lane owns one cell: the per-cell body of the paper's generic action kernel (Sec.
+// 2.3) runs in registers, its tabulation operands arriving through scalar loads
+// (forms.h).  Two deterministic ways to sum the cell vectors into the global vector:
+//
+// colour strategy: cells are greedily coloured so that no two cells of a colour share a
+//   node; one launch per colour, each lane writing (first holder of a node in colour
+//   order) or read-add-writing its nodes.  The colour-sorted structure-of-arrays maps
+//   make every map read of a wavefront contiguous.
+//
+// patch strategy: cells are ordered along a Morton curve and cut into patches of P cells
+//   (one workgroup each, one launch for the whole mesh).  The workgroup stages the
+//   patch's distinct nodes' values in LDS, every lane reads its cell's values from there
+//   and computes its cell vector; the cell vectors are summed into the patch's nodes in a
+//   fixed order, either through an LDS element buffer (each node adds its slots in
+//   ascending (cell, local node)) or colour by colour into an LDS node buffer.  A node no
+//   other patch holds is stored straight into y; a shared one leaves as a partial sum that
+//   a small fixup kernel adds up in patch order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "forms.h"
+#include "internal.h"
+
+namespace femx {
+
+using ColourFn = void (*)(const LaunchArgs);
+using PatchFn = void (*)(const PatchArgs, int);   // (arguments, cells per patch)
+using BatchFn = void (*)(const BatchDesc *, const int32_t *, int);
+
+struct Kernels {
+    ColourFn colour;
+    PatchFn patch[4][3];  // [lanes per cell 1..3][sum mode 1..2], null where absent
+    BatchFn batch[4][3];
+};
+
+// one per form, each in its own translation unit (they compile in parallel)
+Kernels lookup_mass(int dim, int degree, bool vjp);
+Kernels lookup_elasticity(int dim, int degree, bool vjp);
+Kernels lookup_neohookean(int dim, int degree, bool vjp);
+Kernels lookup_svk(int dim, int degree, bool vjp);
+
+constexpr int kMaxBlock = 256;
+
+namespace {
+
+
+// Waves per SIMD the register allocator is asked to leave room for (occupancy target):
+// the lane-pair kernels and the one-lane low-degree 2D kernels fit without spilling in
+// the loop; everything else keeps the allocator's default.
+constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc)
+{
+    if (lpc == 3) return 1;
+    if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : 4;
+    return (!vjp && dim == 2 && k <= 4 && form != FEM_MASS) ? 3 : 1;
+}
+
+template <int DIM>
+__device__ __forceinline__ double gather_geometry(const int32_t *__restrict__ verts,
+                                                  int64_t stride, int64_t s,
+                                                  const double *__restrict__ coords,
+                                                  double (&K)[DIM][DIM])
+{
+    double x[DIM + 1][DIM];
+#pragma unroll
+    for (int j = 0; j <= DIM; ++j) {
+        const int64_t vj = verts[j * stride + s];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) x[j][i] = coords[vj * DIM + i];
+    }
+    return affine_geometry<DIM>(x, K);
+}
+
+// ------------------------------------------------------------------ colour strategy
+template <int FORM, int DIM, int K, bool VJP>
+__global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
+{
+    constexpr int NLOC = nloc_of(DIM, K);
+    constexpr int NC = FORM == FEM_MASS ? 1 : DIM;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.count) return;
+    const int64_t s = a.begin + i;
+    double Kinv[DIM][DIM];
+    const double adet = gather_geometry<DIM>(a.verts, a.stride, s, a.coords, Kinv);
+    double ul[NLOC][NC], vl[VJP ? NLOC : 1][NC], yl[NLOC][NC];
+#pragma unroll
+    for (int n = 0; n < NLOC; ++n) {
+        const int64_t nd = a.nodes[n * a.stride + s];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            ul[n][c] = a.u[nd * NC + c];
+            if constexpr (VJP) vl[n][c] = a.v[nd * NC + c];
+        }
+    }
+    cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
+    const uint64_t first = a.first[s];
+#pragma unroll
+    for (int n = 0; n < NLOC; ++n) {
+        const int64_t nd = a.nodes[n * a.stride + s];
+        double *dst = a.y + nd * NC;
+        if ((first >> n) & 1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) dst[c] = yl[n][c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) dst[c] += yl[n][c];
+        }
+    }
+}
+
+// ------------------------------------------------------------------- patch strategy
+// Stage the patch's node ids (region B) and nodal values (region A) in LDS.  Each thread
+// takes B nodes per round and issues all their id loads, then all their value loads,
+// before the first wait: a few memory round trips per workgroup instead of one per node a
+// thread stages.  Indices past the end are clamped to the last node (U >= 1 for every
+// patch), so the loads need no branches; only the LDS stores are guarded.  B = 8, or 4
+// for the mass form, whose patches hold about 2.5 nodes per lane and whose occupancy is
+// set by registers.
+
+template <int NC, bool VJP, int B>
+__device__ __forceinline__ void stage_nodes(const PatchArgs &a, int nb, int U, int tid,
+                                            int nthreads, double *lds, int32_t *b_node)
+{
+    for (int j0 = tid; j0 < U; j0 += B * nthreads) {
+        int32_t nd[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = min(j0 + b * nthreads, U - 1);
+            nd[b] = a.patch_nodes[nb + j];
+        }
+        double uv[B][NC], vv[VJP ? B : 1][NC];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                uv[b][c] = a.u[(int64_t)nd[b] * NC + c];
+                if constexpr (VJP) vv[b][c] = a.v[(int64_t)nd[b] * NC + c];
+            }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = j0 + b * nthreads;
+            if (j < U) {
+                b_node[j] = nd[b];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    lds[j * NC + c] = uv[b][c];
+                    if constexpr (VJP) lds[(U + j) * NC + c] = vv[b][c];
+                }
+            }
+        }
+    }
+}
+
+// Copy n consecutive elements from global memory to LDS, kStageBatch loads in flight per
+// thread (indices clamped as in stage_nodes; n >= 1).
+constexpr int kStageBatch = 8;
+
+template <typename T>
+__device__ __forceinline__ void stage_copy(const T *__restrict__ src, int n, int tid,
+                                           int nthreads, T *dst)
+{
+    for (int j0 = tid; j0 < n; j0 += kStageBatch * nthreads) {
+        T val[kStageBatch];
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) val[b] = src[min(j0 + b * nthreads, n - 1)];
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) {
+            const int j = j0 + b * nthreads;
+            if (j < n) dst[j] = val[b];
+        }
+    }
+}
+
+// LPC lanes per cell: 1; 2 for the 2D vector forms (lane c of a pair owns component c);
+// 3 for the 3D vector forms (lane c of a triple owns component c; a wavefront holds 21
+// triples and leaves its last lane idle).  SUM: SUM_ELEMENT (LDS element buffer and fixed-
+// order node sums) or SUM_COLOURED (sub-colour phases accumulating into an LDS node buffer).
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
+__device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
+{
+    constexpr int NLOC = nloc_of(DIM, K);
+    constexpr int NC = FORM == FEM_MASS ? 1 : DIM;
+    static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && FORM != FEM_MASS) ||
+                      (LPC == 3 && DIM == 3 && FORM != FEM_MASS),
+                  "lane split");
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    int cl, comp, base = 0;                   // local cell, component, first lane of the triple
+    if constexpr (LPC == 1) {
+        cl = tid;
+        comp = 0;
+    } else if constexpr (LPC == 2) {
+        cl = tid >> 1;
+        comp = tid & 1;
+    } else {
+        const int lane = tid & 63, wave = tid >> 6;
+        cl = lane < 63 ? wave * 21 + lane / 3 : P;    // the idle lane owns no cell
+        comp = lane < 63 ? lane % 3 : 0;
+        base = lane < 63 ? lane - comp : 0;
+    }
+    const int nb = a.patch_off[p];
+    const int U = a.patch_off[p + 1] - nb;
+    const int nint = a.patch_nint[p];
+    const int pbase = a.patch_pbase[p];
+
+    // 1. the cell's own loads (geometry, local node indices) go out first, then the patch's
+    //    distinct nodal values are staged in LDS (region A) and its node ids (and, for the
+    //    element buffer, its sum lists) in region B
+    const int64_t s = p * P + cl;
+    const bool active = cl < P && s < a.n_cell;
+    constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
+    double Kinv[DIM][DIM], adet = 0.0;
+    int lid[NLOC];
+    if (active) {
+        adet = gather_geometry<DIM>(a.verts, a.stride, s, a.coords, Kinv);
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n) lid[n] = a.lidx[n * a.stride + s];
+    }
+    int32_t *b_node = reinterpret_cast<int32_t *>(lds + a.lds_a);
+    int32_t *b_off = b_node + U;              // element buffer only
+    uint16_t *b_slot = reinterpret_cast<uint16_t *>(b_off + U + 1);
+    int e_base = 0;
+    if constexpr (SUM == SUM_ELEMENT) {
+        // slot lists: b_off holds global CSR offsets, rebased by e_base when read
+        e_base = a.csr_off[nb];
+        const int n_slots = a.csr_off[nb + U] - e_base;
+        stage_copy(a.csr_off + nb, U + 1, tid, nthreads, b_off);
+        stage_copy(a.csr_slots + e_base, n_slots, tid, nthreads, b_slot);
+    }
+    stage_nodes<NC, VJP, FORM == FEM_MASS ? 4 : 8>(a, nb, U, tid, nthreads, lds, b_node);
+    __syncthreads();
+
+    // 2. the cell's values from LDS
+    double ul[NLOC][CW], vl[VJP ? NLOC : 1][CW], yl[NLOC][CW];
+    if (active) {
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n) {
+            const int l = lid[n];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                ul[n][c] = lds[l * NC + c + comp];
+                if constexpr (VJP) vl[n][c] = lds[(U + l) * NC + c + comp];
+            }
+        }
+    }
+    __syncthreads();   // the staged values are dead from here on; region A is reused
+
+    if constexpr (SUM == SUM_COLOURED) {
+        for (int j = tid; j < U * NC; j += nthreads) lds[j] = 0.0;   // the node accumulator
+    }
+
+    // 3. the cell's quadrature loop
+    if (active) {
+        if constexpr (LPC == 1) {
+            cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
+        } else if constexpr (LPC == 3) {
+            double u1[NLOC], v1[VJP ? NLOC : 1], y1[NLOC];
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) {
+                u1[n] = ul[n][0];
+                if constexpr (VJP) v1[n] = vl[n][0];
+            }
+            cell_quadrature_triple<FORM, K, VJP>(u1, v1, comp, base, Kinv, adet, a.tab, a.nq,
+                                                 a.lam, a.mu, y1);
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) yl[n][0] = y1[n];
+        } else {
+            double u1[NLOC], v1[VJP ? NLOC : 1], y1[NLOC];
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) {
+                u1[n] = ul[n][0];
+                if constexpr (VJP) v1[n] = vl[n][0];
+            }
+            cell_quadrature_pair<FORM, K, VJP>(u1, v1, comp, Kinv, adet, a.tab, a.nq, a.lam, a.mu,
+                                               y1);
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) yl[n][0] = y1[n];
+        }
+    }
+
+    // 4. sum the cell vectors into the patch's nodes
+    if constexpr (SUM == SUM_ELEMENT) {
+        if (active) {
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) lds[(n * NC + c + comp) * P + cl] = yl[n][c];
+        }
+        __syncthreads();
+    } else {
+        // reloaded after the barriers rather than kept live through the quadrature loop
+        const int col = active ? a.colour[s] : -1;
+        int lid2[NLOC];
+        if (active) {
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) lid2[n] = a.lidx[n * a.stride + s];
+        }
+        const int ncol = a.patch_ncol[p];
+        __syncthreads();                      // the accumulator is zero everywhere
+        // no two cells of a colour share a node, so within a phase each address has one
+        // writer: the LDS atomic add (no return) is only a read-modify-write without the
+        // round trip, and the sum order stays fixed (colour order)
+        for (int k = 0; k < ncol; ++k) {
+            if (col == k) {
+#pragma unroll
+                for (int n = 0; n < NLOC; ++n)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c)
+                        __hip_atomic_fetch_add(&lds[lid2[n] * NC + c + comp], yl[n][c],
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            __syncthreads();
+        }
+    }
+
+    // 5. each distinct node stored once: interior nodes into y, shared ones as partials
+    for (int j = tid; j < U; j += nthreads) {
+        double sum[NC];
+        if constexpr (SUM == SUM_ELEMENT) {
+            const int e0 = b_off[j] - e_base, e1 = b_off[j + 1] - e_base;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sum[c] = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int sl = b_slot[e];
+                const int an = sl >> 8, sc = sl & 255;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sum[c] += lds[(an * NC + c) * P + sc];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sum[c] = lds[j * NC + c];
+        }
+        if (j < nint) {
+            const int64_t nd = b_node[j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a.y[nd * NC + c] = sum[c];
+        } else {
+            const int64_t dest = a.pdest[pbase + (j - nint)];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a.partial[dest * NC + c] = sum[c];
+        }
+    }
+}
+
+// The dispatcher deals workgroups to the 8 XCDs in turn (workgroup b to XCD b mod 8), and
+// each XCD has its own L2.  Renumbering so that XCD x works through one contiguous run of
+// the n patches -- runs of n/8 patches, the first n mod 8 runs one longer -- keeps Morton
+// neighbours, which share nodes and vertices, in one L2.  A bijection of [0, n) whatever
+// the dispatch order, so only locality depends on the dealing rule.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n)
+{
+    const int64_t q = n / kXcds, r = n % kXcds;
+    const int64_t x = b % kXcds, i = b / kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
+__global__ void __launch_bounds__(kMaxBlock)
+    __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
+    patch_kernel(const PatchArgs a, int P)
+{
+    patch_body<FORM, DIM, K, VJP, LPC, SUM>(a, xcd_order(blockIdx.x, gridDim.x), P);
+}
+
+// Many meshes of one kernel variant in one launch: workgroup b works on patch
+// b - desc[m].first_patch of mesh m = patch_mesh[b].
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
+__global__ void __launch_bounds__(kMaxBlock)
+    __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
+    batch_patch_kernel(const BatchDesc *__restrict__ desc, const int32_t *__restrict__ patch_mesh,
+                       int P)
+{
+    const int64_t b = xcd_order(blockIdx.x, gridDim.x);
+    const int m = patch_mesh[b];
+    const BatchDesc &d = desc[m];
+    patch_body<FORM, DIM, K, VJP, LPC, SUM>(d.args, b - d.first_patch, P);
+}
+
+template <int FORM, int DIM, int K, bool VJP, int LPC>
+void fill_lanes(Kernels &k)
+{
+    k.patch[LPC][SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
+    k.patch[LPC][SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+    k.batch[LPC][SUM_ELEMENT] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
+    k.batch[LPC][SUM_COLOURED] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+}
+
+template <int FORM, int DIM, int K, bool VJP>
+Kernels entry()
+{
+    Kernels k{};
+    k.colour = colour_kernel<FORM, DIM, K, VJP>;
+    fill_lanes<FORM, DIM, K, VJP, 1>(k);
+    if constexpr (DIM == 2 && FORM != FEM_MASS) fill_lanes<FORM, DIM, K, VJP, 2>(k);
+    if constexpr (DIM == 3 && FORM != FEM_MASS) fill_lanes<FORM, DIM, K, VJP, 3>(k);
+    return k;
+}
+
+// the kernel table of one form for (dim, degree), empty where not built
+template <int FORM, int DIM, int K>
+Kernels pick(bool vjp)
+{
+    if constexpr (FORM == FEM_NEOHOOKEAN || FORM == FEM_SVK) {
+        if (vjp) return entry<FORM, DIM, K, true>();
+    }
+    return entry<FORM, DIM, K, false>();
+}
+
+template <int FORM>
+Kernels lookup_form(int dim, int degree, bool vjp)
+{
+    if (dim == 2) {
+        switch (degree) {
+        case 1: return pick<FORM, 2, 1>(vjp);
+        case 2: return pick<FORM, 2, 2>(vjp);
+        case 3: return pick<FORM, 2, 3>(vjp);
+        case 4: return pick<FORM, 2, 4>(vjp);
+        case 5: return pick<FORM, 2, 5>(vjp);
+        case 6: return pick<FORM, 2, 6>(vjp);
+        default: break;
+        }
+    } else if (dim == 3) {
+        switch (degree) {
+        case 1: return pick<FORM, 3, 1>(vjp);
+        case 2: return pick<FORM, 3, 2>(vjp);
+        case 3: return pick<FORM, 3, 3>(vjp);
+        case 4: return pick<FORM, 3, 4>(vjp);
+        default: break;
+        }
+    }
+    return Kernels{};
+}
+
+}  // namespace
+}  // namespace femx

@@ -574,7 +574,7 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
     PatchLayout L = make_patch_layout(p, coords, cell_verts, cell_nodes, P);
     const char *chk = std::getenv("FEM_CHECK");
     if (chk && chk[0] == '1') validate_patch_layout(p, L, cell_nodes);
-    const size_t lds = femx::patch_lds_bytes(p->form, p->dim, p->degree, p->form == FEM_NEOHOOKEAN,
+    const size_t lds = femx::patch_lds_bytes(p->form, p->dim, p->degree, femx::nonlinear_form(p->form),
                                              P, L.max_nodes, p->sum_mode);
     if (lds > 160 * 1024)
         throw Error(FEM_E_UNSUPPORTED, "patch of " + std::to_string(P) + " cells needs " +
@@ -669,7 +669,7 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         femx::check_hip(femx::launch_zero_nodes(p->d_untouched, p->n_untouched, p->ncomp, y, s),
                         "zero untouched nodes");
     // the linear forms are symmetric: their VJP is the action applied to v
-    const bool nl_vjp = vjp && p->form == FEM_NEOHOOKEAN;
+    const bool nl_vjp = vjp && femx::nonlinear_form(p->form);
     const double *in = (vjp && !nl_vjp) ? v : u;
     if (p->strategy == femx::STRAT_PATCH && p->patch > 0) {
         femx::PatchArgs a{};
@@ -775,7 +775,7 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
         throw Error(FEM_E_ARG, "patch_cells must be 64, 128 or 256 (at most 256 lanes) for one or "
                                "two lanes per cell, and 21, 42, 63 or 84 for three");
     const size_t lds = patch_lds_bytes(plan->form, plan->dim, plan->degree,
-                                       plan->form == FEM_NEOHOOKEAN, P,
+                                       femx::nonlinear_form(plan->form), P,
                                        P == plan->patch ? plan->max_patch_nodes : 0, mode);
     if (P == plan->patch && lds > 160 * 1024)
         throw Error(FEM_E_UNSUPPORTED, "this sum mode needs more than 160 KB of LDS");
@@ -824,7 +824,7 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
     const int st = guarded([&] {
         using femx::Error;
         if (!out) throw Error(FEM_E_ARG, "null output pointer");
-        if (form < FEM_MASS || form > FEM_NEOHOOKEAN) throw Error(FEM_E_UNSUPPORTED, "unknown form");
+        if (form < FEM_MASS || form > FEM_SVK) throw Error(FEM_E_UNSUPPORTED, "unknown form");
         if (dim != 2 && dim != 3) throw Error(FEM_E_UNSUPPORTED, "dim must be 2 or 3");
         if (degree < 1 || degree > (dim == 2 ? 6 : 4) || !femx::kernel_available(form, dim, degree))
             throw Error(FEM_E_UNSUPPORTED, "degree " + std::to_string(degree) + " not built for dim " +
@@ -868,6 +868,14 @@ void fem_plan_destroy(fem_plan *plan)
     (void)hipDeviceSynchronize();
     free_plan_memory(plan);
     delete plan;
+}
+
+int fem_action_jvp(const fem_plan *plan, const double *u, const double *w, double *out,
+                   void *stream)
+{
+    // the tangent of a hyperelastic residual has major symmetry, so (dA/du) w equals
+    // (dA/du)^T w and the VJP kernels compute it; the linear forms give A w
+    return guarded([&] { run(plan, u, w, out, stream, true); });
 }
 
 int fem_action_once(int form, int dim, int degree, int quad_degree, int64_t n_vert,
@@ -999,7 +1007,7 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
 {
     return guarded([&] {
         using femx::Error;
-        if (form < FEM_MASS || form > FEM_NEOHOOKEAN || (dim != 2 && dim != 3) || degree < 1 ||
+        if (form < FEM_MASS || form > FEM_SVK || (dim != 2 && dim != 3) || degree < 1 ||
             degree > 8)
             throw Error(FEM_E_UNSUPPORTED, "unsupported form/dim/degree");
         if (n_vert < 0 || n_cell < 1 || n_node < 0) throw Error(FEM_E_ARG, "bad size");
@@ -1027,7 +1035,7 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
             stats[3] = (int64_t)L.patch_nodes.size();
             stats[4] = (int64_t)L.fix_node.size();
             stats[5] = L.fix_off.back();
-            stats[6] = (int64_t)femx::patch_lds_bytes(form, dim, degree, form == FEM_NEOHOOKEAN, P,
+            stats[6] = (int64_t)femx::patch_lds_bytes(form, dim, degree, femx::nonlinear_form(form), P,
                                                       L.max_nodes, p.sum_mode);
             stats[7] = L.max_colours;
         }

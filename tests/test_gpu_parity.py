@@ -46,6 +46,9 @@ def params_for(form):
     return () if form == fx.FORM_MASS else (LAME if form == fx.FORM_ELASTICITY else NH)
 
 
+HYPERELASTIC = (fx.FORM_NEOHOOKEAN, fx.FORM_SVK)
+
+
 def inputs(form, mesh, seed):
     rng = np.random.default_rng(seed)
     ncomp = 1 if form == fx.FORM_MASS else mesh.dim
@@ -53,6 +56,9 @@ def inputs(form, mesh, seed):
         u = meshgen.nh_displacement(rng, mesh, 0.01)
         # an admissible state: det F > 0 at every quadrature point of the rule used
         assert oracle.min_det_f(mesh, u, 2 * mesh.k) > 0.5
+    elif form == fx.FORM_SVK:
+        # SVK needs no det F > 0; a larger state exercises its cubic terms
+        u = meshgen.nh_displacement(rng, mesh, 0.2)
     else:
         u = rng.uniform(-1, 1, mesh.n_node * ncomp)
     v = rng.uniform(-1, 1, mesh.n_node * ncomp)
@@ -63,8 +69,8 @@ def qdeg(form, k):
     return 2 * (k - 1) if form == fx.FORM_ELASTICITY else 2 * k
 
 
-CASES = [(f, 2, k) for f in (0, 1, 2) for k in range(1, 7)] + \
-        [(f, 3, k) for f in (0, 1, 2) for k in range(1, 5)]
+CASES = [(f, 2, k) for f in (0, 1, 2, 3) for k in range(1, 7)] + \
+        [(f, 3, k) for f in (0, 1, 2, 3) for k in range(1, 5)]
 
 
 def plan_family(w):
@@ -149,9 +155,9 @@ def test_kernel_timing_counts_calls_and_leaves_results(strategy):
     assert plan.timing() == (0.0, 0)
 
 
-@pytest.mark.parametrize("form,dim,k", [c for c in CASES if c[0] == fx.FORM_NEOHOOKEAN])
+@pytest.mark.parametrize("form,dim,k", [c for c in CASES if c[0] in HYPERELASTIC])
 def test_conical_rule_parity(form, dim, k):
-    """The neo-Hookean operator depends on the rule: both families against the oracle."""
+    """The hyperelastic operators depend on the rule: both families against the oracle."""
     n = 7 if dim == 2 else 2
     mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(300 + k))
     u, v = inputs(form, mesh, 70 + k)
@@ -163,6 +169,27 @@ def test_conical_rule_parity(form, dim, k):
     g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
     assert max(rel_err(y, oracle.action(form, mesh, u, qd, params_for(form), family="conical"))) < TOL
     assert max(rel_err(g, oracle.vjp(form, mesh, u, v, qd, params_for(form), family="conical"))) < TOL
+
+
+@pytest.mark.parametrize("form", HYPERELASTIC)
+@pytest.mark.parametrize("dim,k,n", [(2, 4, 6), (3, 2, 2)])
+def test_jvp_is_tangent_action(form, dim, k, n):
+    """(dA/du) w from fem_action_jvp: equal to the VJP (the hyperelastic tangents are
+    symmetric), to the oracle's literal transpose, and to central differences of the
+    residual along w (h = 1e-6)."""
+    mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(400 + k))
+    u, w = inputs(form, mesh, 90 + k)
+    qd = qdeg(form, k)
+    say(f"[jvp] form={form} dim={dim} k={k} n={n}")
+    plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    ut, wt = gpu(u), gpu(w)
+    jw = plan.jvp(ut, wt)
+    assert torch.equal(jw, plan.vjp(ut, wt))
+    ref = oracle.vjp(form, mesh, u, w, qd, params_for(form), family=plan.quad_family_name)
+    assert max(rel_err(jw.cpu().numpy(), ref)) < TOL
+    h = 1e-6
+    fd = ((plan.action(ut + h * wt) - plan.action(ut - h * wt)) / (2 * h)).cpu().numpy()
+    assert np.max(np.abs(fd - ref)) < 1e-6 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("block", [64, 128, 256])
@@ -236,7 +263,7 @@ def test_single_cell_and_ragged_counts():
         assert rel_err(y, ref)[0] < TOL
 
 
-FULL = ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d", "nh_vjp_p4_2d", "mass_p2_2d_1024"]
+FULL = ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d", "nh_vjp_p4_2d", "mass_p2_2d_1024", "svk_p4_2d"]
 _ref_cache = {}
 
 

@@ -6,10 +6,12 @@ Each pin is fixed by the mathematics, not by the oracle itself:
                equality with the quadrature-free exact assembly (brute force);
   elasticity   rigid modes in the kernel; affine patch test; symmetry;
                lambda = 0, mu = 1/2 gives sigma = eps; exact assembly (brute force);
-  neo-Hookean  r(0) = 0, r(u + c) = r(u), r(finite rotation) = 0 (frame indifference);
+  neo-Hookean and St Venant-Kirchhoff
+               r(0) = 0, r(u + c) = r(u), r(finite rotation) = 0 (frame indifference);
                r = grad of the discrete energy (central differences);
                VJP at u = 0 equals the elasticity action with the same (lambda, mu);
                VJP against central differences of r and the transpose identity;
+               SVK stretch and simple shear on one P1 cell against hand-worked stresses;
   colouring    validity and greedy first-fit minimality.
 """
 import math
@@ -21,7 +23,8 @@ import meshgen
 import oracle
 from oracle import exact
 
-F_MASS, F_EL, F_NH = oracle.FORM_MASS, oracle.FORM_ELAST, oracle.FORM_NH
+F_MASS, F_EL, F_NH, F_SVK = oracle.FORM_MASS, oracle.FORM_ELAST, oracle.FORM_NH, oracle.FORM_SVK
+HYPER = pytest.mark.parametrize("form", [F_NH, F_SVK], ids=["nh", "svk"])
 
 
 def small_mesh(dim, n, k, seed=0, jitter=None):
@@ -158,22 +161,23 @@ def test_elasticity_paper_constants_sigma_is_eps():
     assert np.allclose(2 * y, y2, rtol=0, atol=1e-13)
 
 
-# ----------------------------------------------------------------------------- neo-Hookean
+# ------------------------------------------------------------ hyperelastic (NH and SVK)
 NH = (10.0, 1.0)
 
 
 @pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 2)])
-def test_nh_invariances(dim, k):
+@HYPER
+def test_hyper_invariances(form, dim, k):
     m = small_mesh(dim, 3 if dim == 2 else 2, k, seed=6)
     qd = 2 * k
-    r0 = oracle.action(F_NH, m, np.zeros(m.n_node * dim), qd, NH)
+    r0 = oracle.action(form, m, np.zeros(m.n_node * dim), qd, NH)
     assert np.max(np.abs(r0)) == 0.0
     rng = np.random.default_rng(4)
     u = meshgen.nh_displacement(rng, m, 0.05)
     assert oracle.min_det_f(m, u, qd) > 0.5
-    r = oracle.action(F_NH, m, u, qd, NH)
+    r = oracle.action(form, m, u, qd, NH)
     c = np.tile(rng.normal(size=dim), m.n_node)
-    rc = oracle.action(F_NH, m, u + c, qd, NH)
+    rc = oracle.action(form, m, u + c, qd, NH)
     assert np.max(np.abs(rc - r)) < 1e-12 * np.max(np.abs(r))
     # finite rotation: u_R = (R - I) x is in P_k and P(R) = 0
     X = lattice_positions(m)
@@ -185,44 +189,47 @@ def test_nh_invariances(dim, k):
         Kx = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
         R = np.eye(3) + np.sin(th) * Kx + (1 - np.cos(th)) * Kx @ Kx
     uR = (X @ (R - np.eye(dim)).T).ravel()
-    rR = oracle.action(F_NH, m, uR, qd, NH)
+    rR = oracle.action(form, m, uR, qd, NH)
     assert np.max(np.abs(rR)) < 1e-12
 
 
 @pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 2)])
-def test_nh_residual_is_energy_gradient(dim, k):
+@HYPER
+def test_hyper_residual_is_energy_gradient(form, dim, k):
     m = small_mesh(dim, 2 if dim == 2 else 1, k, seed=8)
     qd = 2 * k
     rng = np.random.default_rng(5)
     u = meshgen.nh_displacement(rng, m, 0.05)
     assert oracle.min_det_f(m, u, qd) > 0.5
-    r = oracle.action(F_NH, m, u, qd, NH)
+    r = oracle.action(form, m, u, qd, NH)
     h = 1e-6
     fd = np.zeros_like(u)
     for i in range(len(u)):
         e = np.zeros_like(u)
         e[i] = h
-        fd[i] = (oracle.nh_energy(m, u + e, qd, NH) - oracle.nh_energy(m, u - e, qd, NH)) / (2 * h)
+        fd[i] = (oracle.energy(form, m, u + e, qd, NH) - oracle.energy(form, m, u - e, qd, NH)) / (2 * h)
     assert np.max(np.abs(fd - r)) < 1e-6 * np.max(np.abs(r)) + 1e-9
 
 
 @pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 2)])
-def test_nh_vjp_at_zero_is_elasticity(dim, k):
+@HYPER
+def test_hyper_vjp_at_zero_is_elasticity(form, dim, k):
     m = small_mesh(dim, 2, k, seed=9)
     qd = 2 * k
     rng = np.random.default_rng(6)
     v = rng.uniform(-1, 1, m.n_node * dim)
-    g = oracle.vjp(F_NH, m, np.zeros(m.n_node * dim), v, qd, NH)
+    g = oracle.vjp(form, m, np.zeros(m.n_node * dim), v, qd, NH)
     a = oracle.action(F_EL, m, v, qd, NH)
     assert np.max(np.abs(g - a)) < 1e-12 * np.max(np.abs(a))
     # and the linearisation of r at 0 along v is the same operator (central differences)
     h = 1e-6
-    fd = (oracle.action(F_NH, m, h * v, qd, NH) - oracle.action(F_NH, m, -h * v, qd, NH)) / (2 * h)
+    fd = (oracle.action(form, m, h * v, qd, NH) - oracle.action(form, m, -h * v, qd, NH)) / (2 * h)
     assert np.max(np.abs(fd - a)) < 1e-6 * np.max(np.abs(a))
 
 
 @pytest.mark.parametrize("dim,k,n", [(2, 2, 2), (2, 4, 2), (3, 2, 1)])
-def test_nh_vjp_against_finite_differences(dim, k, n):
+@HYPER
+def test_hyper_vjp_against_finite_differences(form, dim, k, n):
     m = small_mesh(dim, n, k, seed=10)
     qd = 2 * k
     rng = np.random.default_rng(7)
@@ -230,19 +237,51 @@ def test_nh_vjp_against_finite_differences(dim, k, n):
     assert oracle.min_det_f(m, u, qd) > 0.5
     v = rng.uniform(-1, 1, m.n_node * dim)
     w = rng.uniform(-1, 1, m.n_node * dim)
-    g = oracle.vjp(F_NH, m, u, v, qd, NH)
+    g = oracle.vjp(form, m, u, v, qd, NH)
     # Jacobian columns by central differences; J^T v compared entrywise
     h = 1e-6
     Jcols = np.zeros((len(u), len(u)))
     for i in range(len(u)):
         e = np.zeros_like(u)
         e[i] = h
-        Jcols[:, i] = (oracle.action(F_NH, m, u + e, qd, NH)
-                       - oracle.action(F_NH, m, u - e, qd, NH)) / (2 * h)
+        Jcols[:, i] = (oracle.action(form, m, u + e, qd, NH)
+                       - oracle.action(form, m, u - e, qd, NH)) / (2 * h)
     assert np.max(np.abs(Jcols.T @ v - g)) < 1e-6 * np.max(np.abs(g))
     # transpose identity <v, J w> = <J^T v, w>, J w by central differences
-    Jw = (oracle.action(F_NH, m, u + h * w, qd, NH) - oracle.action(F_NH, m, u - h * w, qd, NH)) / (2 * h)
+    Jw = (oracle.action(form, m, u + h * w, qd, NH) - oracle.action(form, m, u - h * w, qd, NH)) / (2 * h)
     assert abs(v @ Jw - g @ w) < 1e-6 * abs(g @ w)
+
+
+@pytest.mark.parametrize("case", ["stretch", "shear"])
+def test_svk_homogeneous_one_cell(case):
+    """One reference triangle, P1, u = (F - I) x, so F is constant and the residual is
+    r_(a, c) = |T| sum_j P_cj d_j phi_a with grad phi = (-1,-1), (1,0), (0,1).  Closed forms of
+    the SVK stress P = F S worked out by hand:
+      uniaxial stretch F = diag(s, 1): E = diag(e, 0), e = (s^2 - 1)/2,
+        P = diag(s (lam + 2 mu) e, lam e);
+      simple shear F = [[1, g], [0, 1]]: E = [[0, g/2], [g/2, g^2/2]], tr E = g^2/2,
+        S = [[lam g^2/2, mu g], [mu g, lam g^2/2 + mu g^2]],
+        P = [[lam g^2/2 + mu g^2, mu g + g (lam g^2/2 + mu g^2)], [mu g, lam g^2/2 + mu g^2]]."""
+    lam, mu = 10.0, 1.0
+    m = meshgen.Mesh(2, 1, 1, np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]),
+                     np.array([[0, 1, 2]], dtype=np.int32), np.array([[0, 1, 2]], dtype=np.int32),
+                     3, 1.0)
+    if case == "stretch":
+        s_ = 1.3
+        F = np.diag([s_, 1.0])
+        e = (s_ * s_ - 1.0) / 2.0
+        P = np.diag([s_ * (lam + 2 * mu) * e, lam * e])
+    else:
+        g = 0.4
+        F = np.array([[1.0, g], [0.0, 1.0]])
+        t = lam * g * g / 2
+        P = np.array([[t + mu * g * g, mu * g + g * (t + mu * g * g)], [mu * g, t + mu * g * g]])
+    X = m.coords
+    u = ((X @ F.T) - X).ravel()
+    r = oracle.action(F_SVK, m, u, 2, (lam, mu)).reshape(3, 2)
+    grads = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])
+    ref = 0.5 * grads @ P.T
+    assert np.max(np.abs(r - ref)) < 1e-13 * np.max(np.abs(ref))
 
 
 # ----------------------------------------------------------------------------- colouring

@@ -20,11 +20,11 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 MUTATIONS = {
     "nh_drop_log_term": ("S[i][j] = mu * (F[i][j] - FiT) + lam * lnJ * FiT;",
                          "S[i][j] = mu * (F[i][j] - FiT);",
-                         [lambda: pins.test_nh_residual_is_energy_gradient(2, 2),
-                          lambda: pins.test_nh_vjp_at_zero_is_elasticity(2, 2)]),
+                         [lambda: pins.test_hyper_residual_is_energy_gradient(pins.F_NH, 2, 2),
+                          lambda: pins.test_hyper_vjp_at_zero_is_elasticity(pins.F_NH, 2, 2)]),
     "nh_sign_of_cofactor": ("S[i][j] = mu * (F[i][j] - FiT) + lam * lnJ * FiT;",
                             "S[i][j] = mu * (F[i][j] + FiT) + lam * lnJ * FiT;",
-                            [lambda: pins.test_nh_invariances(2, 2)]),
+                            [lambda: pins.test_hyper_invariances(pins.F_NH, 2, 2)]),
     "jacobian_transposed": ("J[i][r] = x[r + 1][i] - x[0][i];",
                             "J[r][i] = x[r + 1][i] - x[0][i];",
                             [lambda: pins.test_elasticity_equals_exact_assembly(2, 2, 2, pins.LAME)]),
@@ -42,13 +42,23 @@ MUTATIONS = {
                                [lambda: pins.test_elasticity_equals_exact_assembly(2, 2, 2, pins.LAME)]),
     "vjp_tangent_index": ("+ (mu - lam * lnJ) * Fi[j][k] * Fi[l][i]",
                           "+ (mu - lam * lnJ) * Fi[k][j] * Fi[l][i]",
-                          [lambda: pins.test_nh_vjp_against_finite_differences(2, 2, 2)]),
+                          [lambda: pins.test_hyper_vjp_against_finite_differences(pins.F_NH, 2, 2, 2)]),
     "energy_sign": ("return 0.5 * mu * (trC - d) - mu * lnJ + 0.5 * lam * lnJ * lnJ;",
                     "return 0.5 * mu * (trC - d) + mu * lnJ + 0.5 * lam * lnJ * lnJ;",
-                    [lambda: pins.test_nh_residual_is_energy_gradient(2, 2)]),
+                    [lambda: pins.test_hyper_residual_is_energy_gradient(pins.F_NH, 2, 2)]),
     "mass_test_function_dropped": ("out[a] += phi[q * nloc + a] * e;",
                                    "out[a] += e / nloc;",
                                    [lambda: pins.test_mass_equals_exact_assembly(2, 2, 2)]),
+    "svk_stress_transposed_product": ("S[i][j] += F[i][k] * S2[k][j];",
+                                      "S[i][j] += S2[i][k] * F[k][j];",
+                                      [lambda: pins.test_hyper_invariances(pins.F_SVK, 2, 2),
+                                       lambda: pins.test_svk_homogeneous_one_cell("shear")]),
+    "svk_energy_missing_half": ("return 0.5 * lam * trE * trE + mu * EE;",
+                                "return lam * trE * trE + mu * EE;",
+                                [lambda: pins.test_hyper_residual_is_energy_gradient(pins.F_SVK, 2, 2)]),
+    "svk_tangent_drops_geometric_term": ("C = (i == k ? S2[l][j] : 0.0) + lam * F[i][j] * F[k][l]",
+                                         "C = lam * F[i][j] * F[k][l]",
+                                         [lambda: pins.test_hyper_vjp_against_finite_differences(pins.F_SVK, 2, 2, 2)]),
     "colouring_ignores_conflicts": ("if ((masks[nd * nwords + c / 64] >> (c % 64)) & 1u) {",
                                     "if (0) {",
                                     [lambda: pins.test_colouring_valid_and_greedy(2, 6, 1)]),
