@@ -39,6 +39,11 @@ def flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
     if form == 0:                        # mass: eval 2n, weight 2, contraction 2n
         per_q = 2 * nloc + 2 + 2 * nloc
         return geo + nq * per_q
+    if form in (4, 5):                   # Laplace (+ mass term for Helmholtz)
+        per_q = 2 * d * nloc + 2 * d * d + d + 1 + 2 * d * nloc
+        if form == 5:
+            per_q += 2 * nloc + 1 + 2 * nloc
+        return geo + 2 * d ** 3 + nq * per_q
     ev = 2 * d * d * nloc                # reference gradients of the d components
     ct = 2 * d * d * nloc                # contraction against the test gradients
     geo_q = 2 * d ** 3 + (2 * d ** 3 + d * d) + 1   # G = gref K, T = W S K^T, W
@@ -324,6 +329,67 @@ def cpu_baseline(w, family: str, max_cells: int = 65536):
                       f"{dt * 1e3:.1f} ms each; DoF/s scaled by DoFs per cell of the full mesh"}
 
 
+FORM_NAMES = {0: "mass", 1: "elasticity", 2: "neohookean", 3: "svk", 4: "laplace", 5: "helmholtz"}
+
+
+def quad_degree_for(form: int, k: int) -> int:
+    """Exact for the bilinear forms' polynomial integrands; 2k for the hyperelastic ones."""
+    return 2 * (k - 1) if form in (1, 4) else 2 * k
+
+
+def run_sweep(steps: int, warmup: int, tri_cells: float = 5e5, tet_cells: float = 2e5):
+    """Every (form, dimension, degree) the library builds, at the paper's smaller mesh sizes
+    (about 5e5 triangles / 2e5 tetrahedra), default launch configuration and rule: µs per
+    action, DoF/s, algorithmic GFLOP/s and footprint GB/s, and the fraction of the binding
+    roof (FP64 vector if the algorithmic intensity is above the 9.8 flop/byte ridge, else
+    HBM)."""
+    import torch
+    import meshgen
+    import paper_2506_17471_amd as fx
+
+    out = []
+    for dim, degrees in ((2, range(1, 7)), (3, range(1, 5))):
+        for k in degrees:
+            rng = np.random.default_rng(100 * dim + k)
+            if dim == 2:
+                mesh = meshgen.unit_square(max(1, round(math.sqrt(tri_cells / 2))), k, 0.1, rng)
+            else:
+                mesh = meshgen.unit_cube(max(1, round((tet_cells / 6) ** (1 / 3))), k, 0.05, rng)
+            for form in range(6):
+                ncomp = 1 if form in (0, 4, 5) else dim
+                n_dof = mesh.n_node * ncomp
+                params = () if ncomp == 1 else ((10.0, 1.0) if form in (2, 3)
+                                                 else meshgen.lame_from_young(1.0, 0.3))
+                if form in (2, 3):
+                    u0 = meshgen.nh_displacement(rng, mesh)
+                else:
+                    u0 = rng.uniform(-1, 1, n_dof)
+                plan = fx.Plan.from_mesh(form, mesh, quad_degree_for(form, k), params)
+                u = torch.as_tensor(u0, device="cuda")
+                y = torch.empty_like(u)
+                ms, _ = time_steps(lambda: plan.action(u, out=y), steps, warmup)
+                kms = time_kernel(plan, lambda: plan.action(u, out=y), steps)
+                fl = flops_per_cell(form, dim, plan.n_loc, plan.n_quad) * mesh.n_cell
+                by = footprint_bytes(dim, mesh.n_vert, mesh.n_cell, plan.n_loc, n_dof, 2)
+                t = ms / 1e3
+                ai = fl / by
+                bound = "alu" if ai > FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) else "hbm"
+                frac = (fl / t / 1e12 / FP64_PEAK_TFLOPS) if bound == "alu" else (by / t / 1e9 / HBM_PEAK_GBS)
+                st = plan.strategy()
+                row = dict(form=FORM_NAMES[form], dim=dim, degree=k, n_cell=mesh.n_cell,
+                           n_dof=n_dof, n_quad=plan.n_quad, rule=plan.quad_family_name,
+                           launch=list(st), us=ms * 1e3, kernel_us=kms * 1e3,
+                           dof_per_s=n_dof / t, gflops=fl / t / 1e9, gbs=by / t / 1e9,
+                           intensity=ai, bound=bound, frac=frac)
+                out.append(row)
+                print(f"# sweep {row['form']:10s} {dim}D P{k}: {row['us']:9.1f} us "
+                      f"{row['dof_per_s']:.3e} DoF/s {bound} {100 * frac:5.1f}%",
+                      file=sys.stderr, flush=True)
+                del plan, u, y
+            del mesh
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +402,8 @@ def main():
     ap.add_argument("--rule", choices=["default", "conical", "symmetric"], default="default",
                     help="quadrature rule family of the timed workload (default: the plan's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the degree sweep over every built (form, dim, degree)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
@@ -360,6 +428,9 @@ def main():
                           "copy_gbs_read_plus_write": 2 * n * 8 / (ms / 1e3) / 1e9}))
         return
     tune = not args.no_tune
+    if args.sweep:
+        print(json.dumps({"sweep": run_sweep(args.steps, args.warmup)}))
+        return
 
     def note(msg):
         print(f"# {msg}", file=sys.stderr, flush=True)

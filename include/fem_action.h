@@ -30,7 +30,8 @@
  *   (fem_plan_set_quadrature switches).  The mass and elasticity operators do not depend
  *   on the rule (polynomial integrands); the neo-Hookean operator does.
  * - Vectors are node-major interleaved: component c of node n at index n * ncomp + c,
- *   ncomp = 1 for the mass form and d for the vector forms.
+ *   ncomp = 1 for the scalar forms (mass, Laplace, Helmholtz) and d for the vector forms
+ *   (elasticity, neo-Hookean, St Venant-Kirchhoff).
  * - Host arrays are read during the call only.  Device arrays (u, v, y, g) are caller-
  *   owned device memory (e.g. PyTorch CUDA tensors); the library never frees them.
  * - Kernels are enqueued on the caller's HIP stream (hipStream_t passed as void*, NULL =
@@ -64,6 +65,8 @@ extern "C" {
                              P = mu (F - F^{-T}) + lambda ln(det F) F^{-T}
                              (energy mu/2 (tr F^T F - d) - mu ln J + lambda/2 ln^2 J),
                              params {lambda, mu}                                     */
+#define FEM_LAPLACE 4     /* a(u, v) = int grad u . grad v  (scalar)                  */
+#define FEM_HELMHOLTZ 5   /* a(u, v) = int grad u . grad v + u v  (scalar, paper App. A) */
 #define FEM_SVK 3         /* St Venant-Kirchhoff residual (paper App. A hyperelastic law):
                              r(u; v) = int F S : grad v,  E = (F^T F - I)/2,
                              S = lambda tr(E) I + 2 mu E  (energy lambda/2 tr^2 E + mu E:E),
@@ -87,7 +90,8 @@ typedef struct fem_plan fem_plan;
  * and uploads colour-sorted copies of the maps and the coordinates to the current HIP
  * device.  Synchronous; allocates device memory owned by the plan.
  *
- *   form         FEM_MASS, FEM_ELASTICITY, FEM_NEOHOOKEAN or FEM_SVK
+ *   form         FEM_MASS, FEM_ELASTICITY, FEM_NEOHOOKEAN, FEM_SVK, FEM_LAPLACE or
+ *                FEM_HELMHOLTZ
  *   dim          2 (triangles) or 3 (tetrahedra)
  *   degree       polynomial degree k: 1..6 in 2D, 1..4 in 3D
  *   quad_degree  degree the rule integrates exactly: 0..20
@@ -95,7 +99,8 @@ typedef struct fem_plan fem_plan;
  *   cell_verts   HOST i32 [n_cell][dim+1]   vertex ids, the affine map's vertex order
  *   cell_nodes   HOST i32 [n_cell][n_loc]   node ids in the local order above
  *   n_node       number of nodes; vectors have n_node * ncomp entries
- *   params       HOST f64 [n_params]: {lambda, mu} for the vector forms, unused for mass
+ *   params       HOST f64 [n_params]: {lambda, mu} for the vector forms, unused for the
+ *                scalar forms (mass, Laplace, Helmholtz)
  * Errors: FEM_E_ARG, FEM_E_UNSUPPORTED, FEM_E_INDEX, FEM_E_INVERTED, FEM_E_HIP,
  * FEM_E_NOMEM.  On error *out is set to NULL and nothing is leaked.
  */

@@ -182,7 +182,7 @@ def nh_displacement(rng, mesh: Mesh, amplitude: float = 0.01) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # The named workloads.  Form ids: 0 mass, 1 linear elasticity, 2 neo-Hookean.
 # ---------------------------------------------------------------------------
-FORM_MASS, FORM_ELAST, FORM_NH, FORM_SVK = 0, 1, 2, 3
+FORM_MASS, FORM_ELAST, FORM_NH, FORM_SVK, FORM_LAPLACE, FORM_HELMHOLTZ = 0, 1, 2, 3, 4, 5
 
 
 def lame_from_young(E: float, nu: float) -> tuple[float, float]:
@@ -203,7 +203,7 @@ class Workload:
 
     @property
     def ncomp(self) -> int:
-        return 1 if self.form == FORM_MASS else self.mesh.dim
+        return 1 if self.form in (FORM_MASS, FORM_LAPLACE, FORM_HELMHOLTZ) else self.mesh.dim
 
     @property
     def n_dof(self) -> int:
@@ -235,7 +235,7 @@ def workload(name: str, n: int | None = None, seed: int | None = None,
     n = n0 if n is None else n
     rng = np.random.default_rng(seed0 if seed is None else seed)
     mesh = make_mesh(dim, n, k, jit, rng)
-    ncomp = 1 if form == FORM_MASS else dim
+    ncomp = 1 if form in (FORM_MASS, FORM_LAPLACE, FORM_HELMHOLTZ) else dim
     if form in (FORM_NH, FORM_SVK):
         u = nh_displacement(rng, mesh)
     else:

@@ -10,8 +10,8 @@ Pieces:
 * ``quadrature.symmetric`` -- fully symmetric rules (moment equations, scipy least squares);
 * ``basis.tabulate``     -- Silvester-formula P_k Lagrange values and reference gradients;
 * ``fem_oracle.c``       -- the per-cell loop of the paper's generic action kernel
-  (Sec. 2.3) for the mass, linear elasticity, neo-Hookean and St Venant-Kirchhoff forms
-  (App. A), the hyperelastic VJPs written as the literal transpose of the tangent, the
+  (Sec. 2.3) for the mass, Laplace, Helmholtz, linear elasticity, neo-Hookean and
+  St Venant-Kirchhoff forms (App. A), the hyperelastic VJPs written as the literal transpose of the tangent, the
   discrete energies, and greedy first-fit colouring;
 * ``exact``              -- quadrature-free assembly of mass and elasticity matrices by
   exact integration of barycentric monomials (the brute-force pin).
@@ -34,7 +34,8 @@ _SRC = os.path.join(_HERE, "fem_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-FORM_MASS, FORM_ELAST, FORM_NH, FORM_SVK = 0, 1, 2, 3
+FORM_MASS, FORM_ELAST, FORM_NH, FORM_SVK, FORM_LAPLACE, FORM_HELMHOLTZ = 0, 1, 2, 3, 4, 5
+SCALAR_FORMS = (FORM_MASS, FORM_LAPLACE, FORM_HELMHOLTZ)
 
 
 def build() -> str:
@@ -141,7 +142,7 @@ def action(form: int, mesh, u: np.ndarray, quad_degree: int, params=(),
     lib = _load()
     t = tables(mesh.dim, mesh.k, quad_degree, family)
     cv, cn, xy = _mesh_arrays(mesh)
-    ncomp = 1 if form == FORM_MASS else mesh.dim
+    ncomp = 1 if form in SCALAR_FORMS else mesh.dim
     n_dof = mesh.n_node * ncomp
     u = np.ascontiguousarray(u, dtype=np.float64)
     assert u.shape == (n_dof,)
@@ -158,7 +159,7 @@ def vjp(form: int, mesh, u: np.ndarray, v: np.ndarray, quad_degree: int, params=
     lib = _load()
     t = tables(mesh.dim, mesh.k, quad_degree, family)
     cv, cn, xy = _mesh_arrays(mesh)
-    ncomp = 1 if form == FORM_MASS else mesh.dim
+    ncomp = 1 if form in SCALAR_FORMS else mesh.dim
     n_dof = mesh.n_node * ncomp
     u = np.ascontiguousarray(u, dtype=np.float64)
     v = np.ascontiguousarray(v, dtype=np.float64)

@@ -1,4 +1,5 @@
-"""Quadrature-free assembly of the mass and elasticity matrices -- TEST INFRASTRUCTURE ONLY.
+"""Quadrature-free assembly of the mass, Laplace and elasticity matrices -- TEST
+INFRASTRUCTURE ONLY.
 
 A brute-force pin for the oracle: every basis function is expanded into a polynomial in
 the barycentric coordinates lambda_0..lambda_d (Silvester product, multiplied out), the
@@ -141,3 +142,16 @@ def assemble_elasticity(mesh, lam: float, mu: float) -> np.ndarray:
         idx = (mesh.cell_nodes[cell][:, None] * d + np.arange(d)[None, :]).ravel()
         K[np.ix_(idx, idx)] += Ke.reshape(n * d, n * d)
     return K
+
+
+def assemble_laplace(mesh) -> np.ndarray:
+    """L[a, b] = int grad phi_a . grad phi_b."""
+    d = mesh.dim
+    R = _ref(d, mesh.k)
+    L = np.zeros((mesh.n_node, mesh.n_node))
+    for cell in range(mesh.n_cell):
+        vol, gl = _cell_bary(mesh.coords[mesh.cell_verts[cell]])
+        D = vol * np.einsum("aibk,ij,kl->ajbl", R.grad, gl, gl)
+        nodes = mesh.cell_nodes[cell]
+        L[np.ix_(nodes, nodes)] += np.einsum("ajbj->ab", D)
+    return L

@@ -22,7 +22,8 @@
  *     St Venant-Kirchhoff, body force 0):  r = int P(F) : grad v,
  *     F = I + grad u,  P = dPsi/dF = mu (F - F^{-T}) + lam ln(det F) F^{-T};
  *   3 St Venant-Kirchhoff residual (the paper's hyperelastic law, App. A): E = (F^T F - I)/2,
- *     S = lam tr(E) I + 2 mu E, P = F S (energy Psi = lam/2 tr(E)^2 + mu E:E).
+ *     S = lam tr(E) I + 2 mu E, P = F S (energy Psi = lam/2 tr(E)^2 + mu E:E);
+ *   4 Laplace  a = int grad u . grad v;   5 Helmholtz  a = int grad u . grad v + u v.
  *
  * Layouts: coords [n_vert][d]; cell_verts [n_cell][d+1]; cell_nodes [n_cell][nloc];
  * vectors node-major interleaved, value (node, c) at node*ncomp + c;
@@ -32,7 +33,7 @@
 #include <stdint.h>
 #include <string.h>
 
-enum { OR_MASS = 0, OR_ELAST = 1, OR_NH = 2, OR_SVK = 3 };
+enum { OR_MASS = 0, OR_ELAST = 1, OR_NH = 2, OR_SVK = 3, OR_LAPLACE = 4, OR_HELMHOLTZ = 5 };
 
 /* largest local node count handled (P8 triangle: 45, P6 tetrahedron: 84) */
 #define ORACLE_MAX_NLOC 128
@@ -214,7 +215,8 @@ void oracle_action(int form, int d, int nloc, int nq, const double *phi, const d
                    const double *coords, const int32_t *cell_nodes, double lam, double mu,
                    const double *u, double *y, int64_t n_dof)
 {
-    const int ncomp = (form == OR_MASS) ? 1 : d;
+    const int scalar = form == OR_MASS || form == OR_LAPLACE || form == OR_HELMHOLTZ;
+    const int ncomp = scalar ? 1 : d;
     double uloc[ORACLE_MAX_NLOC * 3], out[ORACLE_MAX_NLOC * 3];
     memset(y, 0, sizeof(double) * (size_t)n_dof);
     for (int64_t cell = 0; cell < n_cell; ++cell) {
@@ -225,14 +227,30 @@ void oracle_action(int form, int d, int nloc, int nq, const double *phi, const d
             out[i] = 0.0;
         for (int q = 0; q < nq; ++q) {
             const double W = w[q] * detJ;
-            if (form == OR_MASS) {
+            if (form == OR_MASS || form == OR_HELMHOLTZ) {
                 double uq = 0.0;
                 for (int a = 0; a < nloc; ++a)
                     uq += phi[q * nloc + a] * uloc[a];
                 double e = W * uq;
                 for (int a = 0; a < nloc; ++a)
                     out[a] += phi[q * nloc + a] * e;
-            } else {
+            }
+            if (form == OR_LAPLACE || form == OR_HELMHOLTZ) {
+                /* physical gradients: grad phi_a = K^T grad_ref phi_a, grad u_h = sum_a u_a grad phi_a */
+                const double *dq = dphi + (int64_t)q * nloc * d;
+                double gu[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < nloc; ++a)
+                    for (int j = 0; j < d; ++j)
+                        for (int r = 0; r < d; ++r)
+                            gu[j] += uloc[a] * dq[a * d + r] * K[r][j];
+                for (int a = 0; a < nloc; ++a)
+                    for (int j = 0; j < d; ++j) {
+                        double gphi = 0.0;
+                        for (int r = 0; r < d; ++r)
+                            gphi += dq[a * d + r] * K[r][j];
+                        out[a] += W * gphi * gu[j];
+                    }
+            } else if (form != OR_MASS && form != OR_HELMHOLTZ) {
                 double G[3][3], S[3][3], E[3][3];
                 const double *dq = dphi + (int64_t)q * nloc * d;
                 physical_gradient(d, nloc, dq, K, uloc, G);

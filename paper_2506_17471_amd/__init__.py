@@ -23,7 +23,8 @@ __all__ = ["FORM_MASS", "FORM_ELASTICITY", "FORM_NEOHOOKEAN", "FemError", "Plan"
            "lib", "reference_tables", "colouring", "check_patch_layout", "LIB_PATH", "Batch",
            "SCATTER_COLOUR", "SCATTER_PATCH"]
 
-FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN, FORM_SVK = 0, 1, 2, 3
+FORM_MASS, FORM_ELASTICITY, FORM_NEOHOOKEAN, FORM_SVK, FORM_LAPLACE, FORM_HELMHOLTZ = 0, 1, 2, 3, 4, 5
+SCALAR_FORMS = (FORM_MASS, FORM_LAPLACE, FORM_HELMHOLTZ)
 QUAD_CONICAL, QUAD_SYMMETRIC = 0, 1
 SCATTER_COLOUR, SCATTER_PATCH = 0, 1
 SUM_ELEMENT, SUM_COLOURED = 1, 2
@@ -332,7 +333,7 @@ def action_once(form: int, dim: int, degree: int, quad_degree: int, coords, cell
     cell_verts = np.ascontiguousarray(cell_verts, dtype=np.int32)
     cell_nodes = np.ascontiguousarray(cell_nodes, dtype=np.int32)
     prm = np.ascontiguousarray(params, dtype=np.float64)
-    n = int(n_node) * (1 if form == FORM_MASS else dim)
+    n = int(n_node) * (1 if form in SCALAR_FORMS else dim)
     if out is None:
         out = torch.empty_like(u)
     _check(lib().fem_action_once(form, dim, degree, quad_degree, coords.shape[0],

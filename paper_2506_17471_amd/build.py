@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfemx.so")
 SOURCES = ["kernels_neohookean.hip", "kernels_svk.hip", "kernels_elasticity.hip",
-           "kernels_mass.hip", "kernels.hip", "plan.cpp", "refel.cpp", "tune.cpp", "batch.cpp"]
+           "kernels_mass.hip", "kernels_laplace.hip", "kernels_helmholtz.hip", "kernels.hip",
+           "plan.cpp", "refel.cpp", "tune.cpp", "batch.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for the whole library (the build never relies on

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/fem_action.h"
+#include "internal.h"
 
 #define FEMX_CONSTANT __attribute__((address_space(4)))
 
@@ -17,10 +18,13 @@ __host__ __device__ constexpr int nloc_of(int dim, int k)
     return dim == 2 ? (k + 1) * (k + 2) / 2 : (k + 1) * (k + 2) * (k + 3) / 6;
 }
 
-// doubles per quadrature-point record of the kernel table (see table_record())
+// doubles per quadrature-point record of the kernel table (see table_record()): values
+// phi_a (mass, Helmholtz), reference derivatives (all but mass), the weight; even length
 __host__ __device__ constexpr int record_of(int form, int dim, int nloc)
 {
-    return (((form == FEM_MASS ? nloc : dim * nloc) + 1) + 1) & ~1;
+    const int vals = (form == FEM_MASS || form == FEM_HELMHOLTZ) ? nloc : 0;
+    const int ders = form == FEM_MASS ? 0 : dim * nloc;
+    return (vals + ders + 1 + 1) & ~1;
 }
 
 // 1/d: hardware reciprocal estimate refined by two Newton-Raphson steps (each doubles the
@@ -357,10 +361,10 @@ __device__ __forceinline__ void pointwise(const double (&G)[DIM][DIM], const dou
 // values arrive through scalar loads.
 template <int FORM, int DIM, int K, bool VJP>
 __device__ __forceinline__ void cell_quadrature(
-    const double (&ul)[nloc_of(DIM, K)][FORM == FEM_MASS ? 1 : DIM],
-    const double (&vl)[VJP ? nloc_of(DIM, K) : 1][FORM == FEM_MASS ? 1 : DIM],
+    const double (&ul)[nloc_of(DIM, K)][ncomp_of(FORM, DIM)],
+    const double (&vl)[VJP ? nloc_of(DIM, K) : 1][ncomp_of(FORM, DIM)],
     const double (&Kinv)[DIM][DIM], double adet, const double *table, int nq, double lam,
-    double mu, double (&yl)[nloc_of(DIM, K)][FORM == FEM_MASS ? 1 : DIM])
+    double mu, double (&yl)[nloc_of(DIM, K)][ncomp_of(FORM, DIM)])
 {
     constexpr int NLOC = nloc_of(DIM, K);
     constexpr int REC = record_of(FORM, DIM, NLOC);
@@ -377,6 +381,59 @@ __device__ __forceinline__ void cell_quadrature(
             const double e = t[NLOC] * adet * uq;
 #pragma unroll
             for (int n = 0; n < NLOC; ++n) yl[n][0] = fma(t[n], e, yl[n][0]);
+        }
+    } else if constexpr (FORM == FEM_LAPLACE || FORM == FEM_HELMHOLTZ) {
+        // record: [phi_a (Helmholtz only); d phi_a / d xi_r, r-major; w]
+        constexpr int D0 = FORM == FEM_HELMHOLTZ ? NLOC : 0;
+        // K K^T maps reference derivatives of u to the flux against reference test
+        // derivatives: grad phi_a . grad u = sum_rs dref_r phi_a (K K^T)_rs dref_s u
+        double KKt[DIM][DIM];
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int s2 = 0; s2 < DIM; ++s2) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) acc = fma(Kinv[r][j], Kinv[s2][j], acc);
+                KKt[r][s2] = acc;
+            }
+#pragma unroll
+        for (int n = 0; n < NLOC; ++n) yl[n][0] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < nq; ++q) {
+            const FEMX_CONSTANT double *t = tab + q * REC;
+            double g[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int n = 0; n < NLOC; ++n) acc = fma(t[D0 + r * NLOC + n], ul[n][0], acc);
+                g[r] = acc;
+            }
+            const double W = t[D0 + DIM * NLOC] * adet;
+            double f[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int s2 = 0; s2 < DIM; ++s2) acc = fma(KKt[r][s2], g[s2], acc);
+                f[r] = W * acc;
+            }
+            double e = 0.0;
+            if constexpr (FORM == FEM_HELMHOLTZ) {
+                double uq = 0.0;
+#pragma unroll
+                for (int n = 0; n < NLOC; ++n) uq = fma(t[n], ul[n][0], uq);
+                e = W * uq;
+            }
+#pragma unroll
+            for (int n = 0; n < NLOC; ++n) {
+                double acc = yl[n][0];
+                if constexpr (FORM == FEM_HELMHOLTZ) acc = fma(t[n], e, acc);
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) acc = fma(t[D0 + r * NLOC + n], f[r], acc);
+                yl[n][0] = acc;
+            }
         }
     } else {
 #pragma unroll

@@ -170,6 +170,12 @@ size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_n
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
 // the hyperelastic forms: nonlinear residuals whose VJP is a tangent action at u
 inline bool nonlinear_form(int form) { return form == FEM_NEOHOOKEAN || form == FEM_SVK; }
+// scalar forms carry one component per node, vector forms dim (host and device)
+constexpr bool scalar_form(int form)
+{
+    return form == FEM_MASS || form == FEM_LAPLACE || form == FEM_HELMHOLTZ;
+}
+constexpr int ncomp_of(int form, int dim) { return scalar_form(form) ? 1 : dim; }
 bool pair_available(int form, int dim, int degree);
 bool triple_available(int form, int dim, int degree);
 hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch, int sum_mode,

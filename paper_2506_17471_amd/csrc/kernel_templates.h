@@ -44,6 +44,8 @@ Kernels lookup_mass(int dim, int degree, bool vjp);
 Kernels lookup_elasticity(int dim, int degree, bool vjp);
 Kernels lookup_neohookean(int dim, int degree, bool vjp);
 Kernels lookup_svk(int dim, int degree, bool vjp);
+Kernels lookup_laplace(int dim, int degree, bool vjp);
+Kernels lookup_helmholtz(int dim, int degree, bool vjp);
 
 constexpr int kMaxBlock = 256;
 
@@ -57,7 +59,7 @@ constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc)
 {
     if (lpc == 3) return 1;
     if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : 4;
-    return (!vjp && dim == 2 && k <= 4 && form != FEM_MASS) ? 3 : 1;
+    return (!vjp && dim == 2 && k <= 4 && !scalar_form(form)) ? 3 : 1;
 }
 
 template <int DIM>
@@ -81,7 +83,7 @@ template <int FORM, int DIM, int K, bool VJP>
 __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
 {
     constexpr int NLOC = nloc_of(DIM, K);
-    constexpr int NC = FORM == FEM_MASS ? 1 : DIM;
+    constexpr int NC = ncomp_of(FORM, DIM);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.count) return;
     const int64_t s = a.begin + i;
@@ -184,9 +186,9 @@ template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
 __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 {
     constexpr int NLOC = nloc_of(DIM, K);
-    constexpr int NC = FORM == FEM_MASS ? 1 : DIM;
-    static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && FORM != FEM_MASS) ||
-                      (LPC == 3 && DIM == 3 && FORM != FEM_MASS),
+    constexpr int NC = ncomp_of(FORM, DIM);
+    static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && !scalar_form(FORM)) ||
+                      (LPC == 3 && DIM == 3 && !scalar_form(FORM)),
                   "lane split");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -233,7 +235,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
         stage_copy(a.csr_off + nb, U + 1, tid, nthreads, b_off);
         stage_copy(a.csr_slots + e_base, n_slots, tid, nthreads, b_slot);
     }
-    stage_nodes<NC, VJP, FORM == FEM_MASS ? 4 : 8>(a, nb, U, tid, nthreads, lds, b_node);
+    stage_nodes<NC, VJP, scalar_form(FORM) ? 4 : 8>(a, nb, U, tid, nthreads, lds, b_node);
     __syncthreads();
 
     // 2. the cell's values from LDS
@@ -399,8 +401,8 @@ Kernels entry()
     Kernels k{};
     k.colour = colour_kernel<FORM, DIM, K, VJP>;
     fill_lanes<FORM, DIM, K, VJP, 1>(k);
-    if constexpr (DIM == 2 && FORM != FEM_MASS) fill_lanes<FORM, DIM, K, VJP, 2>(k);
-    if constexpr (DIM == 3 && FORM != FEM_MASS) fill_lanes<FORM, DIM, K, VJP, 3>(k);
+    if constexpr (DIM == 2 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 2>(k);
+    if constexpr (DIM == 3 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 3>(k);
     return k;
 }
 

@@ -67,6 +67,8 @@ Kernels lookup(int form, int dim, int degree, bool vjp)
     case FEM_ELASTICITY: return lookup_elasticity(dim, degree, vjp);
     case FEM_NEOHOOKEAN: return lookup_neohookean(dim, degree, vjp);
     case FEM_SVK: return lookup_svk(dim, degree, vjp);
+    case FEM_LAPLACE: return lookup_laplace(dim, degree, vjp);
+    case FEM_HELMHOLTZ: return lookup_helmholtz(dim, degree, vjp);
     default: return Kernels{};
     }
 }
@@ -96,7 +98,7 @@ hipError_t launch_action(const fem_plan &p, const LaunchArgs &a, int block, bool
 size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode)
 {
     const int nloc = nloc_of(dim, degree);
-    const int nc = form == FEM_MASS ? 1 : dim;
+    const int nc = ncomp_of(form, dim);
     const size_t stage = (size_t)max_nodes * nc * (vjp ? 2 : 1);
     if (sum_mode == SUM_COLOURED) return stage;
     const size_t elem = (size_t)patch * nloc * nc;

@@ -204,7 +204,7 @@ void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
 {
     using femx::Error;
     const int d = p->dim, nv = d + 1, nloc = p->nloc;
-    if (p->form != FEM_MASS) {
+    if (!femx::scalar_form(p->form)) {
         if (n_params < 2 || !params) throw Error(FEM_E_ARG, "vector forms need params {lambda, mu}");
         p->lam = params[0];
         p->mu = params[1];
@@ -824,7 +824,7 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
     const int st = guarded([&] {
         using femx::Error;
         if (!out) throw Error(FEM_E_ARG, "null output pointer");
-        if (form < FEM_MASS || form > FEM_SVK) throw Error(FEM_E_UNSUPPORTED, "unknown form");
+        if (form < FEM_MASS || form > FEM_HELMHOLTZ) throw Error(FEM_E_UNSUPPORTED, "unknown form");
         if (dim != 2 && dim != 3) throw Error(FEM_E_UNSUPPORTED, "dim must be 2 or 3");
         if (degree < 1 || degree > (dim == 2 ? 6 : 4) || !femx::kernel_available(form, dim, degree))
             throw Error(FEM_E_UNSUPPORTED, "degree " + std::to_string(degree) + " not built for dim " +
@@ -840,7 +840,7 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
         p->degree = degree;
         p->quad_degree = quad_degree;
         p->nloc = femx::n_local(dim, degree);
-        p->ncomp = form == FEM_MASS ? 1 : dim;
+        p->ncomp = femx::ncomp_of(form, dim);
         p->n_vert = n_vert;
         p->n_cell = n_cell;
         p->n_node = n_node;
@@ -1007,7 +1007,7 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
 {
     return guarded([&] {
         using femx::Error;
-        if (form < FEM_MASS || form > FEM_SVK || (dim != 2 && dim != 3) || degree < 1 ||
+        if (form < FEM_MASS || form > FEM_HELMHOLTZ || (dim != 2 && dim != 3) || degree < 1 ||
             degree > 8)
             throw Error(FEM_E_UNSUPPORTED, "unsupported form/dim/degree");
         if (n_vert < 0 || n_cell < 1 || n_node < 0) throw Error(FEM_E_ARG, "bad size");
@@ -1017,7 +1017,7 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
         p.dim = dim;
         p.degree = degree;
         p.nloc = femx::n_local(dim, degree);
-        p.ncomp = form == FEM_MASS ? 1 : dim;
+        p.ncomp = femx::ncomp_of(form, dim);
         p.n_vert = n_vert;
         p.n_cell = n_cell;
         p.n_node = n_node;

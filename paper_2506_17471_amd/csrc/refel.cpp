@@ -505,25 +505,28 @@ RefTables reference_tables(int dim, int degree, int quad_degree, int family)
 
 int table_record(int form, int dim, int nloc)
 {
-    const int n = (form == FEM_MASS ? nloc : dim * nloc) + 1;
-    return (n + 1) & ~1;
+    const int vals = (form == FEM_MASS || form == FEM_HELMHOLTZ) ? nloc : 0;
+    const int ders = form == FEM_MASS ? 0 : dim * nloc;
+    return (vals + ders + 1 + 1) & ~1;
 }
 
+// Per quadrature point: phi_a (mass, Helmholtz), then d phi_a / d xi_r for r, a (all other
+// forms, r-major), then the weight; zero-padded to an even length.
 std::vector<double> kernel_table(int form, const RefTables &t)
 {
     const int rec = table_record(form, t.dim, t.nloc);
     std::vector<double> out((size_t)t.nq * rec, 0.0);
+    const bool vals = form == FEM_MASS || form == FEM_HELMHOLTZ, ders = form != FEM_MASS;
     for (int q = 0; q < t.nq; ++q) {
         double *o = &out[(size_t)q * rec];
-        if (form == FEM_MASS) {
-            for (int a = 0; a < t.nloc; ++a) o[a] = t.phi[(size_t)q * t.nloc + a];
-            o[t.nloc] = t.weights[q];
-        } else {
+        int k = 0;
+        if (vals)
+            for (int a = 0; a < t.nloc; ++a) o[k++] = t.phi[(size_t)q * t.nloc + a];
+        if (ders)
             for (int r = 0; r < t.dim; ++r)
                 for (int a = 0; a < t.nloc; ++a)
-                    o[r * t.nloc + a] = t.dphi[((size_t)q * t.nloc + a) * t.dim + r];
-            o[t.dim * t.nloc] = t.weights[q];
-        }
+                    o[k++] = t.dphi[((size_t)q * t.nloc + a) * t.dim + r];
+        o[k] = t.weights[q];
     }
     return out;
 }

@@ -43,7 +43,9 @@ def gpu(x):
 
 
 def params_for(form):
-    return () if form == fx.FORM_MASS else (LAME if form == fx.FORM_ELASTICITY else NH)
+    if form in fx.SCALAR_FORMS:
+        return ()
+    return LAME if form == fx.FORM_ELASTICITY else NH
 
 
 HYPERELASTIC = (fx.FORM_NEOHOOKEAN, fx.FORM_SVK)
@@ -51,7 +53,7 @@ HYPERELASTIC = (fx.FORM_NEOHOOKEAN, fx.FORM_SVK)
 
 def inputs(form, mesh, seed):
     rng = np.random.default_rng(seed)
-    ncomp = 1 if form == fx.FORM_MASS else mesh.dim
+    ncomp = 1 if form in fx.SCALAR_FORMS else mesh.dim
     if form == fx.FORM_NEOHOOKEAN:
         u = meshgen.nh_displacement(rng, mesh, 0.01)
         # an admissible state: det F > 0 at every quadrature point of the rule used
@@ -66,11 +68,11 @@ def inputs(form, mesh, seed):
 
 
 def qdeg(form, k):
-    return 2 * (k - 1) if form == fx.FORM_ELASTICITY else 2 * k
+    return 2 * (k - 1) if form in (fx.FORM_ELASTICITY, fx.FORM_LAPLACE) else 2 * k
 
 
-CASES = [(f, 2, k) for f in (0, 1, 2, 3) for k in range(1, 7)] + \
-        [(f, 3, k) for f in (0, 1, 2, 3) for k in range(1, 5)]
+CASES = [(f, 2, k) for f in range(6) for k in range(1, 7)] + \
+        [(f, 3, k) for f in range(6) for k in range(1, 5)]
 
 
 def plan_family(w):
@@ -86,7 +88,7 @@ STRAT_IDS = ["patch", "patch64x1e", "patch128x1c", "colour", "patch42x3e", "patc
 
 
 def apply_strategy(plan, strategy, form, dim):
-    if strategy[2] == 3 and (dim != 3 or form == fx.FORM_MASS):
+    if strategy[2] == 3 and (dim != 3 or form in fx.SCALAR_FORMS):
         pytest.skip("three lanes per cell exist for the 3D vector forms only")
     plan.set_strategy(*strategy)
 

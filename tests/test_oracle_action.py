@@ -4,6 +4,9 @@ Each pin is fixed by the mathematics, not by the oracle itself:
   mass         partition of unity (sum of M 1 = |Omega| = 1); P2 closed form of M 1;
                P1 element matrix |T| (1 + delta_ab) / ((d+1)(d+2));
                equality with the quadrature-free exact assembly (brute force);
+  Laplace      constants in the kernel; affine patch test; symmetry; the P1 reference
+               element matrix; exact assembly (brute force);
+  Helmholtz    equals exact Laplace plus exact mass assembly;
   elasticity   rigid modes in the kernel; affine patch test; symmetry;
                lambda = 0, mu = 1/2 gives sigma = eps; exact assembly (brute force);
   neo-Hookean and St Venant-Kirchhoff
@@ -24,6 +27,7 @@ import oracle
 from oracle import exact
 
 F_MASS, F_EL, F_NH, F_SVK = oracle.FORM_MASS, oracle.FORM_ELAST, oracle.FORM_NH, oracle.FORM_SVK
+F_LAP, F_HELM = oracle.FORM_LAPLACE, oracle.FORM_HELMHOLTZ
 HYPER = pytest.mark.parametrize("form", [F_NH, F_SVK], ids=["nh", "svk"])
 
 
@@ -87,6 +91,48 @@ def test_mass_equals_exact_assembly(dim, n, k):
     y = oracle.action(F_MASS, m, u, 2 * k)
     M = exact.assemble_mass(m)
     assert np.max(np.abs(y - M @ u)) < 1e-14 * max(1, np.max(np.abs(M @ u))) * 10
+
+
+# ------------------------------------------------------------------- Laplace and Helmholtz
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 3), (2, 6), (3, 1), (3, 2), (3, 4)])
+def test_laplace_kernel_patch_test_symmetry(dim, k):
+    m = small_mesh(dim, 3 if dim == 2 else 2, k, seed=12, jitter=0.2 if dim == 2 else 0.1)
+    qd = 2 * (k - 1)
+    y1 = oracle.action(F_LAP, m, np.ones(m.n_node), qd)
+    assert np.max(np.abs(y1)) < 1e-13
+    # affine u: the residual vanishes at every interior node (divergence theorem)
+    X = lattice_positions(m)
+    u = 0.3 + X @ np.arange(1.0, dim + 1.0)
+    y = oracle.action(F_LAP, m, u, qd)
+    interior = np.all((X > 1e-9) & (X < 1 - 1e-9), axis=1)
+    assert np.max(np.abs(y[interior])) < 1e-12 * max(1.0, np.max(np.abs(y)))
+    rng = np.random.default_rng(13)
+    a, b = rng.uniform(-1, 1, (2, m.n_node))
+    La, Lb = oracle.action(F_LAP, m, a, qd), oracle.action(F_LAP, m, b, qd)
+    assert abs(b @ La - a @ Lb) < 1e-12 * abs(b @ La)
+
+
+def test_laplace_p1_reference_element():
+    """Textbook P1 stiffness of the reference triangle: [[1,-1/2,-1/2],[-1/2,1/2,0],[-1/2,0,1/2]]."""
+    m = meshgen.Mesh(2, 1, 1, np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]),
+                     np.array([[0, 1, 2]], dtype=np.int32), np.array([[0, 1, 2]], dtype=np.int32),
+                     3, 1.0)
+    Kref = np.array([[1.0, -0.5, -0.5], [-0.5, 0.5, 0.0], [-0.5, 0.0, 0.5]])
+    cols = np.array([oracle.action(F_LAP, m, e, 0) for e in np.eye(3)]).T
+    assert np.max(np.abs(cols - Kref)) < 1e-15
+
+
+@pytest.mark.parametrize("dim,n,k", [(2, 2, 2), (2, 2, 4), (3, 1, 2), (3, 1, 3)])
+def test_laplace_helmholtz_equal_exact_assembly(dim, n, k):
+    m = small_mesh(dim, n, k, seed=14, jitter=0.2 if dim == 2 else 0.1)
+    rng = np.random.default_rng(15)
+    u = rng.uniform(-1, 1, m.n_node)
+    L = exact.assemble_laplace(m)
+    M = exact.assemble_mass(m)
+    yl = oracle.action(F_LAP, m, u, 2 * (k - 1))
+    yh = oracle.action(F_HELM, m, u, 2 * k)
+    assert np.max(np.abs(yl - L @ u)) < 1e-13 * np.max(np.abs(L @ u))
+    assert np.max(np.abs(yh - (L + M) @ u)) < 1e-13 * np.max(np.abs((L + M) @ u))
 
 
 # ----------------------------------------------------------------------------- elasticity

@@ -31,8 +31,8 @@ MUTATIONS = {
     "no_abs_det": ("double detJ = fabs(geometry(d, x, J, K));\n        for (int i = 0; i < nloc * ncomp; ++i)",
                    "double detJ = geometry(d, x, J, K);\n        for (int i = 0; i < nloc * ncomp; ++i)",
                    [lambda: pins.test_mass_partition_of_unity(3, 2)]),
-    "weight_without_det": ("const double W = w[q] * detJ;\n            if (form == OR_MASS)",
-                           "const double W = w[q];\n            if (form == OR_MASS)",
+    "weight_without_det": ("const double W = w[q] * detJ;\n            if (form == OR_MASS || form == OR_HELMHOLTZ)",
+                           "const double W = w[q];\n            if (form == OR_MASS || form == OR_HELMHOLTZ)",
                            [lambda: pins.test_mass_partition_of_unity(2, 2)]),
     "elasticity_half_shear": ("S[i][j] = 2.0 * mu * eps + (i == j ? lam * tr : 0.0);",
                               "S[i][j] = mu * eps + (i == j ? lam * tr : 0.0);",
@@ -59,6 +59,12 @@ MUTATIONS = {
     "svk_tangent_drops_geometric_term": ("C = (i == k ? S2[l][j] : 0.0) + lam * F[i][j] * F[k][l]",
                                          "C = lam * F[i][j] * F[k][l]",
                                          [lambda: pins.test_hyper_vjp_against_finite_differences(pins.F_SVK, 2, 2, 2)]),
+    "laplace_gradient_not_mapped": ("                            gu[j] += uloc[a] * dq[a * d + r] * K[r][j];",
+                                    "                            gu[j] += uloc[a] * dq[a * d + r] * K[j][r];",
+                                    [lambda: pins.test_laplace_helmholtz_equal_exact_assembly(2, 2, 2)]),
+    "helmholtz_mass_term_dropped": ("if (form == OR_MASS || form == OR_HELMHOLTZ) {\n                double uq",
+                                    "if (form == OR_MASS) {\n                double uq",
+                                    [lambda: pins.test_laplace_helmholtz_equal_exact_assembly(2, 2, 2)]),
     "colouring_ignores_conflicts": ("if ((masks[nd * nwords + c / 64] >> (c % 64)) & 1u) {",
                                     "if (0) {",
                                     [lambda: pins.test_colouring_valid_and_greedy(2, 6, 1)]),
