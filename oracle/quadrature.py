@@ -85,6 +85,10 @@ SYMMETRIC_APPROX = {
     (2, 10): [("c", (), 0.0416099), ("aab", (0.0285035,), 0.00547564),
               ("aab", (0.162913,), 0.0263260), ("abc", (0.153303, 0.0336857), 0.0146614),
               ("abc", (0.363363, 0.607330), 0.0176975), ("abc", (0.336696, 0.146812), 0.0281386)],
+    (2, 12): [("aab", (0.271463,), 0.0312706), ("aab", (0.488204,), 0.0121334),
+              ("aab", (0.440112,), 0.0249592), ("aab", (0.109258,), 0.0142430),
+              ("aab", (0.0246464,), 0.00396582), ("abc", (0.255454, 0.116296), 0.0216137),
+              ("abc", (0.127280, 0.851338), 0.00754184), ("abc", (0.291656, 0.0230342), 0.0108918)],
     (3, 5): [("aaab", (0.310886,), 0.0187813), ("aaab", (0.0927353,), 0.0122488),
              ("aabb", (0.0455037,), 0.00709100)],
     (3, 6): [("aaab", (0.214603,), 0.00665379), ("aaab", (0.0406740,), 0.00167954),
@@ -95,7 +99,7 @@ SYMMETRIC_APPROX = {
 def _orbit(dim: int, kind: str, prm) -> list[tuple]:
     """Barycentric points of one orbit: the distinct arrangements of its symbol pattern."""
     if kind == "c":
-        return [tuple([1.0 / (dim + 1)] * (dim + 1))]
+        return [tuple([np.longdouble(1) / (dim + 1)] * (dim + 1))]
     if dim == 2 and kind == "aab":
         value = {"a": prm[0], "b": 1.0 - 2.0 * prm[0]}
     elif dim == 2 and kind == "abc":
@@ -171,8 +175,35 @@ def symmetric(dim: int, degree: int) -> tuple[np.ndarray, np.ndarray]:
     for _, prm, w in structure:
         x0 += list(prm) + [w]
     sol = least_squares(residual, np.asarray(x0), xtol=1e-15, ftol=1e-15, gtol=1e-15)
-    pts, wts = _expand(dim, structure, sol.x)
-    if np.max(np.abs(residual(sol.x))) > 1e-14 or np.any(wts <= 0):
+    # polish in extended precision (numpy long double): Gauss-Newton with a central-
+    # difference Jacobian, so the root is resolved below double rounding even where the
+    # moment equations are ill-conditioned
+    exact_ld = np.array([np.longdouble(math.prod(math.factorial(k) for k in e))
+                         / np.longdouble(math.factorial(int(sum(e)) + dim)) for e in mons])
+
+    def residual_ld(x):
+        pts, wts = _expand(dim, structure, x)
+        vals = np.prod(pts.astype(np.longdouble)[:, None, :] ** mons[None, :, :], axis=2)
+        return (wts.astype(np.longdouble) @ vals - exact_ld) / exact_ld
+
+    x = sol.x.astype(np.longdouble)
+    for _ in range(30):
+        r = residual_ld(x)
+        if np.max(np.abs(r)) < 1e-18:
+            break
+        J = np.empty((len(r), len(x)))
+        for k in range(len(x)):
+            h = np.longdouble(1e-8) * max(np.longdouble(1e-2), abs(x[k]))
+            xp, xm = x.copy(), x.copy()
+            xp[k] += h
+            xm[k] -= h
+            J[:, k] = ((residual_ld(xp) - residual_ld(xm)) / (2 * h)).astype(np.float64)
+        dx = np.linalg.lstsq(J, -r.astype(np.float64), rcond=None)[0]
+        x = x + dx.astype(np.longdouble)
+    pts, wts = _expand(dim, structure, x)
+    pts, wts = pts.astype(np.float64), wts.astype(np.float64)
+    sol_x = x.astype(np.float64)
+    if np.max(np.abs(residual(sol_x))) > 1e-14 or np.any(wts <= 0):
         raise RuntimeError(f"symmetric rule {dim}D degree {m} did not converge")
     lam0 = 1.0 - pts.sum(axis=1)
     if np.any(pts < -1e-15) or np.any(lam0 < -1e-15):

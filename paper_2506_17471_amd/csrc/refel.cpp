@@ -138,39 +138,41 @@ int orbit_params(int kind)
 }
 
 // barycentric coordinates of an orbit's points, appended to lam (dim + 1 per point)
-void orbit_points(int kind, const double *prm, std::vector<double> &lam)
+template <typename T>
+void orbit_points(int kind, const T *prm, std::vector<T> &lam)
 {
-    auto put = [&](std::initializer_list<double> l) { lam.insert(lam.end(), l); };
-    const double a = prm ? prm[0] : 0.0, b = (prm && orbit_params(kind) == 2) ? prm[1] : 0.0;
+    auto put = [&](std::initializer_list<T> l) { lam.insert(lam.end(), l); };
+    const T a = prm ? prm[0] : T(0), b = (prm && orbit_params(kind) == 2) ? prm[1] : T(0);
+    const T third = T(1) / 3, quarter = T(1) / 4, half = T(1) / 2;
     switch (kind) {
-    case S3: put({1.0 / 3, 1.0 / 3, 1.0 / 3}); break;
+    case S3: put({third, third, third}); break;
     case S21: {
-        const double c = 1.0 - 2.0 * a;
+        const T c = T(1) - 2 * a;
         put({a, a, c}); put({a, c, a}); put({c, a, a});
         break;
     }
     case S111: {
-        const double v[3] = {a, b, 1.0 - a - b};
+        const T v[3] = {a, b, T(1) - a - b};
         const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
         for (auto &pm : perm) put({v[pm[0]], v[pm[1]], v[pm[2]]});
         break;
     }
-    case S4: put({0.25, 0.25, 0.25, 0.25}); break;
+    case S4: put({quarter, quarter, quarter, quarter}); break;
     case S31: {
-        const double c = 1.0 - 3.0 * a;
+        const T c = T(1) - 3 * a;
         for (int k = 0; k < 4; ++k)
             for (int i = 0; i < 4; ++i) lam.push_back(i == k ? c : a);
         break;
     }
     case S22: {
-        const double c = 0.5 - a;
+        const T c = half - a;
         for (int i = 0; i < 4; ++i)
             for (int j = i + 1; j < 4; ++j)
                 for (int l = 0; l < 4; ++l) lam.push_back(l == i || l == j ? a : c);
         break;
     }
     case S211: {
-        const double c = 1.0 - 2.0 * a - b;
+        const T c = T(1) - 2 * a - b;
         for (int i = 0; i < 4; ++i)
             for (int j = 0; j < 4; ++j) {
                 if (j == i) continue;
@@ -207,6 +209,11 @@ const std::vector<SymmetricSpec> &symmetric_specs()
         {2, 10, {S3, S21, S21, S111, S111, S111},
          {0.0416099, 0.0285035, 0.00547564, 0.162913, 0.0263260, 0.153303, 0.0336857, 0.0146614,
           0.363363, 0.607330, 0.0176975, 0.336696, 0.146812, 0.0281386}},
+        // triangle, degree 12: 33 points
+        {2, 12, {S21, S21, S21, S21, S21, S111, S111, S111},
+         {0.271463, 0.0312706, 0.488204, 0.0121334, 0.440112, 0.0249592, 0.109258, 0.0142430,
+          0.0246464, 0.00396582, 0.255454, 0.116296, 0.0216137, 0.127280, 0.851338, 0.00754184,
+          0.291656, 0.0230342, 0.0108918}},
         // tetrahedron, degree 5: 14 points
         {3, 5, {S31, S31, S22}, {0.310886, 0.0187813, 0.0927353, 0.0122488, 0.0455037, 0.00709100}},
         // tetrahedron, degree 6: 24 points
@@ -217,30 +224,32 @@ const std::vector<SymmetricSpec> &symmetric_specs()
 }
 
 // exact integral of xi^e over the reference simplex: prod e_i! / (|e| + dim)!
-double monomial_integral(int dim, const int *e)
+long double monomial_integral(int dim, const int *e)
 {
-    double num = 1.0;
+    long double num = 1, den = 1;
     int tot = 0;
     for (int r = 0; r < dim; ++r) {
-        num *= std::tgamma(e[r] + 1.0);
+        for (int f = 2; f <= e[r]; ++f) num *= f;
         tot += e[r];
     }
-    return num / std::tgamma(tot + dim + 1.0);
+    for (int f = 2; f <= tot + dim; ++f) den *= f;
+    return num / den;
 }
 
-void expand(const SymmetricSpec &sp, const std::vector<double> &x, std::vector<double> &pts,
-            std::vector<double> &wts)
+template <typename T>
+void expand(const SymmetricSpec &sp, const std::vector<T> &x, std::vector<T> &pts,
+            std::vector<T> &wts)
 {
     pts.clear();
     wts.clear();
-    std::vector<double> lam;
+    std::vector<T> lam;
     size_t i = 0;
     for (int kind : sp.kinds) {
         const int np = orbit_params(kind);
         lam.clear();
-        orbit_points(kind, np ? &x[i] : nullptr, lam);
+        orbit_points<T>(kind, np ? &x[i] : nullptr, lam);
         i += np;
-        const double w = x[i++];
+        const T w = x[i++];
         const int npt = (int)lam.size() / (sp.dim + 1);
         for (int q = 0; q < npt; ++q) {
             for (int r = 1; r <= sp.dim; ++r) pts.push_back(lam[q * (sp.dim + 1) + r]);
@@ -250,18 +259,19 @@ void expand(const SymmetricSpec &sp, const std::vector<double> &x, std::vector<d
 }
 
 // relative moment errors of the rule x over all monomials of degree <= sp.degree
+template <typename T>
 void moment_residual(const SymmetricSpec &sp, const std::vector<std::array<int, 3>> &mons,
-                     const std::vector<double> &exact, const std::vector<double> &x,
-                     std::vector<double> &res)
+                     const std::vector<T> &exact, const std::vector<T> &x, std::vector<T> &res)
 {
-    std::vector<double> pts, wts;
-    expand(sp, x, pts, wts);
-    res.assign(mons.size(), 0.0);
+    std::vector<T> pts, wts;
+    expand<T>(sp, x, pts, wts);
+    res.assign(mons.size(), T(0));
     for (size_t m = 0; m < mons.size(); ++m) {
-        double s = 0.0;
+        T s = 0;
         for (size_t q = 0; q < wts.size(); ++q) {
-            double v = wts[q];
-            for (int r = 0; r < sp.dim; ++r) v *= std::pow(pts[q * sp.dim + r], mons[m][r]);
+            T v = wts[q];
+            for (int r = 0; r < sp.dim; ++r)
+                for (int e = 0; e < mons[m][r]; ++e) v *= pts[q * sp.dim + r];
             s += v;
         }
         res[m] = (s - exact[m]) / exact[m];
@@ -304,11 +314,14 @@ std::vector<double> lstsq(std::vector<double> A, std::vector<double> b, int m, i
 }
 
 // Solve the moment equations from the spec's approximate parameters by Gauss-Newton
-// (central-difference Jacobian); accept the root only if every monomial of degree <= the
-// rule's degree is integrated to 1e-14 relative, all weights are positive and all points
-// lie in the closed simplex.
+// (central-difference Jacobian, Householder QR), residuals and iterates in extended
+// precision so the root is resolved well below double rounding even where the equations
+// are ill-conditioned; accept it only if every monomial of degree <= the rule's degree is
+// integrated to 1e-14 relative, all weights are positive and all points lie in the
+// closed simplex.
 bool solve_symmetric(const SymmetricSpec &sp, std::vector<double> &pts, std::vector<double> &wts)
 {
+    using LD = long double;
     std::vector<std::array<int, 3>> mons;
     for (int i = 0; i <= sp.degree; ++i)
         for (int j = 0; i + j <= sp.degree; ++j)
@@ -317,36 +330,39 @@ bool solve_symmetric(const SymmetricSpec &sp, std::vector<double> &pts, std::vec
             } else {
                 for (int l = 0; i + j + l <= sp.degree; ++l) mons.push_back({i, j, l});
             }
-    std::vector<double> exact(mons.size());
+    std::vector<LD> exact(mons.size());
     for (size_t m = 0; m < mons.size(); ++m) exact[m] = monomial_integral(sp.dim, mons[m].data());
-    std::vector<double> x = sp.guess, r, rp, rm;
+    std::vector<LD> x(sp.guess.begin(), sp.guess.end()), r, rp, rm;
     const int n = (int)x.size(), m = (int)mons.size();
-    double prev = 1e300;
+    LD prev = 1e300L;
     for (int it = 0; it < 60; ++it) {
-        moment_residual(sp, mons, exact, x, r);
-        double err = 0.0;
-        for (double t : r) err = std::max(err, std::fabs(t));
-        if (err < 1e-15 || (err >= prev && it > 8)) break;
+        moment_residual<LD>(sp, mons, exact, x, r);
+        LD err = 0;
+        for (LD t : r) err = std::max(err, std::fabs(t));
+        if (err < 1e-18L || (err >= prev && it > 8)) break;
         prev = err;
         std::vector<double> J((size_t)m * n);
         for (int k = 0; k < n; ++k) {
-            const double h = 1e-7 * std::max(1e-2, std::fabs(x[k]));
-            std::vector<double> xp = x, xm = x;
+            const LD h = 1e-8L * std::max(LD(1e-2), std::fabs(x[k]));
+            std::vector<LD> xp = x, xm = x;
             xp[k] += h;
             xm[k] -= h;
-            moment_residual(sp, mons, exact, xp, rp);
-            moment_residual(sp, mons, exact, xm, rm);
-            for (int i = 0; i < m; ++i) J[(size_t)i * n + k] = (rp[i] - rm[i]) / (2.0 * h);
+            moment_residual<LD>(sp, mons, exact, xp, rp);
+            moment_residual<LD>(sp, mons, exact, xm, rm);
+            for (int i = 0; i < m; ++i) J[(size_t)i * n + k] = (double)((rp[i] - rm[i]) / (2 * h));
         }
         std::vector<double> negr(m);
-        for (int i = 0; i < m; ++i) negr[i] = -r[i];
+        for (int i = 0; i < m; ++i) negr[i] = -(double)r[i];
         const std::vector<double> dx = lstsq(J, negr, m, n);
         for (int k = 0; k < n; ++k) x[k] += dx[k];
     }
-    moment_residual(sp, mons, exact, x, r);
-    for (double t : r)
-        if (!(std::fabs(t) < 1e-14)) return false;
-    expand(sp, x, pts, wts);
+    moment_residual<LD>(sp, mons, exact, x, r);
+    for (LD t : r)
+        if (!(std::fabs(t) < 1e-14L)) return false;
+    std::vector<LD> lp, lw;
+    expand<LD>(sp, x, lp, lw);
+    pts.assign(lp.begin(), lp.end());
+    wts.assign(lw.begin(), lw.end());
     for (double w : wts)
         if (!(w > 0.0)) return false;
     for (size_t q = 0; q < wts.size(); ++q) {
