@@ -23,8 +23,8 @@
  *   symmetric rules (points on orbits of the simplex's symmetry group, one weight per
  *   orbit, positive weights, points inside), each an isolated root of its moment
  *   equations solved by Newton's method at plan creation: triangles of degree <= 2, 4, 6,
- *   8, 10, 12 (1, 3, 6, 12, 16, 25, 33 points), tetrahedra of degree <= 2, 5, 6 (1, 4, 14,
- *   24 points);
+ *   8, 10, 12 (1, 3, 6, 12, 16, 25, 33 points), tetrahedra of degree <= 2, 5, 6, 8 (1, 4,
+ *   14, 24, 50 points);
  *   a degree without its own rule takes the next tabulated one.  A plan uses the
  *   symmetric rule when one is built for its degree, else the conical rule
  *   (fem_plan_set_quadrature switches).  The mass and elasticity operators do not depend

@@ -93,6 +93,9 @@ SYMMETRIC_APPROX = {
              ("aabb", (0.0455037,), 0.00709100)],
     (3, 6): [("aaab", (0.214603,), 0.00665379), ("aaab", (0.0406740,), 0.00167954),
              ("aaab", (0.322338,), 0.00922620), ("aabc", (0.0636610, 0.269672), 0.00803571)],
+    (3, 8): [("aaab", (0.0834534,), 0.00200563), ("aaab", (0.0100916,), 0.000209000),
+             ("aabb", (0.449481,), 0.00454683), ("aabc", (0.0368078, 0.734271), 0.00214781),
+             ("aabc", (0.222840, 0.430062), 0.00428064), ("aabc", (0.229785, 0.513039), 0.00444881)],
 }
 
 

@@ -219,6 +219,11 @@ const std::vector<SymmetricSpec> &symmetric_specs()
         // tetrahedron, degree 6: 24 points
         {3, 6, {S31, S31, S31, S211}, {0.214603, 0.00665379, 0.0406740, 0.00167954, 0.322338,
                                        0.00922620, 0.0636610, 0.269672, 0.00803571}},
+        // tetrahedron, degree 8: 50 points
+        {3, 8, {S31, S31, S22, S211, S211, S211},
+         {0.0834534, 0.00200563, 0.0100916, 0.000209000, 0.449481, 0.00454683, 0.0368078,
+          0.734271, 0.00214781, 0.222840, 0.430062, 0.00428064, 0.229785, 0.513039,
+          0.00444881}},
     };
     return specs;
 }

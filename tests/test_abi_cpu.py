@@ -143,7 +143,7 @@ def test_patch_layout_rejects_bad_size():
         fx.check_patch_layout(0, m, 300)
 
 
-SYM_DEGREES = [(2, d) for d in range(0, 13)] + [(3, d) for d in range(0, 7)]
+SYM_DEGREES = [(2, d) for d in range(0, 13)] + [(3, d) for d in range(0, 9)]
 
 
 @pytest.mark.parametrize("dim,deg", SYM_DEGREES)
