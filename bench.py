@@ -390,6 +390,56 @@ def run_sweep(steps: int, warmup: int, tri_cells: float = 5e5, tet_cells: float 
     return out
 
 
+def spearman(a, b) -> float:
+    """Rank correlation (average ranks for ties)."""
+    from scipy.stats import rankdata
+    ra, rb = rankdata(a), rankdata(b)
+    ra, rb = ra - ra.mean(), rb - rb.mean()
+    return float((ra @ rb) / math.sqrt((ra @ ra) * (rb @ rb)))
+
+
+def run_model_eval(tri_cells: float = 5e5, tet_cells: float = 2e5):
+    """The tuner's cost model against the tuner's own measurements (the paper's evaluation
+    of its heuristic model): per case the Spearman rank correlation between predicted and
+    measured candidate times, and the top-k regret -- the throughput of the best measured
+    candidate among the model's k best, as a fraction of the best measured overall."""
+    import torch
+    import meshgen
+    import paper_2506_17471_amd as fx
+
+    cases = [(f, 2, k) for f in (0, 1, 2, 4) for k in (2, 4)] + [(f, 3, 2) for f in (0, 1, 2, 4)]
+    out = []
+    for form, dim, k in cases:
+        rng = np.random.default_rng(7 * dim + k)
+        if dim == 2:
+            mesh = meshgen.unit_square(round(math.sqrt(tri_cells / 2)), k, 0.1, rng)
+        else:
+            mesh = meshgen.unit_cube(round((tet_cells / 6) ** (1 / 3)), k, 0.05, rng)
+        ncomp = 1 if form in (0, 4, 5) else dim
+        params = () if ncomp == 1 else ((10.0, 1.0) if form in (2, 3) else
+                                        meshgen.lame_from_young(1.0, 0.3))
+        u0 = meshgen.nh_displacement(rng, mesh) if form in (2, 3) else rng.uniform(-1, 1, mesh.n_node * ncomp)
+        plan = fx.Plan.from_mesh(form, mesh, quad_degree_for(form, k), params)
+        u = torch.as_tensor(u0, device="cuda")
+        pred = {tuple(int(x) for x in r[:5]): r[5] for r in plan.tune_predict()}
+        meas = {tuple(int(x) for x in r[:5]): r[5] for r in plan.tune(u)}
+        keys = [key for key in meas if key in pred]
+        pm, mm = np.array([pred[key] for key in keys]), np.array([meas[key] for key in keys])
+        order = np.argsort(pm)
+        best = mm.min()
+        regret = {f"top{kk}": float(best / mm[order[:kk]].min()) for kk in (1, 3, 5)}
+        row = dict(form=FORM_NAMES[form], dim=dim, degree=k, candidates=len(keys),
+                   spearman=spearman(pm, mm), **regret,
+                   best_measured_ms=float(best), model_pick_ms=float(mm[order[0]]))
+        out.append(row)
+        print(f"# model {row['form']:10s} {dim}D P{k}: rho {row['spearman']:.2f} "
+              f"top1 {regret['top1']:.2f} top3 {regret['top3']:.2f} top5 {regret['top5']:.2f}",
+              file=sys.stderr, flush=True)
+        del plan, u
+    summary = {k: float(np.mean([r[k] for r in out])) for k in ("spearman", "top1", "top3", "top5")}
+    return {"cases": out, "mean": summary}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +454,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="only run the degree sweep over every built (form, dim, degree)")
+    ap.add_argument("--model-eval", action="store_true",
+                    help="only evaluate the tuner's cost model against measured candidates")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
@@ -430,6 +482,9 @@ def main():
     tune = not args.no_tune
     if args.sweep:
         print(json.dumps({"sweep": run_sweep(args.steps, args.warmup)}))
+        return
+    if args.model_eval:
+        print(json.dumps({"model_eval": run_model_eval()}))
         return
 
     def note(msg):

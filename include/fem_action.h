@@ -263,11 +263,26 @@ int fem_plan_get_timing(fem_plan *plan, double *kernel_ms, int64_t *calls);
  *          and rule family, round(log2(cell count)).
  *   results HOST f64 [max_results][6] out: strategy, cells per patch, lanes per cell,
  *          cells per workgroup (colour), sum mode, mean milliseconds; n_results HOST out.
+ *   max_timed  0: time every candidate; k > 0: only the cost model's k best
+ *          (fem_tune_predict) plus the entry configuration.
  * Errors: FEM_E_ARG, FEM_E_HIP, FEM_E_NOMEM.
  */
 int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vjp,
              const char *cache_path, void *stream, double *results, int max_results,
-             int *n_results);
+             int *n_results, int max_timed);
+
+/*
+ * The autotuner's cost model (paper Sec. 5, the heuristic performance model, adapted to
+ * gfx950): an analytic time for every candidate of fem_tune, from the plan's sizes and the
+ * compiled kernels' register counts, with no launch -- FP64 VALU time derated for low
+ * occupancy (registers, LDS), memory time of the footprint plus shared-node partials or
+ * colour scatters, and barrier / launch counts.  fem_tune with max_timed = k > 0 times only
+ * the model's k best candidates (and the plan's entry configuration).
+ *   results HOST f64 [max_results][6] out: as fem_tune's, the last column predicted ms.
+ * Errors: FEM_E_ARG.
+ */
+int fem_tune_predict(const fem_plan *plan, int vjp, double *results, int max_results,
+                     int *n_results);
 
 /*
  * Batched actions over many meshes (y_i = A_i(u_i) for every plan of the batch) in a few

@@ -87,8 +87,10 @@ def lib() -> ctypes.CDLL:
     L.fem_plan_set_strategy.restype = i32
     L.fem_plan_get_strategy.argtypes = [P, P, P, P, P]
     L.fem_plan_get_strategy.restype = i32
-    L.fem_tune.argtypes = [P, P, P, P, i32, ctypes.c_char_p, P, P, i32, P]
+    L.fem_tune.argtypes = [P, P, P, P, i32, ctypes.c_char_p, P, P, i32, P, i32]
     L.fem_tune.restype = i32
+    L.fem_tune_predict.argtypes = [P, i32, P, i32, P]
+    L.fem_tune_predict.restype = i32
     L.fem_check_patch_layout.argtypes = [i32, i32, i32, i64, P, i64, P, P, i64, i32, P]
     L.fem_check_patch_layout.restype = i32
     L.fem_batch_create.argtypes = [ctypes.POINTER(P), i32, P, P, P]
@@ -273,8 +275,10 @@ class Plan:
                                            ctypes.byref(ln), ctypes.byref(sm)))
         return st.value, pc.value, ln.value, sm.value
 
-    def tune(self, u, y=None, v=None, cache_path: str | None = None, stream=None):
-        """Time every launch configuration on (u[, v]) and keep the fastest.
+    def tune(self, u, y=None, v=None, cache_path: str | None = None, stream=None,
+             max_timed: int = 0):
+        """Time the launch configurations on (u[, v]) and keep the fastest (all of them, or
+        the cost model's `max_timed` best plus the current one).
 
         Returns a list of (strategy, cells_per_patch, lanes_per_cell, block, sum_mode, ms)."""
         import torch
@@ -287,7 +291,15 @@ class Plan:
                               _dev_ptr(v, self.n_dof, "v") if vjp else None,
                               _dev_ptr(y, self.n_dof, "y"), int(vjp),
                               cache_path.encode() if cache_path else None, _stream_handle(stream),
-                              _np_ptr(res), 64, ctypes.byref(nres)))
+                              _np_ptr(res), 64, ctypes.byref(nres), int(max_timed)))
+        return [tuple(r) for r in res[:nres.value]]
+
+    def tune_predict(self, vjp: bool = False):
+        """The cost model's predicted ms for every tuner candidate (no launch), as rows
+        (strategy, cells_per_patch, lanes_per_cell, block, sum_mode, predicted_ms)."""
+        res = np.zeros((64, 6))
+        nres = ctypes.c_int()
+        _check(lib().fem_tune_predict(self.handle, int(vjp), _np_ptr(res), 64, ctypes.byref(nres)))
         return [tuple(r) for r in res[:nres.value]]
 
     def colouring(self) -> np.ndarray:

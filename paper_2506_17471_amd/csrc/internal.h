@@ -178,6 +178,9 @@ constexpr bool scalar_form(int form)
 constexpr int ncomp_of(int form, int dim) { return scalar_form(form) ? 1 : dim; }
 bool pair_available(int form, int dim, int degree);
 bool triple_available(int form, int dim, int degree);
+int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int lanes,
+                     int sum_mode);
+int patch_threads(int P, int lanes);
 hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch, int sum_mode,
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
                               size_t lds, hipStream_t s);
@@ -189,7 +192,8 @@ void run_action(const fem_plan *p, const double *u, const double *v, double *y, 
 // tune.cpp
 void apply_tuning_cache(fem_plan *p);
 int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
-         hipStream_t s, double *results, int max_results, int *n_results);
+         hipStream_t s, double *results, int max_results, int *n_results, int max_timed);
+int tune_predict(const fem_plan *p, bool vjp, double *results, int max_results, int *n_results);
 hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off,
                         int64_t n_shared, const double *partial, int ncomp, double *y,
                         hipStream_t s);

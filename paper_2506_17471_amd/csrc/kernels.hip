@@ -126,6 +126,24 @@ bool triple_available(int form, int dim, int degree)
     return lookup(form, dim, degree, false).patch[3][SUM_ELEMENT] != nullptr;
 }
 
+// Registers per lane of the kernel a launch configuration runs (the compiled kernel's
+// attributes), 0 if that kernel is not built.
+int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int lanes,
+                     int sum_mode)
+{
+    const Kernels ks = lookup(form, dim, degree, vjp);
+    const void *fn = colour ? (const void *)ks.colour
+                            : (lanes >= 1 && lanes <= 3 && sum_mode >= 1 && sum_mode <= 2
+                                   ? (const void *)ks.patch[lanes][sum_mode] : nullptr);
+    if (!fn) return 0;
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, fn) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return attr.numRegs;
+}
+
 // threads of a patch workgroup: P * lanes, or 64 per 21 cells for lane triples
 int patch_threads(int P, int lanes)
 {

@@ -1065,15 +1065,25 @@ int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lan
 
 int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vjp,
              const char *cache_path, void *stream, double *results, int max_results,
-             int *n_results)
+             int *n_results, int max_timed)
 {
     return guarded([&] {
         check_plan(plan);
         if (plan->n_cell == 0) throw femx::Error(FEM_E_ARG, "nothing to tune on an empty mesh");
         if (!u || !y || (vjp && !v)) throw femx::Error(FEM_E_ARG, "null vector");
-        if (max_results < 0) throw femx::Error(FEM_E_ARG, "negative max_results");
+        if (max_results < 0 || max_timed < 0) throw femx::Error(FEM_E_ARG, "negative count");
         femx::tune(plan, u, v, y, vjp != 0, cache_path, (hipStream_t)stream, results, max_results,
-                   n_results);
+                   n_results, max_timed);
+    });
+}
+
+int fem_tune_predict(const fem_plan *plan, int vjp, double *results, int max_results,
+                     int *n_results)
+{
+    return guarded([&] {
+        check_plan(plan);
+        if (max_results < 0) throw femx::Error(FEM_E_ARG, "negative max_results");
+        femx::tune_predict(plan, vjp != 0, results, max_results, n_results);
     });
 }
 

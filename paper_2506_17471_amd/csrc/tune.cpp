@@ -12,6 +12,7 @@
 // environment variable FEM_TUNE_CACHE names the file.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -158,8 +159,7 @@ void apply_tuning_cache(fem_plan *p)
     }
 }
 
-int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
-         hipStream_t s, double *results, int max_results, int *n_results)
+std::vector<Candidate> candidates(const fem_plan *p)
 {
     std::vector<Candidate> cands;
     for (int blk : {64, 128, 256}) cands.push_back({FEM_SCATTER_COLOUR, 0, 1, blk, 0});
@@ -174,6 +174,91 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
         for (int P : {42, 63, 84})
             for (int m : {SUM_ELEMENT, SUM_COLOURED})
                 cands.push_back({FEM_SCATTER_PATCH, P, 3, 0, m});
+    return cands;
+}
+
+// FP64 work of one quadrature point of a cell (the plain loop, FMA = 2 flops)
+double flops_per_point(int form, int d, int nloc, bool vjp)
+{
+    const double n = nloc, dd = d;
+    if (form == FEM_MASS) return 4 * n + 2;
+    if (form == FEM_LAPLACE || form == FEM_HELMHOLTZ)
+        return 4 * dd * n + 2 * dd * dd + dd + 1 + (form == FEM_HELMHOLTZ ? 4 * n + 1 : 0);
+    const double ev = 2 * dd * dd * n * (vjp ? 2 : 1), ct = 2 * dd * dd * n;
+    const double geo = 2 * dd * dd * dd * (vjp ? 3 : 2) + dd * dd;
+    double pw = 3 * dd * dd + 2 * dd;                       // elasticity
+    if (form == FEM_NEOHOOKEAN) pw = d == 2 ? 40 : 110;     // inverse, log, stress
+    if (form == FEM_SVK) pw = 4 * dd * dd * dd + 4 * dd * dd;
+    if (vjp) pw += 4 * dd * dd * dd;
+    return ev + ct + geo + pw;
+}
+
+// Analytic time of one candidate (ms), from the plan's sizes and the compiled kernel's
+// registers -- no launch.  The terms, after the paper's cost model adapted to gfx950:
+//   VALU time: FP64 instructions (work / 2, plus what a lane split repeats) at 16 lanes
+//     per SIMD per cycle over 1024 SIMDs, derated when fewer than three waves per SIMD
+//     (set by registers and, for patches, by LDS) are there to hide latency;
+//   memory time: the footprint plus the partial sums of shared nodes (patches) or the
+//     uncoalesced read-add-write scatter (colours) at 4 TB/s;
+//   synchronisation: per workgroup round one barrier per sub-colour (coloured sums) or
+//     three (element buffer), and one launch per colour for the colour strategy.
+double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
+{
+    const bool nl = vjp && nonlinear_form(p->form);
+    const double n = (double)p->n_cell, d = p->dim, nloc = p->nloc, nc = p->ncomp;
+    const double nodes_per_cell = (double)p->n_node / std::max<int64_t>(1, p->n_cell);
+    double instr = flops_per_point(p->form, p->dim, p->nloc, nl) * p->nq / 2.0 * 1.25;
+    if (c.lanes == 2) instr *= 1.35;                      // pointwise form on both lanes
+    if (c.lanes == 3) instr *= 1.2;                       // shuffles of the gradient rows
+    const int regs = kernel_registers(p->form, p->dim, p->degree, nl,
+                                      c.strategy == FEM_SCATTER_COLOUR, c.lanes,
+                                      c.strategy == FEM_SCATTER_COLOUR ? 1 : c.sum_mode);
+    const double waves_regs = std::min(8, 512 / std::max(8, (regs + 7) / 8 * 8));
+    double waves = waves_regs, rounds_sync = 0.0, barriers = 0.0, extra_bytes = 0.0;
+    const double vec_bytes = 8.0 * p->n_node * nc;
+    if (c.strategy == FEM_SCATTER_PATCH) {
+        const double P = c.patch;
+        const double share = d == 2 ? 2.5 / std::sqrt(P) : 4.0 / std::cbrt(P);
+        const int U = (int)(P * nodes_per_cell * (1.0 + share)) + 8;
+        const size_t lds = patch_lds_bytes(p->form, p->dim, p->degree, nl, c.patch, U, c.sum_mode);
+        const double wgs_lds = std::floor(160.0 * 1024 / std::max<size_t>(1, lds));
+        const double wave_per_wg = std::ceil(patch_threads(c.patch, c.lanes) / 64.0);
+        waves = std::min(waves, wgs_lds * wave_per_wg / 4.0);
+        const double wg_per_cu = std::max(1.0, waves * 4.0 / wave_per_wg);
+        rounds_sync = std::ceil(n / P / (256.0 * wg_per_cu));
+        barriers = c.sum_mode == SUM_COLOURED ? (d == 2 ? 7 : 24) + 3 : 3;
+        extra_bytes = 2.0 * share * vec_bytes * (vjp ? 1.0 : 1.0) * 2.0;
+    } else {
+        extra_bytes = 2.0 * n * nloc * nc * 8.0;          // gathers and read-add-writes
+    }
+    const double eta = std::min(1.0, std::max(waves, 0.25) / 3.0);
+    const double t_valu = n * instr * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
+    const double bytes = vec_bytes * (nl ? 3 : 2) + 8.0 * d * p->n_vert +
+                         4.0 * (nloc + d + 1) * n + extra_bytes;
+    const double t_mem = bytes / 4.0e12;
+    double t = std::max(t_valu, t_mem) + rounds_sync * barriers * 0.4e-6;
+    if (c.strategy == FEM_SCATTER_COLOUR) t += p->n_colours * 4.0e-6;
+    else t += 4.0e-6;                                     // the fixup launch
+    return t * 1e3;
+}
+
+int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
+         hipStream_t s, double *results, int max_results, int *n_results, int max_timed)
+{
+    std::vector<Candidate> cands = candidates(p);
+    if (max_timed > 0 && max_timed < (int)cands.size()) {
+        // prune to the model's best max_timed candidates (the entry configuration is kept
+        // below regardless), keeping their original order so layout builds are shared
+        std::vector<std::pair<double, int>> pred;
+        for (int i = 0; i < (int)cands.size(); ++i) pred.push_back({predict_ms(p, cands[i], vjp), i});
+        std::sort(pred.begin(), pred.end());
+        std::vector<int> keep;
+        for (int i = 0; i < max_timed; ++i) keep.push_back(pred[i].second);
+        std::sort(keep.begin(), keep.end());
+        std::vector<Candidate> kept;
+        for (int i : keep) kept.push_back(cands[i]);
+        cands = kept;
+    }
     // the configuration the plan had on entry competes too, and keeps its place unless a
     // candidate beats it by more than kMargin (timing noise must not flip configurations)
     constexpr double kMargin = 0.03;
@@ -185,6 +270,8 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
         return a.strategy == b.strategy && a.patch == b.patch && a.lanes == b.lanes &&
                a.sum_mode == b.sum_mode && (a.strategy == FEM_SCATTER_PATCH || a.block == b.block);
     };
+    if (std::none_of(cands.begin(), cands.end(), [&](const Candidate &c) { return same(c, entry); }))
+        cands.push_back(entry);
     double best = 1e300, entry_ms = 1e300;
     Candidate best_c = cands[0];
     int nres = 0;
@@ -225,6 +312,26 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
                            (double)best_c.block, (double)best_c.sum_mode, best};
         write_cache(cache, c);
     }
+    return FEM_OK;
+}
+
+int tune_predict(const fem_plan *p, bool vjp, double *results, int max_results, int *n_results)
+{
+    const std::vector<Candidate> cands = candidates(p);
+    int nres = 0;
+    for (const Candidate &c : cands) {
+        if (results && nres < max_results) {
+            double *r = results + 6 * nres;
+            r[0] = c.strategy;
+            r[1] = c.patch;
+            r[2] = c.lanes;
+            r[3] = c.block;
+            r[4] = c.sum_mode;
+            r[5] = predict_ms(p, c, vjp);
+        }
+        ++nres;
+    }
+    if (n_results) *n_results = nres;
     return FEM_OK;
 }
 

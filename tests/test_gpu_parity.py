@@ -367,6 +367,24 @@ def test_tuner_picks_a_candidate_and_keeps_parity(tmp_path):
     assert cache.exists() and "f2/d2/k4/q8" in cache.read_text()
 
 
+def test_cost_model_prunes_and_keeps_parity():
+    w = meshgen.workload("nh_p4_2d", n=32)
+    say("[tune-pruned] nh_p4_2d n=32")
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    pred = plan.tune_predict()
+    assert len(pred) >= 6 and all(np.isfinite(r[5]) and r[5] > 0 for r in pred)
+    # colour launches (one per colour, scattered read-add-writes) never beat patches here
+    best_colour = min(r[5] for r in pred if r[0] == fx.SCATTER_COLOUR)
+    best_patch = min(r[5] for r in pred if r[0] == fx.SCATTER_PATCH)
+    assert best_patch < best_colour
+    u = gpu(w.u)
+    res = plan.tune(u, max_timed=3)
+    assert 1 <= len(res) <= 4          # the model's three, plus the entry configuration
+    y = plan.action(u).cpu().numpy()
+    ref = oracle.action(w.form, w.mesh, w.u, w.quad_degree, w.params, family=plan.quad_family_name)
+    assert rel_err(y, ref)[0] < TOL
+
+
 def _batch_meshes(n_mesh=9, seed=11):
     """An uneven mix of the three batch forms at sizes the oracle handles quickly."""
     return meshgen.batch_workloads(n_mesh=n_mesh, seed=seed, lo=20, hi=600)
