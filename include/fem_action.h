@@ -109,6 +109,29 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
                     const int32_t *cell_verts, const int32_t *cell_nodes, int64_t n_node,
                     const double *params, int n_params);
 
+/*
+ * A plan on curved (non-affine) cells: every cell carries the 6 (triangle) or 10
+ * (tetrahedron) nodes of a P2 geometry, and the map x(xi) = sum_g x_g phiG_g(xi) is
+ * differentiated at every quadrature point, so J, J^{-1} and |det J| are evaluated per
+ * point instead of once per cell (paper Sec. 2.4, non-affine geometry: the coordinates are
+ * handled like a vector trial function).
+ *   n_gnode      number of geometry nodes;  gcoords HOST f64 [n_gnode][dim]
+ *   cell_gnodes  HOST i32 [n_cell][6 or 10]: the cell's geometry nodes in the P2 local
+ *                order (reference lattice points alpha/2, first coordinate fastest, as for
+ *                cell_nodes), so local nodes 0, 2, 5 (2D) or 0, 2, 5, 9 (3D) are the
+ *                vertices
+ *   other arguments as fem_plan_create (the solution degree is independent of the
+ *   geometry degree: isoparametric for degree 2, sub- or super-parametric otherwise).
+ * det J is checked at every point of the rule (FEM_E_INVERTED where it is zero, not
+ * finite, changes sign within a cell, or is negative in 2D); between the points the map is
+ * not checked.  Curved plans run one lane per cell (FEM_E_UNSUPPORTED for lane splits) and
+ * cannot join a batch.  Errors as fem_plan_create.
+ */
+int fem_plan_create_curved(fem_plan **out, int form, int dim, int degree, int quad_degree,
+                           int64_t n_gnode, const double *gcoords, int64_t n_cell,
+                           const int32_t *cell_gnodes, const int32_t *cell_nodes, int64_t n_node,
+                           const double *params, int n_params);
+
 /* Release a plan and its device memory (NULL is a no-op).  Synchronises the device
  * before freeing so that no enqueued launch still reads the plan's arrays. */
 void fem_plan_destroy(fem_plan *plan);

@@ -39,7 +39,7 @@ import numpy as np
 
 __all__ = [
     "Mesh", "local_lattice", "unit_square", "unit_cube", "make_mesh", "n_local",
-    "Workload", "workload", "batch_workloads", "nh_displacement",
+    "Workload", "workload", "batch_workloads", "nh_displacement", "curved",
 ]
 
 
@@ -75,6 +75,9 @@ class Mesh:
     cell_nodes: np.ndarray      # int32 [n_cell, C(k+d,d)]
     n_node: int
     h: float = field(default=0.0)
+    # curved meshes only (see ``curved``): P2 geometry nodes and each cell's 6 / 10 of them
+    gcoords: np.ndarray | None = None       # float64 [n_gnode, dim]
+    cell_gnodes: np.ndarray | None = None   # int32 [n_cell, C(2+d,d)], local P2 lattice order
 
     @property
     def n_cell(self) -> int:
@@ -170,6 +173,50 @@ def make_mesh(dim: int, n: int, k: int, jitter: float | None = None, rng=None) -
     raise ValueError("dim must be 2 or 3")
 
 
+def _warp(x: np.ndarray) -> np.ndarray:
+    """Smooth displacement field vanishing on the boundary of the unit square / cube:
+    prod_j sin(pi x_j) times (cos pi x_1, cos pi x_0) in 2D, (cos pi x_1, cos pi x_2,
+    cos pi x_0) in 3D."""
+    d = x.shape[1]
+    s = np.prod(np.sin(np.pi * x), axis=1)
+    return s[:, None] * np.cos(np.pi * x[:, [(i + 1) % d for i in range(d)]])
+
+
+def curved(mesh: Mesh, amp: float = 0.05) -> Mesh:
+    """The same mesh with curved (non-affine) cells: a P2 geometry per cell.
+
+    Geometry nodes: the P2 lattice of the mesh, numbered like P2 solution nodes
+    (L = 2 v_0 + sum_r alpha_r (v_r - v_0) on the (2n+1)^d lattice), each placed at the
+    barycentric point (alpha_0, alpha_1, ..)/2 of its cell's (jittered) vertices and then
+    moved by ``amp * _warp(x)``.  Nodes on the boundary do not move, so the domain stays the
+    unit square / cube and every boundary edge straight; inside, each cell is the P2
+    interpolant of a smooth nonlinear map.  ``amp = 0`` gives straight P2 geometry, which
+    describes the affine cells exactly.  The solution nodes (``cell_nodes``) are unchanged.
+    """
+    d, n = mesh.dim, mesh.n
+    nv1, nn1 = n + 1, 2 * n + 1
+    vid = mesh.cell_verts.astype(np.int64)
+    if d == 2:
+        vl = np.stack([vid % nv1, vid // nv1], axis=-1)
+    else:
+        vl = np.stack([vid % nv1, (vid // nv1) % nv1, vid // (nv1 * nv1)], axis=-1)
+    alpha = local_lattice(d, 2)                                  # [ng, d]
+    e = vl[:, 1:, :] - vl[:, :1, :]
+    L = 2 * vl[:, None, 0, :] + np.einsum("ar,crx->cax", alpha, e)
+    gid = L[..., 0] + nn1 * L[..., 1] + (nn1 * nn1 * L[..., 2] if d == 3 else 0)
+    bary = np.concatenate([2 - alpha.sum(axis=1, keepdims=True), alpha], axis=1) / 2.0
+    X = mesh.coords[mesh.cell_verts]                             # [cell, d+1, d]
+    pts = np.einsum("gv,cvx->cgx", bary, X)
+    gcoords = np.zeros((nn1 ** d, d))
+    gcoords[gid.reshape(-1)] = pts.reshape(-1, d)
+    lat = np.zeros((nn1 ** d, d), dtype=np.int64)
+    lat[gid.reshape(-1)] = L.reshape(-1, d)
+    interior = np.all((lat > 0) & (lat < 2 * n), axis=1)
+    gcoords[interior] += amp * _warp(gcoords[interior])
+    return Mesh(d, n, mesh.k, mesh.coords, mesh.cell_verts, mesh.cell_nodes, mesh.n_node,
+                mesh.h, gcoords, gid.astype(np.int32))
+
+
 def nh_displacement(rng, mesh: Mesh, amplitude: float = 0.01) -> np.ndarray:
     """Displacement for the hyperelastic forms: amplitude * (h/k) * U[-1,1] per DoF.
 
@@ -225,7 +272,12 @@ _SPECS = {
     # St Venant-Kirchhoff residual and tangent on the same mesh and rule degree (the
     # paper's hyperelastic law; its benchmark times the tangent action)
     "svk_p4_2d": (FORM_SVK, 2, 512, 4, 8, 0.1, 5, (10.0, 1.0)),
+    # curved (P2-geometry) cells: the neo-Hookean P4 residual and the P2 mass action on
+    # the meshes above with every cell bent by ``curved(mesh, 0.05)``
+    "nh_p4_2d_curved": (FORM_NH, 2, 512, 4, 8, 0.1, 1, (10.0, 1.0)),
+    "mass_p2_2d_1024_curved": (FORM_MASS, 2, 1024, 2, 4, 0.1, 0, ()),
 }
+_CURVED_AMP = {"nh_p4_2d_curved": 0.05, "mass_p2_2d_1024_curved": 0.05}
 
 
 def workload(name: str, n: int | None = None, seed: int | None = None,
@@ -235,6 +287,8 @@ def workload(name: str, n: int | None = None, seed: int | None = None,
     n = n0 if n is None else n
     rng = np.random.default_rng(seed0 if seed is None else seed)
     mesh = make_mesh(dim, n, k, jit, rng)
+    if name in _CURVED_AMP:
+        mesh = curved(mesh, _CURVED_AMP[name])
     ncomp = 1 if form in (FORM_MASS, FORM_LAPLACE, FORM_HELMHOLTZ) else dim
     if form in (FORM_NH, FORM_SVK):
         u = nh_displacement(rng, mesh)

@@ -40,8 +40,12 @@ SCALAR_FORMS = (FORM_MASS, FORM_LAPLACE, FORM_HELMHOLTZ)
 
 def build() -> str:
     """Compile the C oracle with gcc (plain -O2, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", _LIB, _SRC, "-lm"]
+    # build beside the target and rename, so that concurrent test workers never load a
+    # half-written library
+    tmp = f"{_LIB}.{os.getpid()}.tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
     return _LIB
 
 
@@ -77,13 +81,15 @@ class using_library:
 def _bind(lib):
     P = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_double
-    lib.oracle_action.argtypes = [i32, i32, i32, i32, P, P, P, i64, P, P, P, f64, f64, P, P, i64]
+    lib.oracle_action.argtypes = [i32, i32, i32, i32, P, P, P, i32, P, i64, P, P, P, f64, f64, P,
+                                  P, i64]
     lib.oracle_action.restype = None
-    lib.oracle_vjp.argtypes = [i32, i32, i32, i32, P, P, P, i64, P, P, P, f64, f64, P, P, P, i64]
+    lib.oracle_vjp.argtypes = [i32, i32, i32, i32, P, P, P, i32, P, i64, P, P, P, f64, f64, P, P,
+                               P, i64]
     lib.oracle_vjp.restype = None
-    lib.oracle_energy.argtypes = [i32, i32, i32, i32, P, P, i64, P, P, P, f64, f64, P]
+    lib.oracle_energy.argtypes = [i32, i32, i32, i32, P, P, i32, P, i64, P, P, P, f64, f64, P]
     lib.oracle_energy.restype = f64
-    lib.oracle_min_det_f.argtypes = [i32, i32, i32, P, i64, P, P, P, P]
+    lib.oracle_min_det_f.argtypes = [i32, i32, i32, P, i32, P, i64, P, P, P, P]
     lib.oracle_min_det_f.restype = f64
     lib.oracle_colouring.argtypes = [i64, i32, P, i32, P, P]
     lib.oracle_colouring.restype = i32
@@ -111,6 +117,15 @@ class Tables:
         self.weights = np.ascontiguousarray(self.weights, dtype=np.float64)
         self.nq = len(self.weights)
         self.nloc = self.phi.shape[1]
+        self._geometry = {}
+
+    def geometry(self, degree: int) -> np.ndarray:
+        """Reference gradients [nq, ng, dim] of the degree-1 (vertices) or degree-2 (curved
+        cells) geometry basis at the rule's points: the cell map is x(xi) = sum_g x_g phiG_g."""
+        if degree not in self._geometry:
+            _, g = basis.tabulate(self.dim, degree, self.points)
+            self._geometry[degree] = np.ascontiguousarray(g, dtype=np.float64)
+        return self._geometry[degree]
 
 
 _tables_cache: dict = {}
@@ -123,11 +138,16 @@ def tables(dim: int, k: int, quad_degree: int, family: str = "conical") -> Table
     return _tables_cache[key]
 
 
-def _mesh_arrays(mesh):
-    cv = np.ascontiguousarray(mesh.cell_verts, dtype=np.int32)
+def _mesh_arrays(mesh, t: Tables):
+    """(cell geometry nodes, cell nodes, geometry coordinates, ng, geometry gradients): the
+    vertices and P1 geometry, or a curved mesh's P2 geometry nodes (``mesh.cell_gnodes``)."""
+    curved = getattr(mesh, "cell_gnodes", None) is not None
+    cv = np.ascontiguousarray(mesh.cell_gnodes if curved else mesh.cell_verts, dtype=np.int32)
     cn = np.ascontiguousarray(mesh.cell_nodes, dtype=np.int32)
-    xy = np.ascontiguousarray(mesh.coords, dtype=np.float64)
-    return cv, cn, xy
+    xy = np.ascontiguousarray(mesh.gcoords if curved else mesh.coords, dtype=np.float64)
+    g = t.geometry(2 if curved else 1)
+    assert g.shape[1] == cv.shape[1]
+    return cv, cn, xy, g.shape[1], g
 
 
 def _lam_mu(params):
@@ -141,7 +161,7 @@ def action(form: int, mesh, u: np.ndarray, quad_degree: int, params=(),
     """y = A(u) by the plain per-cell loop."""
     lib = _load()
     t = tables(mesh.dim, mesh.k, quad_degree, family)
-    cv, cn, xy = _mesh_arrays(mesh)
+    cv, cn, xy, ng, g = _mesh_arrays(mesh, t)
     ncomp = 1 if form in SCALAR_FORMS else mesh.dim
     n_dof = mesh.n_node * ncomp
     u = np.ascontiguousarray(u, dtype=np.float64)
@@ -149,7 +169,8 @@ def action(form: int, mesh, u: np.ndarray, quad_degree: int, params=(),
     y = np.empty(n_dof)
     lam, mu = _lam_mu(params)
     lib.oracle_action(form, mesh.dim, t.nloc, t.nq, _ptr(t.phi), _ptr(t.dphi), _ptr(t.weights),
-                      cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u), _ptr(y), n_dof)
+                      ng, _ptr(g), cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u),
+                      _ptr(y), n_dof)
     return y
 
 
@@ -158,7 +179,7 @@ def vjp(form: int, mesh, u: np.ndarray, v: np.ndarray, quad_degree: int, params=
     """g = (dA/du)^T v."""
     lib = _load()
     t = tables(mesh.dim, mesh.k, quad_degree, family)
-    cv, cn, xy = _mesh_arrays(mesh)
+    cv, cn, xy, ng, gd = _mesh_arrays(mesh, t)
     ncomp = 1 if form in SCALAR_FORMS else mesh.dim
     n_dof = mesh.n_node * ncomp
     u = np.ascontiguousarray(u, dtype=np.float64)
@@ -167,8 +188,8 @@ def vjp(form: int, mesh, u: np.ndarray, v: np.ndarray, quad_degree: int, params=
     g = np.empty(n_dof)
     lam, mu = _lam_mu(params)
     lib.oracle_vjp(form, mesh.dim, t.nloc, t.nq, _ptr(t.phi), _ptr(t.dphi), _ptr(t.weights),
-                   cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u), _ptr(v), _ptr(g),
-                   n_dof)
+                   ng, _ptr(gd), cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u),
+                   _ptr(v), _ptr(g), n_dof)
     return g
 
 
@@ -177,11 +198,11 @@ def energy(form: int, mesh, u: np.ndarray, quad_degree: int, params,
     """Discrete energy Pi_h(u) of a hyperelastic form (neo-Hookean or St Venant-Kirchhoff)."""
     lib = _load()
     t = tables(mesh.dim, mesh.k, quad_degree, family)
-    cv, cn, xy = _mesh_arrays(mesh)
+    cv, cn, xy, ng, g = _mesh_arrays(mesh, t)
     u = np.ascontiguousarray(u, dtype=np.float64)
     lam, mu = _lam_mu(params)
-    return lib.oracle_energy(form, mesh.dim, t.nloc, t.nq, _ptr(t.dphi), _ptr(t.weights),
-                             cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u))
+    return lib.oracle_energy(form, mesh.dim, t.nloc, t.nq, _ptr(t.dphi), _ptr(t.weights), ng,
+                             _ptr(g), cv.shape[0], _ptr(cv), _ptr(xy), _ptr(cn), lam, mu, _ptr(u))
 
 
 def nh_energy(mesh, u: np.ndarray, quad_degree: int, params, family: str = "conical") -> float:
@@ -192,10 +213,10 @@ def nh_energy(mesh, u: np.ndarray, quad_degree: int, params, family: str = "coni
 def min_det_f(mesh, u: np.ndarray, quad_degree: int, family: str = "conical") -> float:
     lib = _load()
     t = tables(mesh.dim, mesh.k, quad_degree, family)
-    cv, cn, xy = _mesh_arrays(mesh)
+    cv, cn, xy, ng, g = _mesh_arrays(mesh, t)
     u = np.ascontiguousarray(u, dtype=np.float64)
-    return lib.oracle_min_det_f(mesh.dim, t.nloc, t.nq, _ptr(t.dphi), cv.shape[0], _ptr(cv),
-                                _ptr(xy), _ptr(cn), _ptr(u))
+    return lib.oracle_min_det_f(mesh.dim, t.nloc, t.nq, _ptr(t.dphi), ng, _ptr(g), cv.shape[0],
+                                _ptr(cv), _ptr(xy), _ptr(cn), _ptr(u))
 
 
 def colouring(cell_nodes: np.ndarray, n_node: int, nwords: int = 2) -> tuple[np.ndarray, int]:

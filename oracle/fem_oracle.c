@@ -6,9 +6,11 @@
  *
  * Structure: the generic action kernel of the paper (Sec. 2.3, the generic action
  * algorithm): for every cell, in index order,
- *   gather the vertex coordinates and the cell's DoFs through the maps,
- *   Jacobian J = [x_1 - x_0 | ... | x_d - x_0] and its determinant,
+ *   gather the geometry nodes' coordinates and the cell's DoFs through the maps,
  *   for every quadrature point:
+ *     Jacobian of the cell map x(xi) = sum_g x_g phiG_g(xi) at the point and its
+ *     determinant (affine cells: phiG = P1 on the vertices, J = [x_1 - x_0 | ... | x_d - x_0]
+ *     at every point; curved cells: P2 geometry, J varies over the cell, Sec. 2.4),
  *     evaluation: reference derivatives of u at the point from the tabulation,
  *     apply the form's pointwise map and the geometry (J^{-1}, |det J|, weight),
  *     quadrature: accumulate against the test-function tabulation,
@@ -25,9 +27,10 @@
  *     S = lam tr(E) I + 2 mu E, P = F S (energy Psi = lam/2 tr(E)^2 + mu E:E);
  *   4 Laplace  a = int grad u . grad v;   5 Helmholtz  a = int grad u . grad v + u v.
  *
- * Layouts: coords [n_vert][d]; cell_verts [n_cell][d+1]; cell_nodes [n_cell][nloc];
+ * Layouts: coords [n_vert][d] (geometry nodes); cell_verts [n_cell][ng] (each cell's ng
+ * geometry nodes: d+1 vertices, or the P2 lattice); cell_nodes [n_cell][nloc];
  * vectors node-major interleaved, value (node, c) at node*ncomp + c;
- * phi [nq][nloc]; dphi [nq][nloc][d]; w [nq].
+ * phi [nq][nloc]; dphi [nq][nloc][d]; w [nq]; gdphi [nq][ng][d] (geometry basis).
  */
 #include <math.h>
 #include <stdint.h>
@@ -37,38 +40,8 @@ enum { OR_MASS = 0, OR_ELAST = 1, OR_NH = 2, OR_SVK = 3, OR_LAPLACE = 4, OR_HELM
 
 /* largest local node count handled (P8 triangle: 45, P6 tetrahedron: 84) */
 #define ORACLE_MAX_NLOC 128
-
-/* J[i][r] = x_{r+1,i} - x_{0,i}; returns det J and writes K = J^{-1} (K[r][i]). */
-static double geometry(int d, const double x[4][3], double J[3][3], double K[3][3])
-{
-    for (int i = 0; i < d; ++i)
-        for (int r = 0; r < d; ++r)
-            J[i][r] = x[r + 1][i] - x[0][i];
-    double det;
-    if (d == 2) {
-        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        K[0][0] = J[1][1] / det;
-        K[0][1] = -J[0][1] / det;
-        K[1][0] = -J[1][0] / det;
-        K[1][1] = J[0][0] / det;
-    } else {
-        double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-        /* inverse = adjugate / det, adj[r][i] = cofactor[i][r] */
-        K[0][0] = c00 / det;
-        K[1][0] = c01 / det;
-        K[2][0] = c02 / det;
-        K[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-        K[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-        K[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-        K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-        K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-        K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-    }
-    return det;
-}
+/* largest geometry node count (P2 tetrahedron) */
+#define ORACLE_MAX_GEOM 10
 
 /* determinant and inverse of a d x d matrix (d = 2, 3) */
 static double inverse(int d, const double A[3][3], double B[3][3])
@@ -95,6 +68,21 @@ static double inverse(int d, const double A[3][3], double B[3][3])
         B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
     }
     return det;
+}
+
+/* The cell map's Jacobian at one point, J[i][r] = sum_g x_g,i d phiG_g / d xi_r, from the
+ * geometry basis' reference gradients there (gdq [ng][d]); returns det J and writes
+ * K = J^{-1} (K[r][i]). */
+static double geometry(int d, int ng, const double x[][3], const double *gdq, double J[3][3],
+                       double K[3][3])
+{
+    for (int i = 0; i < d; ++i)
+        for (int r = 0; r < d; ++r) {
+            J[i][r] = 0.0;
+            for (int g = 0; g < ng; ++g)
+                J[i][r] += x[g][i] * gdq[g * d + r];
+        }
+    return inverse(d, J, K);
 }
 
 /* physical gradient G[c][j] = sum_a u[a][c] dphi_j(a), with dphi_j = sum_r K[r][j] dref_r */
@@ -197,13 +185,13 @@ static double energy_density(int form, int d, double lam, double mu, const doubl
     return 0.5 * mu * (trC - d) - mu * lnJ + 0.5 * lam * lnJ * lnJ;
 }
 
-static void gather_cell(int d, int nloc, int ncomp, int64_t cell, const int32_t *cell_verts,
-                        const double *coords, const int32_t *cell_nodes, const double *vec,
-                        double x[4][3], double *loc)
+static void gather_cell(int d, int ng, int nloc, int ncomp, int64_t cell,
+                        const int32_t *cell_verts, const double *coords,
+                        const int32_t *cell_nodes, const double *vec, double x[][3], double *loc)
 {
-    for (int j = 0; j <= d; ++j)
+    for (int j = 0; j < ng; ++j)
         for (int i = 0; i < d; ++i)
-            x[j][i] = coords[(int64_t)cell_verts[cell * (d + 1) + j] * d + i];
+            x[j][i] = coords[(int64_t)cell_verts[cell * ng + j] * d + i];
     for (int a = 0; a < nloc; ++a)
         for (int c = 0; c < ncomp; ++c)
             loc[a * ncomp + c] = vec[(int64_t)cell_nodes[cell * nloc + a] * ncomp + c];
@@ -211,21 +199,21 @@ static void gather_cell(int d, int nloc, int ncomp, int64_t cell, const int32_t 
 
 /* y = A(u), overwriting y [n_dof]. */
 void oracle_action(int form, int d, int nloc, int nq, const double *phi, const double *dphi,
-                   const double *w, int64_t n_cell, const int32_t *cell_verts,
-                   const double *coords, const int32_t *cell_nodes, double lam, double mu,
-                   const double *u, double *y, int64_t n_dof)
+                   const double *w, int ng, const double *gdphi, int64_t n_cell,
+                   const int32_t *cell_verts, const double *coords, const int32_t *cell_nodes,
+                   double lam, double mu, const double *u, double *y, int64_t n_dof)
 {
     const int scalar = form == OR_MASS || form == OR_LAPLACE || form == OR_HELMHOLTZ;
     const int ncomp = scalar ? 1 : d;
     double uloc[ORACLE_MAX_NLOC * 3], out[ORACLE_MAX_NLOC * 3];
     memset(y, 0, sizeof(double) * (size_t)n_dof);
     for (int64_t cell = 0; cell < n_cell; ++cell) {
-        double x[4][3], J[3][3], K[3][3];
-        gather_cell(d, nloc, ncomp, cell, cell_verts, coords, cell_nodes, u, x, uloc);
-        double detJ = fabs(geometry(d, x, J, K));
+        double x[ORACLE_MAX_GEOM][3], J[3][3], K[3][3];
+        gather_cell(d, ng, nloc, ncomp, cell, cell_verts, coords, cell_nodes, u, x, uloc);
         for (int i = 0; i < nloc * ncomp; ++i)
             out[i] = 0.0;
         for (int q = 0; q < nq; ++q) {
+            double detJ = fabs(geometry(d, ng, x, gdphi + (int64_t)q * ng * d, J, K));
             const double W = w[q] * detJ;
             if (form == OR_MASS || form == OR_HELMHOLTZ) {
                 double uq = 0.0;
@@ -285,25 +273,26 @@ void oracle_action(int form, int d, int nloc, int nq, const double *phi, const d
  * For the linear forms (mass, elasticity) A is symmetric and linear: g = A v.
  */
 void oracle_vjp(int form, int d, int nloc, int nq, const double *phi, const double *dphi,
-                const double *w, int64_t n_cell, const int32_t *cell_verts,
-                const double *coords, const int32_t *cell_nodes, double lam, double mu,
-                const double *u, const double *v, double *g, int64_t n_dof)
+                const double *w, int ng, const double *gdphi, int64_t n_cell,
+                const int32_t *cell_verts, const double *coords, const int32_t *cell_nodes,
+                double lam, double mu, const double *u, const double *v, double *g,
+                int64_t n_dof)
 {
     if (form != OR_NH && form != OR_SVK) {
-        oracle_action(form, d, nloc, nq, phi, dphi, w, n_cell, cell_verts, coords,
+        oracle_action(form, d, nloc, nq, phi, dphi, w, ng, gdphi, n_cell, cell_verts, coords,
                       cell_nodes, lam, mu, v, g, n_dof);
         return;
     }
     double uloc[ORACLE_MAX_NLOC * 3], vloc[ORACLE_MAX_NLOC * 3], out[ORACLE_MAX_NLOC * 3];
     memset(g, 0, sizeof(double) * (size_t)n_dof);
     for (int64_t cell = 0; cell < n_cell; ++cell) {
-        double x[4][3], J[3][3], K[3][3];
-        gather_cell(d, nloc, d, cell, cell_verts, coords, cell_nodes, u, x, uloc);
-        gather_cell(d, nloc, d, cell, cell_verts, coords, cell_nodes, v, x, vloc);
-        double detJ = fabs(geometry(d, x, J, K));
+        double x[ORACLE_MAX_GEOM][3], J[3][3], K[3][3];
+        gather_cell(d, ng, nloc, d, cell, cell_verts, coords, cell_nodes, u, x, uloc);
+        gather_cell(d, ng, nloc, d, cell, cell_verts, coords, cell_nodes, v, x, vloc);
         for (int i = 0; i < nloc * d; ++i)
             out[i] = 0.0;
         for (int q = 0; q < nq; ++q) {
+            double detJ = fabs(geometry(d, ng, x, gdphi + (int64_t)q * ng * d, J, K));
             const double W = w[q] * detJ;
             const double *dq = dphi + (int64_t)q * nloc * d;
             double G[3][3], H[3][3], F[3][3], Fi[3][3], D[3][3], E[3][3];
@@ -369,15 +358,16 @@ void oracle_vjp(int form, int d, int nloc, int nq, const double *phi, const doub
 
 /* discrete energy of a hyperelastic form  Pi_h(u) = sum_T sum_q w_q |det J| Psi(F_q) */
 double oracle_energy(int form, int d, int nloc, int nq, const double *dphi, const double *w,
-                        int64_t n_cell, const int32_t *cell_verts, const double *coords,
-                        const int32_t *cell_nodes, double lam, double mu, const double *u)
+                     int ng, const double *gdphi, int64_t n_cell, const int32_t *cell_verts,
+                     const double *coords, const int32_t *cell_nodes, double lam, double mu,
+                     const double *u)
 {
     double uloc[ORACLE_MAX_NLOC * 3], total = 0.0;
     for (int64_t cell = 0; cell < n_cell; ++cell) {
-        double x[4][3], J[3][3], K[3][3];
-        gather_cell(d, nloc, d, cell, cell_verts, coords, cell_nodes, u, x, uloc);
-        double detJ = fabs(geometry(d, x, J, K));
+        double x[ORACLE_MAX_GEOM][3], J[3][3], K[3][3];
+        gather_cell(d, ng, nloc, d, cell, cell_verts, coords, cell_nodes, u, x, uloc);
         for (int q = 0; q < nq; ++q) {
+            double detJ = fabs(geometry(d, ng, x, gdphi + (int64_t)q * ng * d, J, K));
             double G[3][3];
             physical_gradient(d, nloc, dphi + (int64_t)q * nloc * d, K, uloc, G);
             total += w[q] * detJ * energy_density(form, d, lam, mu, G);
@@ -387,16 +377,16 @@ double oracle_energy(int form, int d, int nloc, int nq, const double *dphi, cons
 }
 
 /* minimum over cells and quadrature points of det F (neo-Hookean admissibility) */
-double oracle_min_det_f(int d, int nloc, int nq, const double *dphi, int64_t n_cell,
-                        const int32_t *cell_verts, const double *coords,
-                        const int32_t *cell_nodes, const double *u)
+double oracle_min_det_f(int d, int nloc, int nq, const double *dphi, int ng,
+                        const double *gdphi, int64_t n_cell, const int32_t *cell_verts,
+                        const double *coords, const int32_t *cell_nodes, const double *u)
 {
     double uloc[ORACLE_MAX_NLOC * 3], mn = INFINITY;
     for (int64_t cell = 0; cell < n_cell; ++cell) {
-        double x[4][3], J[3][3], K[3][3], G[3][3], F[3][3], Fi[3][3];
-        gather_cell(d, nloc, d, cell, cell_verts, coords, cell_nodes, u, x, uloc);
-        geometry(d, x, J, K);
+        double x[ORACLE_MAX_GEOM][3], J[3][3], K[3][3], G[3][3], F[3][3], Fi[3][3];
+        gather_cell(d, ng, nloc, d, cell, cell_verts, coords, cell_nodes, u, x, uloc);
         for (int q = 0; q < nq; ++q) {
+            geometry(d, ng, x, gdphi + (int64_t)q * ng * d, J, K);
             physical_gradient(d, nloc, dphi + (int64_t)q * nloc * d, K, uloc, G);
             for (int i = 0; i < d; ++i)
                 for (int j = 0; j < d; ++j)

@@ -57,6 +57,8 @@ def lib() -> ctypes.CDLL:
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     L.fem_plan_create.argtypes = [ctypes.POINTER(P), i32, i32, i32, i32, i64, P, i64, P, P, i64, P, i32]
     L.fem_plan_create.restype = i32
+    L.fem_plan_create_curved.argtypes = L.fem_plan_create.argtypes
+    L.fem_plan_create_curved.restype = i32
     L.fem_plan_destroy.argtypes = [P]
     L.fem_plan_destroy.restype = None
     L.fem_action.argtypes = [P, P, P, P]
@@ -185,7 +187,10 @@ class Plan:
     """A mesh + form + quadrature, validated, coloured and resident on the current device."""
 
     def __init__(self, form: int, dim: int, degree: int, quad_degree: int, coords, cell_verts,
-                 cell_nodes, n_node: int, params=()):
+                 cell_nodes, n_node: int, params=(), geometry: int = 1):
+        """geometry=1: ``cell_verts`` [n_cell, dim+1] vertices of affine cells (fem_plan_create);
+        geometry=2: curved cells, ``coords`` the geometry nodes and ``cell_verts`` each cell's
+        [n_cell, 6 or 10] P2 geometry nodes in the local lattice order (fem_plan_create_curved)."""
         L = lib()
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         cell_verts = np.ascontiguousarray(cell_verts, dtype=np.int32)
@@ -193,19 +198,24 @@ class Plan:
         prm = np.ascontiguousarray(params, dtype=np.float64)
         if coords.ndim != 2 or coords.shape[1] != dim:
             raise ValueError("coords must be [n_vert, dim]")
-        if cell_verts.ndim != 2 or cell_verts.shape[1] != dim + 1:
-            raise ValueError("cell_verts must be [n_cell, dim+1]")
+        if geometry not in (1, 2):
+            raise ValueError("geometry must be 1 (affine) or 2 (P2 curved cells)")
+        nv = dim + 1 if geometry == 1 else math.comb(dim + 2, dim)
+        if cell_verts.ndim != 2 or cell_verts.shape[1] != nv:
+            raise ValueError(f"cell geometry nodes must be [n_cell, {nv}]")
         n_loc = math.comb(degree + dim, dim) if degree >= 0 and dim >= 0 else -1
         if cell_nodes.ndim != 2 or cell_nodes.shape != (cell_verts.shape[0], n_loc):
             raise ValueError(f"cell_nodes must be [n_cell, {n_loc}] for degree {degree}")
         h = ctypes.c_void_p()
         self._h = None
-        _check(L.fem_plan_create(ctypes.byref(h), form, dim, degree, quad_degree,
+        create = L.fem_plan_create if geometry == 1 else L.fem_plan_create_curved
+        _check(create(ctypes.byref(h), form, dim, degree, quad_degree,
                                  coords.shape[0], _np_ptr(coords), cell_verts.shape[0],
                                  _np_ptr(cell_verts), _np_ptr(cell_nodes), int(n_node),
                                  _np_ptr(prm) if prm.size else None, int(prm.size)))
         self._h = h
         self.form, self.dim, self.degree, self.quad_degree = form, dim, degree, quad_degree
+        self.geometry = geometry
         self.n_cell = cell_verts.shape[0]
         nl, nc, nq, ncol, nd = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(),
                                 ctypes.c_int64())
@@ -227,6 +237,10 @@ class Plan:
 
     @classmethod
     def from_mesh(cls, form: int, mesh, quad_degree: int, params=()):
+        """A plan on a generated mesh; curved meshes (``mesh.cell_gnodes`` set) give P2 cells."""
+        if getattr(mesh, "cell_gnodes", None) is not None:
+            return cls(form, mesh.dim, mesh.k, quad_degree, mesh.gcoords, mesh.cell_gnodes,
+                       mesh.cell_nodes, mesh.n_node, params, geometry=2)
         return cls(form, mesh.dim, mesh.k, quad_degree, mesh.coords, mesh.cell_verts,
                    mesh.cell_nodes, mesh.n_node, params)
 

@@ -186,6 +186,8 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             if (p->device != b->device) throw Error(FEM_E_ARG, "plans on different devices");
             for (int j = 0; j < i; ++j)
                 if (plans[j] == p) throw Error(FEM_E_ARG, "a plan appears twice in the batch");
+            if (p->geom != 1)
+                throw Error(FEM_E_UNSUPPORTED, "batches take plans of affine cells only");
             if (p->n_cell > 0 && (p->strategy != femx::STRAT_PATCH || p->patch == 0))
                 femx::set_strategy(p, FEM_SCATTER_PATCH, 0, 0, 0);
             b->plans.push_back(p);

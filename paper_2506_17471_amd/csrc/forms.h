@@ -20,11 +20,16 @@ __host__ __device__ constexpr int nloc_of(int dim, int k)
 
 // doubles per quadrature-point record of the kernel table (see table_record()): values
 // phi_a (mass, Helmholtz), reference derivatives (all but mass), the weight; even length
-__host__ __device__ constexpr int record_of(int form, int dim, int nloc)
+__host__ __device__ constexpr int record_base(int form, int dim, int nloc)
 {
-    const int vals = (form == FEM_MASS || form == FEM_HELMHOLTZ) ? nloc : 0;
-    const int ders = form == FEM_MASS ? 0 : dim * nloc;
-    return (vals + ders + 1 + 1) & ~1;
+    return ((form == FEM_MASS || form == FEM_HELMHOLTZ) ? nloc : 0) +
+           (form == FEM_MASS ? 0 : dim * nloc) + 1;
+}
+
+// ... then, for P2 geometry (geo = 2), the geometry basis' reference derivatives
+__host__ __device__ constexpr int record_of(int form, int dim, int nloc, int geo = 1)
+{
+    return (record_base(form, dim, nloc) + (geo == 2 ? dim * (dim == 2 ? 6 : 10) : 0) + 1) & ~1;
 }
 
 // 1/d: hardware reciprocal estimate refined by two Newton-Raphson steps (each doubles the
@@ -78,15 +83,10 @@ __device__ __forceinline__ double ln_pos(double x)
 }
 
 // K = J^{-1} and |det J| from the vertex coordinates (J[i][r] = x_{r+1,i} - x_{0,i}).
+// K = J^{-1} by cofactors; returns |det J|
 template <int DIM>
-__device__ __forceinline__ double affine_geometry(const double (&x)[DIM + 1][DIM],
-                                                  double (&K)[DIM][DIM])
+__device__ __forceinline__ double jacobian_inverse(const double (&J)[DIM][DIM], double (&K)[DIM][DIM])
 {
-    double J[DIM][DIM];
-#pragma unroll
-    for (int i = 0; i < DIM; ++i)
-#pragma unroll
-        for (int r = 0; r < DIM; ++r) J[i][r] = x[r + 1][i] - x[0][i];
     if constexpr (DIM == 2) {
         const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
         const double inv = 1.0 / det;
@@ -114,7 +114,57 @@ __device__ __forceinline__ double affine_geometry(const double (&x)[DIM + 1][DIM
     }
 }
 
-// A^{-1} and det A for a small matrix.
+// affine cell from its vertices: J = [x_1 - x_0 | ... | x_d - x_0], K = J^{-1}, |det J|
+template <int DIM>
+__device__ __forceinline__ double affine_geometry(const double (&x)[DIM + 1][DIM],
+                                                  double (&K)[DIM][DIM])
+{
+    double J[DIM][DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) J[i][r] = x[r + 1][i] - x[0][i];
+    return jacobian_inverse<DIM>(J, K);
+}
+
+// geometry nodes a cell carries: the d+1 vertices (affine) or the P2 lattice (GEO = 2)
+__host__ __device__ constexpr int geom_nodes(int dim, int geo)
+{
+    return geo == 2 ? nloc_of(dim, 2) : dim + 1;
+}
+
+// Non-affine cells (P2 geometry, paper Sec. 2.4): at quadrature point q,
+// J_ir = sum_g x_g,i d phi^G_g / d xi_r from the tabulated geometry gradients tg (r-major,
+// NG per direction), K = J^{-1} and |det J| per point.  For affine cells (GEO = 1) the
+// cell's constant K and |det J| pass through.
+template <int DIM, int GEO>
+__device__ __forceinline__ double point_geometry(const FEMX_CONSTANT double *tg,
+                                                 const double (&gx)[geom_nodes(DIM, GEO)][DIM],
+                                                 const double (&Kc)[DIM][DIM], double adc,
+                                                 double (&Kq)[DIM][DIM])
+{
+    if constexpr (GEO == 1) {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) Kq[i][j] = Kc[i][j];
+        return adc;
+    } else {
+        constexpr int NG = geom_nodes(DIM, GEO);
+        double J[DIM][DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) acc = fma(gx[g][i], tg[r * NG + g], acc);
+                J[i][r] = acc;
+            }
+        return jacobian_inverse<DIM>(J, Kq);
+    }
+}
+
 template <int DIM>
 __device__ __forceinline__ double invert(const double (&A)[DIM][DIM], double (&B)[DIM][DIM])
 {
@@ -358,16 +408,20 @@ __device__ __forceinline__ void pointwise(const double (&G)[DIM][DIM], const dou
 // The quadrature loop of one cell: evaluation of u (and v) at each point from the
 // tabulation, the pointwise form, and accumulation into yl against the test functions.
 // The tabulation address is uniform across the wavefront (constant address space), so its
-// values arrive through scalar loads.
-template <int FORM, int DIM, int K, bool VJP>
+// values arrive through scalar loads.  GEO = 2: P2-geometry cells, whose K and |det J|
+// are evaluated at every point from the geometry nodes gx (unused for GEO = 1, where the
+// cell's constant Kinv and adet hold).
+template <int FORM, int DIM, int K, bool VJP, int GEO = 1>
 __device__ __forceinline__ void cell_quadrature(
     const double (&ul)[nloc_of(DIM, K)][ncomp_of(FORM, DIM)],
     const double (&vl)[VJP ? nloc_of(DIM, K) : 1][ncomp_of(FORM, DIM)],
-    const double (&Kinv)[DIM][DIM], double adet, const double *table, int nq, double lam,
-    double mu, double (&yl)[nloc_of(DIM, K)][ncomp_of(FORM, DIM)])
+    const double (&Kinv)[DIM][DIM], double adet, const double (&gx)[geom_nodes(DIM, GEO)][DIM],
+    const double *table, int nq, double lam, double mu,
+    double (&yl)[nloc_of(DIM, K)][ncomp_of(FORM, DIM)])
 {
     constexpr int NLOC = nloc_of(DIM, K);
-    constexpr int REC = record_of(FORM, DIM, NLOC);
+    constexpr int REC = record_of(FORM, DIM, NLOC, GEO);
+    constexpr int GOFF = record_base(FORM, DIM, NLOC);      // geometry gradients (GEO = 2)
     const FEMX_CONSTANT double *tab = (const FEMX_CONSTANT double *)table;
     if constexpr (FORM == FEM_MASS) {
 #pragma unroll
@@ -375,10 +429,12 @@ __device__ __forceinline__ void cell_quadrature(
 #pragma unroll 1
         for (int q = 0; q < nq; ++q) {
             const FEMX_CONSTANT double *t = tab + q * REC;
+            double Kq[DIM][DIM];
+            const double adq = point_geometry<DIM, GEO>(t + GOFF, gx, Kinv, adet, Kq);
             double uq = 0.0;
 #pragma unroll
             for (int n = 0; n < NLOC; ++n) uq = fma(t[n], ul[n][0], uq);
-            const double e = t[NLOC] * adet * uq;
+            const double e = t[NLOC] * adq * uq;
 #pragma unroll
             for (int n = 0; n < NLOC; ++n) yl[n][0] = fma(t[n], e, yl[n][0]);
         }
@@ -387,21 +443,34 @@ __device__ __forceinline__ void cell_quadrature(
         constexpr int D0 = FORM == FEM_HELMHOLTZ ? NLOC : 0;
         // K K^T maps reference derivatives of u to the flux against reference test
         // derivatives: grad phi_a . grad u = sum_rs dref_r phi_a (K K^T)_rs dref_s u
-        double KKt[DIM][DIM];
+        auto kkt = [](const double (&Km)[DIM][DIM], double (&KKt)[DIM][DIM]) {
 #pragma unroll
-        for (int r = 0; r < DIM; ++r)
+            for (int r = 0; r < DIM; ++r)
 #pragma unroll
-            for (int s2 = 0; s2 < DIM; ++s2) {
-                double acc = 0.0;
+                for (int s2 = 0; s2 < DIM; ++s2) {
+                    double acc = 0.0;
 #pragma unroll
-                for (int j = 0; j < DIM; ++j) acc = fma(Kinv[r][j], Kinv[s2][j], acc);
-                KKt[r][s2] = acc;
-            }
+                    for (int j = 0; j < DIM; ++j) acc = fma(Km[r][j], Km[s2][j], acc);
+                    KKt[r][s2] = acc;
+                }
+        };
+        double KKc[DIM][DIM];       // the affine cell's constant K K^T
+        if constexpr (GEO == 1) kkt(Kinv, KKc);
 #pragma unroll
         for (int n = 0; n < NLOC; ++n) yl[n][0] = 0.0;
 #pragma unroll 1
         for (int q = 0; q < nq; ++q) {
             const FEMX_CONSTANT double *t = tab + q * REC;
+            double Kq[DIM][DIM], KKt[DIM][DIM];
+            const double adq = point_geometry<DIM, GEO>(t + GOFF, gx, Kinv, adet, Kq);
+            if constexpr (GEO == 2) {
+                kkt(Kq, KKt);
+            } else {
+#pragma unroll
+                for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                    for (int s2 = 0; s2 < DIM; ++s2) KKt[r][s2] = KKc[r][s2];
+            }
             double g[DIM];
 #pragma unroll
             for (int r = 0; r < DIM; ++r) {
@@ -410,7 +479,7 @@ __device__ __forceinline__ void cell_quadrature(
                 for (int n = 0; n < NLOC; ++n) acc = fma(t[D0 + r * NLOC + n], ul[n][0], acc);
                 g[r] = acc;
             }
-            const double W = t[D0 + DIM * NLOC] * adet;
+            const double W = t[D0 + DIM * NLOC] * adq;
             double f[DIM];
 #pragma unroll
             for (int r = 0; r < DIM; ++r) {
@@ -442,6 +511,8 @@ __device__ __forceinline__ void cell_quadrature(
             for (int c = 0; c < DIM; ++c) yl[n][c] = 0.0;
         auto point = [&](int q) {
             const FEMX_CONSTANT double *t = tab + q * REC;
+            double Kq[DIM][DIM];
+            const double adq = point_geometry<DIM, GEO>(t + GOFF, gx, Kinv, adet, Kq);
             double gu[DIM][DIM], gv[DIM][DIM];
 #pragma unroll
             for (int c = 0; c < DIM; ++c)
@@ -462,10 +533,10 @@ __device__ __forceinline__ void cell_quadrature(
                     }
                 }
             double G[DIM][DIM], H[DIM][DIM], S[DIM][DIM], T[DIM][DIM];
-            to_physical<DIM>(gu, Kinv, G);
-            if constexpr (VJP) to_physical<DIM>(gv, Kinv, H);
+            to_physical<DIM>(gu, Kq, G);
+            if constexpr (VJP) to_physical<DIM>(gv, Kq, H);
             pointwise<FORM, DIM, VJP>(G, H, lam, mu, S);
-            pull_back<DIM>(S, Kinv, t[DIM * NLOC] * adet, T);
+            pull_back<DIM>(S, Kq, t[DIM * NLOC] * adq, T);
 #pragma unroll
             for (int n = 0; n < NLOC; ++n)
 #pragma unroll
@@ -477,9 +548,9 @@ __device__ __forceinline__ void cell_quadrature(
         };
         // Two points per trip give the scheduler two independent pointwise chains (the
         // log and reciprocal sequences are long serial dependences) where the cell's
-        // values and outputs leave room: forward actions with at most 42 of them.
-        // Larger cells and the VJP run one point per trip.
-        if constexpr (!VJP && NLOC * DIM <= 42) {
+        // values and outputs leave room: affine forward actions with at most 42 of them.
+        // Larger cells, curved cells and the VJP run one point per trip.
+        if constexpr (!VJP && GEO == 1 && NLOC * DIM <= 42) {
 #pragma unroll 2
             for (int q = 0; q < nq; ++q) point(q);
         } else {

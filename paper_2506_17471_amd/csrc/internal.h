@@ -40,9 +40,11 @@ bool has_symmetric_rule(int dim, int quad_degree);
 // Kernel-side table layout: per quadrature point a contiguous record.
 //   mass:  [phi_0 .. phi_{nloc-1}, w]                       (nloc + 1 doubles)
 //   vector forms: [dphi_r(a) for r in 0..d-1 for a, w]      (d*nloc + 1 doubles)
-// padded to an even number of doubles so every record starts 16-byte aligned.
-int table_record(int form, int dim, int nloc);
-std::vector<double> kernel_table(int form, const RefTables &t);
+// and, for P2-geometry cells, the geometry basis' reference derivatives after the weight
+// ([dphiG_r(g) for r for g], d * n_gnode doubles, from the tables `g`), padded to an even
+// number of doubles so every record starts 16-byte aligned.
+int table_record(int form, int dim, int nloc, int geom = 1);
+std::vector<double> kernel_table(int form, const RefTables &t, const RefTables *g = nullptr);
 
 // Launch parameters of one colour class.
 struct LaunchArgs {
@@ -111,6 +113,7 @@ struct FixDesc {
 struct fem_plan {
     int form = 0, dim = 0, degree = 0, quad_degree = 0, nloc = 0, ncomp = 0, nq = 0;
     int quad_family = FEM_QUAD_CONICAL;
+    int geom = 1;                        // geometry degree: 1 affine cells, 2 P2 (curved)
     int64_t n_vert = 0, n_cell = 0, n_node = 0, n_dof = 0;
     double lam = 0.0, mu = 0.0;
     int n_colours = 0;
@@ -179,7 +182,9 @@ constexpr int ncomp_of(int form, int dim) { return scalar_form(form) ? 1 : dim; 
 bool pair_available(int form, int dim, int degree);
 bool triple_available(int form, int dim, int degree);
 int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int lanes,
-                     int sum_mode);
+                     int sum_mode, int geom = 1);
+// geometry nodes of a cell: the d+1 vertices, or the P2 lattice of a curved cell
+inline int cell_geom_nodes(int dim, int geom) { return geom == 2 ? (dim == 2 ? 6 : 10) : dim + 1; }
 int patch_threads(int P, int lanes);
 hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patch, int sum_mode,
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,

@@ -37,6 +37,8 @@ struct Kernels {
     ColourFn colour;
     PatchFn patch[4][3];  // [lanes per cell 1..3][sum mode 1..2], null where absent
     BatchFn batch[4][3];
+    ColourFn colour_p2;   // P2-geometry cells: colour kernel and one-lane patch kernels
+    PatchFn patch_p2[3];  // [sum mode 1..2]
 };
 
 // one per form, each in its own translation unit (they compile in parallel)
@@ -55,11 +57,12 @@ namespace {
 // Waves per SIMD the register allocator is asked to leave room for (occupancy target):
 // the lane-pair kernels and the one-lane low-degree 2D kernels fit without spilling in
 // the loop; everything else keeps the allocator's default.
-constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc)
+constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc, int geo = 1)
 {
     if (lpc == 3) return 1;
     if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : 4;
-    return (!vjp && dim == 2 && k <= 4 && !scalar_form(form)) ? 3 : 1;
+    // curved cells hold their geometry nodes through the loop: two waves, not three
+    return (!vjp && dim == 2 && k <= 4 && !scalar_form(form)) ? (geo == 2 ? 2 : 3) : 1;
 }
 
 template <int DIM>
@@ -78,8 +81,30 @@ __device__ __forceinline__ double gather_geometry(const int32_t *__restrict__ ve
     return affine_geometry<DIM>(x, K);
 }
 
+// The cell's geometry: its affine K and |det J| (GEO = 1, vertices), or the coordinates of
+// its P2 geometry nodes for per-point evaluation (GEO = 2; K and |det J| then unused).
+template <int DIM, int GEO>
+__device__ __forceinline__ double gather_cell_geometry(const int32_t *__restrict__ verts,
+                                                       int64_t stride, int64_t s,
+                                                       const double *__restrict__ coords,
+                                                       double (&K)[DIM][DIM],
+                                                       double (&gx)[geom_nodes(DIM, GEO)][DIM])
+{
+    if constexpr (GEO == 1) {
+        return gather_geometry<DIM>(verts, stride, s, coords, K);
+    } else {
+#pragma unroll
+        for (int g = 0; g < geom_nodes(DIM, GEO); ++g) {
+            const int64_t vg = verts[g * stride + s];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) gx[g][i] = coords[vg * DIM + i];
+        }
+        return 0.0;
+    }
+}
+
 // ------------------------------------------------------------------ colour strategy
-template <int FORM, int DIM, int K, bool VJP>
+template <int FORM, int DIM, int K, bool VJP, int GEO>
 __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
 {
     constexpr int NLOC = nloc_of(DIM, K);
@@ -87,8 +112,8 @@ __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.count) return;
     const int64_t s = a.begin + i;
-    double Kinv[DIM][DIM];
-    const double adet = gather_geometry<DIM>(a.verts, a.stride, s, a.coords, Kinv);
+    double Kinv[DIM][DIM], gx[geom_nodes(DIM, GEO)][DIM];
+    const double adet = gather_cell_geometry<DIM, GEO>(a.verts, a.stride, s, a.coords, Kinv, gx);
     double ul[NLOC][NC], vl[VJP ? NLOC : 1][NC], yl[NLOC][NC];
 #pragma unroll
     for (int n = 0; n < NLOC; ++n) {
@@ -99,7 +124,7 @@ __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
             if constexpr (VJP) vl[n][c] = a.v[nd * NC + c];
         }
     }
-    cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
+    cell_quadrature<FORM, DIM, K, VJP, GEO>(ul, vl, Kinv, adet, gx, a.tab, a.nq, a.lam, a.mu, yl);
     const uint64_t first = a.first[s];
 #pragma unroll
     for (int n = 0; n < NLOC; ++n) {
@@ -182,7 +207,7 @@ __device__ __forceinline__ void stage_copy(const T *__restrict__ src, int n, int
 // 3 for the 3D vector forms (lane c of a triple owns component c; a wavefront holds 21
 // triples and leaves its last lane idle).  SUM: SUM_ELEMENT (LDS element buffer and fixed-
 // order node sums) or SUM_COLOURED (sub-colour phases accumulating into an LDS node buffer).
-template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM, int GEO>
 __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 {
     constexpr int NLOC = nloc_of(DIM, K);
@@ -190,6 +215,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && !scalar_form(FORM)) ||
                       (LPC == 3 && DIM == 3 && !scalar_form(FORM)),
                   "lane split");
+    static_assert(GEO == 1 || LPC == 1, "P2-geometry cells run one lane per cell");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
@@ -217,10 +243,10 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     const int64_t s = p * P + cl;
     const bool active = cl < P && s < a.n_cell;
     constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
-    double Kinv[DIM][DIM], adet = 0.0;
+    double Kinv[DIM][DIM], adet = 0.0, gx[geom_nodes(DIM, GEO)][DIM];
     int lid[NLOC];
     if (active) {
-        adet = gather_geometry<DIM>(a.verts, a.stride, s, a.coords, Kinv);
+        adet = gather_cell_geometry<DIM, GEO>(a.verts, a.stride, s, a.coords, Kinv, gx);
 #pragma unroll
         for (int n = 0; n < NLOC; ++n) lid[n] = a.lidx[n * a.stride + s];
     }
@@ -260,7 +286,8 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     // 3. the cell's quadrature loop
     if (active) {
         if constexpr (LPC == 1) {
-            cell_quadrature<FORM, DIM, K, VJP>(ul, vl, Kinv, adet, a.tab, a.nq, a.lam, a.mu, yl);
+            cell_quadrature<FORM, DIM, K, VJP, GEO>(ul, vl, Kinv, adet, gx, a.tab, a.nq, a.lam,
+                                                    a.mu, yl);
         } else if constexpr (LPC == 3) {
             double u1[NLOC], v1[VJP ? NLOC : 1], y1[NLOC];
 #pragma unroll
@@ -364,12 +391,12 @@ __device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n)
     return x * q + (x < r ? x : r) + i;
 }
 
-template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM, int GEO>
 __global__ void __launch_bounds__(kMaxBlock)
-    __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
+    __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC, GEO))))
     patch_kernel(const PatchArgs a, int P)
 {
-    patch_body<FORM, DIM, K, VJP, LPC, SUM>(a, xcd_order(blockIdx.x, gridDim.x), P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM, GEO>(a, xcd_order(blockIdx.x, gridDim.x), P);
 }
 
 // Many meshes of one kernel variant in one launch: workgroup b works on patch
@@ -383,14 +410,14 @@ __global__ void __launch_bounds__(kMaxBlock)
     const int64_t b = xcd_order(blockIdx.x, gridDim.x);
     const int m = patch_mesh[b];
     const BatchDesc &d = desc[m];
-    patch_body<FORM, DIM, K, VJP, LPC, SUM>(d.args, b - d.first_patch, P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM, 1>(d.args, b - d.first_patch, P);
 }
 
 template <int FORM, int DIM, int K, bool VJP, int LPC>
 void fill_lanes(Kernels &k)
 {
-    k.patch[LPC][SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
-    k.patch[LPC][SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+    k.patch[LPC][SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT, 1>;
+    k.patch[LPC][SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED, 1>;
     k.batch[LPC][SUM_ELEMENT] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
     k.batch[LPC][SUM_COLOURED] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
 }
@@ -399,8 +426,11 @@ template <int FORM, int DIM, int K, bool VJP>
 Kernels entry()
 {
     Kernels k{};
-    k.colour = colour_kernel<FORM, DIM, K, VJP>;
+    k.colour = colour_kernel<FORM, DIM, K, VJP, 1>;
     fill_lanes<FORM, DIM, K, VJP, 1>(k);
+    k.colour_p2 = colour_kernel<FORM, DIM, K, VJP, 2>;
+    k.patch_p2[SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_ELEMENT, 2>;
+    k.patch_p2[SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_COLOURED, 2>;
     if constexpr (DIM == 2 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 2>(k);
     if constexpr (DIM == 3 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 3>(k);
     return k;

@@ -83,7 +83,8 @@ bool kernel_available(int form, int dim, int degree)
 hipError_t launch_action(const fem_plan &p, const LaunchArgs &a, int block, bool vjp,
                          hipStream_t s)
 {
-    ColourFn fn = lookup(p.form, p.dim, p.degree, vjp).colour;
+    const Kernels ks = lookup(p.form, p.dim, p.degree, vjp);
+    ColourFn fn = p.geom == 2 ? ks.colour_p2 : ks.colour;
     if (!fn) return hipErrorInvalidDeviceFunction;
     if (block <= 0) block = 64;
     if (block > kMaxBlock) return hipErrorInvalidConfiguration;
@@ -129,12 +130,16 @@ bool triple_available(int form, int dim, int degree)
 // Registers per lane of the kernel a launch configuration runs (the compiled kernel's
 // attributes), 0 if that kernel is not built.
 int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int lanes,
-                     int sum_mode)
+                     int sum_mode, int geom)
 {
     const Kernels ks = lookup(form, dim, degree, vjp);
-    const void *fn = colour ? (const void *)ks.colour
-                            : (lanes >= 1 && lanes <= 3 && sum_mode >= 1 && sum_mode <= 2
-                                   ? (const void *)ks.patch[lanes][sum_mode] : nullptr);
+    const bool ok = lanes >= 1 && lanes <= 3 && sum_mode >= 1 && sum_mode <= 2;
+    const void *fn = nullptr;
+    if (geom == 2)
+        fn = colour ? (const void *)ks.colour_p2
+                    : (ok && lanes == 1 ? (const void *)ks.patch_p2[sum_mode] : nullptr);
+    else
+        fn = colour ? (const void *)ks.colour : (ok ? (const void *)ks.patch[lanes][sum_mode] : nullptr);
     if (!fn) return 0;
     hipFuncAttributes attr{};
     if (hipFuncGetAttributes(&attr, fn) != hipSuccess) {
@@ -193,7 +198,9 @@ hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStre
     if (p.lanes < 1 || p.lanes > 3 || (p.sum_mode != SUM_ELEMENT && p.sum_mode != SUM_COLOURED))
         return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(p.form, p.dim, p.degree, vjp);
-    PatchFn fn = ks.patch[p.lanes][p.sum_mode];
+    // curved cells run the one-lane kernels only
+    PatchFn fn = p.geom == 2 ? (p.lanes == 1 ? ks.patch_p2[p.sum_mode] : nullptr)
+                             : ks.patch[p.lanes][p.sum_mode];
     if (!fn) return hipErrorInvalidDeviceFunction;
     const int threads = patch_threads(p.patch, p.lanes);
     if (p.patch < 1 || p.patch > 256 || threads > kMaxBlock) return hipErrorInvalidConfiguration;

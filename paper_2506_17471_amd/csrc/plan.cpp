@@ -198,12 +198,61 @@ int default_patch(const fem_plan *p);
 int default_lanes(const fem_plan *p);
 int default_sum_mode(const fem_plan *p);
 
+// Curved cells: det J (J = sum_g x_g (x) grad_xi phiG_g) at every point of the rule must be
+// finite, nonzero and of one sign over the cell, positive in 2D.  Only the points are
+// checked: they are where the action evaluates the map.
+void check_curved(const fem_plan *p, const double *coords, const int32_t *cell_gnodes,
+                  const femx::RefTables &g)
+{
+    const int d = p->dim, ng = g.nloc;
+    for (int64_t c = 0; c < p->n_cell; ++c) {
+        double sign0 = 0.0;
+        for (int q = 0; q < g.nq; ++q) {
+            double J[3][3] = {};
+            for (int k = 0; k < ng; ++k) {
+                const double *x = coords + (int64_t)cell_gnodes[c * ng + k] * d;
+                for (int i = 0; i < d; ++i)
+                    for (int r = 0; r < d; ++r) J[i][r] += x[i] * g.dphi[((size_t)q * ng + k) * d + r];
+            }
+            const double det = d == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                                      : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            if (q == 0) sign0 = det;
+            if (!std::isfinite(det) || det == 0.0 || (d == 2 && det < 0.0) || det * sign0 <= 0.0)
+                throw femx::Error(FEM_E_INVERTED, "curved cell " + std::to_string(c) +
+                                                      " has det J = " + std::to_string(det) +
+                                                      " at quadrature point " + std::to_string(q));
+        }
+    }
+}
+
+// the rule family a plan starts with: the fully symmetric rule (fewest points) wherever one
+// is built for the degree, else the conical rule
+int default_family(const fem_plan *p)
+{
+    return femx::has_symmetric_rule(p->dim, p->quad_degree) ? FEM_QUAD_SYMMETRIC : FEM_QUAD_CONICAL;
+}
+
+// Kernel tables of the plan's form on the rule of `family`; curved plans append the P2
+// geometry gradients (and, with `check`, have det J checked at the rule's points).
+std::vector<double> plan_tables(const fem_plan *p, int family, const double *coords,
+                                const int32_t *cell_verts, bool check, int *nq)
+{
+    femx::RefTables t = femx::reference_tables(p->dim, p->degree, p->quad_degree, family);
+    *nq = t.nq;
+    if (p->geom == 1) return femx::kernel_table(p->form, t);
+    femx::RefTables g = femx::reference_tables(p->dim, 2, p->quad_degree, family);
+    if (check) check_curved(p, coords, cell_verts, g);
+    return femx::kernel_table(p->form, t, &g);
+}
+
 // Host-side validation of the mesh; runs before any HIP call.
 void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
                    const int32_t *cell_nodes, const double *params, int n_params)
 {
     using femx::Error;
-    const int d = p->dim, nv = d + 1, nloc = p->nloc;
+    const int d = p->dim, nv = femx::cell_geom_nodes(d, p->geom), nloc = p->nloc;
     if (!femx::scalar_form(p->form)) {
         if (n_params < 2 || !params) throw Error(FEM_E_ARG, "vector forms need params {lambda, mu}");
         p->lam = params[0];
@@ -218,7 +267,14 @@ void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
     for (int64_t i = 0; i < p->n_cell * nloc; ++i)
         if (cell_nodes[i] < 0 || cell_nodes[i] >= p->n_node)
             throw Error(FEM_E_INDEX, "cell_nodes entry " + std::to_string(i) + " out of range");
-    for (int64_t c = 0; c < p->n_cell; ++c) {
+    // curved cells: det J varies over the cell and is checked at the points of the rule the
+    // plan starts with
+    if (p->geom == 2) {
+        const femx::RefTables g =
+            femx::reference_tables(d, 2, p->quad_degree, default_family(p));
+        check_curved(p, coords, cell_verts, g);
+    }
+    for (int64_t c = 0; p->geom == 1 && c < p->n_cell; ++c) {
         double e[3][3];
         const double *x0 = coords + (int64_t)cell_verts[c * nv] * d;
         for (int r = 0; r < d; ++r) {
@@ -238,16 +294,13 @@ void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
 void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
                 const int32_t *cell_nodes)
 {
-    const int d = p->dim, nv = d + 1, nloc = p->nloc;
+    const int d = p->dim, nv = femx::cell_geom_nodes(d, p->geom), nloc = p->nloc;
     // --- reference tables
-    // the fully symmetric rule (fewest points) wherever one is built for the degree, else
-    // the conical rule; for the linear forms both give the same operator, the neo-Hookean
-    // integrand is not polynomial and its operator depends on the rule
-    p->quad_family = femx::has_symmetric_rule(d, p->quad_degree) ? FEM_QUAD_SYMMETRIC
-                                                                  : FEM_QUAD_CONICAL;
-    femx::RefTables t = femx::reference_tables(d, p->degree, p->quad_degree, p->quad_family);
-    p->nq = t.nq;
-    std::vector<double> tab = femx::kernel_table(p->form, t);
+    // for the linear forms on affine cells both rule families give the same operator; the
+    // hyperelastic integrands (and curved cells) are not polynomial of the rule's degree,
+    // and their operator depends on the rule
+    p->quad_family = default_family(p);
+    std::vector<double> tab = plan_tables(p, p->quad_family, coords, cell_verts, false, &p->nq);
 
     // --- colouring and colour-sorted structure-of-arrays maps
     p->n_colours = p->n_cell ? greedy_colouring(p->n_cell, nloc, cell_nodes, p->n_node, p->colour) : 0;
@@ -319,7 +372,7 @@ uint64_t spread3(uint64_t v)
 
 std::vector<int64_t> morton_order(const fem_plan *p, const double *coords, const int32_t *cell_verts)
 {
-    const int d = p->dim, nv = d + 1;
+    const int d = p->dim, nv = femx::cell_geom_nodes(d, p->geom);
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < p->n_vert; ++v)
         for (int i = 0; i < d; ++i) {
@@ -373,7 +426,7 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
                               const int32_t *cell_nodes, int P)
 {
     using femx::Error;
-    const int nv = p->dim + 1, nloc = p->nloc;
+    const int nv = femx::cell_geom_nodes(p->dim, p->geom), nloc = p->nloc;
     if (P < 1 || P > 256) throw Error(FEM_E_ARG, "patch size must be 1..256");
     if (nloc > 255) throw Error(FEM_E_UNSUPPORTED, "more than 255 nodes per cell");
     PatchLayout L;
@@ -620,6 +673,7 @@ int default_sum_mode(const fem_plan *p)
 // where one lane's cell vector would not fit its registers.
 int default_lanes(const fem_plan *p)
 {
+    if (p->geom == 2) return 1;    // curved cells: one-lane kernels only
     if (femx::triple_available(p->form, p->dim, p->degree) && p->degree >= 3) return 3;
     return 1;
 }
@@ -764,6 +818,8 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
         if (patch_cells != 0 && !patch_allowed(patch_cells, lanes)) lanes = 1;
     }
     if (lanes < 1 || lanes > 3) throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1, 2 or 3");
+    if (lanes > 1 && plan->geom == 2)
+        throw Error(FEM_E_UNSUPPORTED, "curved cells run one lane per cell");
     if (lanes == 2 && !pair_available(plan->form, plan->dim, plan->degree))
         throw Error(FEM_E_UNSUPPORTED, "two lanes per cell exist for the 2D vector forms only");
     if (lanes == 3 && !triple_available(plan->form, plan->dim, plan->degree))
@@ -812,12 +868,10 @@ void check_hip(hipError_t e, const char *what)
 }
 }  // namespace femx
 
-extern "C" {
-
-int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degree,
-                    int64_t n_vert, const double *coords, int64_t n_cell,
-                    const int32_t *cell_verts, const int32_t *cell_nodes, int64_t n_node,
-                    const double *params, int n_params)
+namespace {
+int create_plan(fem_plan **out, int form, int dim, int degree, int quad_degree, int geom,
+                int64_t n_vert, const double *coords, int64_t n_cell, const int32_t *cell_verts,
+                const int32_t *cell_nodes, int64_t n_node, const double *params, int n_params)
 {
     if (out) *out = nullptr;
     fem_plan *p = nullptr;
@@ -839,6 +893,7 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
         p->dim = dim;
         p->degree = degree;
         p->quad_degree = quad_degree;
+        p->geom = geom;
         p->nloc = femx::n_local(dim, degree);
         p->ncomp = femx::ncomp_of(form, dim);
         p->n_vert = n_vert;
@@ -847,7 +902,7 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
         p->n_dof = n_node * p->ncomp;
         validate_mesh(p, coords, cell_verts, cell_nodes, params, n_params);
         p->h_coords.assign(coords, coords + n_vert * dim);
-        p->h_cell_verts.assign(cell_verts, cell_verts + n_cell * (dim + 1));
+        p->h_cell_verts.assign(cell_verts, cell_verts + n_cell * femx::cell_geom_nodes(dim, geom));
         p->h_cell_nodes.assign(cell_nodes, cell_nodes + n_cell * p->nloc);
         femx::check_hip(hipGetDevice(&p->device), "hipGetDevice");
         build_plan(p, coords, cell_verts, cell_nodes);
@@ -860,6 +915,27 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
     }
     *out = p;
     return FEM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degree,
+                    int64_t n_vert, const double *coords, int64_t n_cell,
+                    const int32_t *cell_verts, const int32_t *cell_nodes, int64_t n_node,
+                    const double *params, int n_params)
+{
+    return create_plan(out, form, dim, degree, quad_degree, 1, n_vert, coords, n_cell,
+                       cell_verts, cell_nodes, n_node, params, n_params);
+}
+
+int fem_plan_create_curved(fem_plan **out, int form, int dim, int degree, int quad_degree,
+                           int64_t n_gnode, const double *gcoords, int64_t n_cell,
+                           const int32_t *cell_gnodes, const int32_t *cell_nodes, int64_t n_node,
+                           const double *params, int n_params)
+{
+    return create_plan(out, form, dim, degree, quad_degree, 2, n_gnode, gcoords, n_cell,
+                       cell_gnodes, cell_nodes, n_node, params, n_params);
 }
 
 void fem_plan_destroy(fem_plan *plan)
@@ -1046,13 +1122,14 @@ int fem_plan_set_quadrature(fem_plan *plan, int family)
 {
     return guarded([&] {
         check_plan(plan);
-        femx::RefTables t = femx::reference_tables(plan->dim, plan->degree, plan->quad_degree, family);
-        std::vector<double> tab = femx::kernel_table(plan->form, t);
+        int nq = 0;
+        std::vector<double> tab = plan_tables(plan, family, plan->h_coords.data(),
+                                              plan->h_cell_verts.data(), true, &nq);
         double *d = device_upload(tab, "tables");
         femx::check_hip(hipDeviceSynchronize(), "synchronise before replacing tables");
         (void)hipFree(plan->d_tab);
         plan->d_tab = d;
-        plan->nq = t.nq;
+        plan->nq = nq;
         plan->quad_family = family;
     });
 }

@@ -524,20 +524,24 @@ RefTables reference_tables(int dim, int degree, int quad_degree, int family)
     return t;
 }
 
-int table_record(int form, int dim, int nloc)
+int table_record(int form, int dim, int nloc, int geom)
 {
     const int vals = (form == FEM_MASS || form == FEM_HELMHOLTZ) ? nloc : 0;
     const int ders = form == FEM_MASS ? 0 : dim * nloc;
-    return (vals + ders + 1 + 1) & ~1;
+    const int gders = geom == 2 ? dim * cell_geom_nodes(dim, 2) : 0;
+    return (vals + ders + 1 + gders + 1) & ~1;
 }
 
 // Per quadrature point: phi_a (mass, Helmholtz), then d phi_a / d xi_r for r, a (all other
-// forms, r-major), then the weight; zero-padded to an even length.
-std::vector<double> kernel_table(int form, const RefTables &t)
+// forms, r-major), then the weight, then (curved cells, tables g of the P2 geometry basis
+// on the same rule) d phiG_g / d xi_r for r, g; zero-padded to an even length.
+std::vector<double> kernel_table(int form, const RefTables &t, const RefTables *g)
 {
-    const int rec = table_record(form, t.dim, t.nloc);
+    const int rec = table_record(form, t.dim, t.nloc, g ? 2 : 1);
     std::vector<double> out((size_t)t.nq * rec, 0.0);
     const bool vals = form == FEM_MASS || form == FEM_HELMHOLTZ, ders = form != FEM_MASS;
+    if (g && (g->nq != t.nq || g->dim != t.dim || g->nloc != cell_geom_nodes(t.dim, 2)))
+        throw Error(FEM_E_ARG, "geometry tables do not match the rule");
     for (int q = 0; q < t.nq; ++q) {
         double *o = &out[(size_t)q * rec];
         int k = 0;
@@ -547,7 +551,11 @@ std::vector<double> kernel_table(int form, const RefTables &t)
             for (int r = 0; r < t.dim; ++r)
                 for (int a = 0; a < t.nloc; ++a)
                     o[k++] = t.dphi[((size_t)q * t.nloc + a) * t.dim + r];
-        o[k] = t.weights[q];
+        o[k++] = t.weights[q];
+        if (g)
+            for (int r = 0; r < t.dim; ++r)
+                for (int a = 0; a < g->nloc; ++a)
+                    o[k++] = g->dphi[((size_t)q * g->nloc + a) * t.dim + r];
     }
     return out;
 }

@@ -46,7 +46,8 @@ std::string cache_key(const fem_plan *p)
     const int bucket = p->n_cell > 0 ? (int)std::lround(std::log2((double)p->n_cell)) : 0;
     std::ostringstream k;
     k << arch_name() << "/f" << p->form << "/d" << p->dim << "/k" << p->degree << "/q"
-      << p->quad_degree << (p->quad_family == FEM_QUAD_SYMMETRIC ? "s" : "c") << "/c" << bucket;
+      << p->quad_degree << (p->quad_family == FEM_QUAD_SYMMETRIC ? "s" : "c")
+      << (p->geom == 2 ? "/g2" : "") << "/c" << bucket;
     return k.str();
 }
 
@@ -166,6 +167,7 @@ std::vector<Candidate> candidates(const fem_plan *p)
     // patch sizes grouped so that one layout build serves both sum modes
     for (int P : {64, 128, 256})
         for (int m : {SUM_ELEMENT, SUM_COLOURED}) cands.push_back({FEM_SCATTER_PATCH, P, 1, 0, m});
+    if (p->geom == 2) return cands;     // curved cells: one lane per cell
     if (pair_available(p->form, p->dim, p->degree))
         for (int P : {64, 128})
             for (int m : {SUM_ELEMENT, SUM_COLOURED})
@@ -208,11 +210,14 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
     const double n = (double)p->n_cell, d = p->dim, nloc = p->nloc, nc = p->ncomp;
     const double nodes_per_cell = (double)p->n_node / std::max<int64_t>(1, p->n_cell);
     double instr = flops_per_point(p->form, p->dim, p->nloc, nl) * p->nq / 2.0 * 1.25;
+    // curved cells: J from the geometry gradients and its inverse at every point
+    const int ng = cell_geom_nodes(p->dim, p->geom);
+    if (p->geom == 2) instr += (2.0 * d * d * ng + (p->dim == 2 ? 12 : 60)) * p->nq / 2.0 * 1.25;
     if (c.lanes == 2) instr *= 1.35;                      // pointwise form on both lanes
     if (c.lanes == 3) instr *= 1.2;                       // shuffles of the gradient rows
     const int regs = kernel_registers(p->form, p->dim, p->degree, nl,
                                       c.strategy == FEM_SCATTER_COLOUR, c.lanes,
-                                      c.strategy == FEM_SCATTER_COLOUR ? 1 : c.sum_mode);
+                                      c.strategy == FEM_SCATTER_COLOUR ? 1 : c.sum_mode, p->geom);
     const double waves_regs = std::min(8, 512 / std::max(8, (regs + 7) / 8 * 8));
     double waves = waves_regs, rounds_sync = 0.0, barriers = 0.0, extra_bytes = 0.0;
     const double vec_bytes = 8.0 * p->n_node * nc;
@@ -234,7 +239,7 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
     const double eta = std::min(1.0, std::max(waves, 0.25) / 3.0);
     const double t_valu = n * instr * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
     const double bytes = vec_bytes * (nl ? 3 : 2) + 8.0 * d * p->n_vert +
-                         4.0 * (nloc + d + 1) * n + extra_bytes;
+                         4.0 * (nloc + ng) * n + extra_bytes;
     const double t_mem = bytes / 4.0e12;
     double t = std::max(t_valu, t_mem) + rounds_sync * barriers * 0.4e-6;
     if (c.strategy == FEM_SCATTER_COLOUR) t += p->n_colours * 4.0e-6;

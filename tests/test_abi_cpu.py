@@ -112,6 +112,43 @@ def test_error_paths_from_host():
     assert L.fem_plan_get_timing(None, None, None) == -1
 
 
+def _create_curved(mesh, gcoords=None, cell_gnodes=None, form=0, degree=2, qd=4):
+    L = fx.lib()
+    gc = np.ascontiguousarray(mesh.gcoords if gcoords is None else gcoords, dtype=np.float64)
+    cg = np.ascontiguousarray(mesh.cell_gnodes if cell_gnodes is None else cell_gnodes,
+                              dtype=np.int32)
+    cn = np.ascontiguousarray(mesh.cell_nodes, dtype=np.int32)
+    h = ctypes.c_void_p()
+    st = L.fem_plan_create_curved(ctypes.byref(h), form, mesh.dim, degree, qd, gc.shape[0],
+                                  gc.ctypes.data, cg.shape[0], cg.ctypes.data, cn.ctypes.data,
+                                  mesh.n_node, None, 0)
+    if st == 0:
+        L.fem_plan_destroy(h)
+    return st, L.fem_last_error().decode()
+
+
+def test_curved_plan_validation_from_host():
+    m = meshgen.curved(meshgen.unit_square(3, 2), 0.05)
+    # a valid curved mesh passes validation (and then needs a device)
+    st, _ = _create_curved(m)
+    try:
+        import torch
+        has_dev = torch.cuda.is_available()
+    except ImportError:
+        has_dev = False
+    assert st == (0 if has_dev else -5)
+    bad = m.cell_gnodes.copy()
+    bad[2, 3] = m.gcoords.shape[0]
+    assert _create_curved(m, cell_gnodes=bad)[0] == -3
+    # an edge node of cell 4 dragged across its cell folds the map: det J changes sign
+    gc = m.gcoords.copy()
+    c = 4
+    mid, opp = m.cell_gnodes[c, 1], m.cell_gnodes[c, 5]     # edge (v0, v1) and vertex v2
+    gc[mid] = gc[mid] + 1.5 * (gc[opp] - gc[mid])
+    st, msg = _create_curved(m, gcoords=gc)
+    assert st == -4 and "curved cell" in msg
+
+
 def test_plan_without_device_reports_hip_error():
     try:
         import torch

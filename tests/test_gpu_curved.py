@@ -1,0 +1,113 @@
+"""GPU parity on curved (non-affine, P2-geometry) cells: the HIP path through the C ABI
+(fem_plan_create_curved) against the CPU oracle, FP64, same bar as the affine cells
+(relative max and L2 error <= 1e-12)."""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_17471_amd as fx  # noqa: E402
+
+TOL = 1e-12
+DEV = torch.device("cuda:0")
+NH = (10.0, 1.0)
+LAME = meshgen.lame_from_young(1.0, 0.3)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_err(y, ref):
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    return np.max(np.abs(y - ref)) / scale, np.linalg.norm(y - ref) / max(np.linalg.norm(ref), 1e-300)
+
+
+def gpu(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def params_for(form):
+    if form in fx.SCALAR_FORMS:
+        return ()
+    return LAME if form == fx.FORM_ELASTICITY else NH
+
+
+def inputs(form, mesh, seed):
+    rng = np.random.default_rng(seed)
+    ncomp = 1 if form in fx.SCALAR_FORMS else mesh.dim
+    if form in (fx.FORM_NEOHOOKEAN, fx.FORM_SVK):
+        u = meshgen.nh_displacement(rng, mesh, 0.01 if form == fx.FORM_NEOHOOKEAN else 0.2)
+        if form == fx.FORM_NEOHOOKEAN:
+            assert oracle.min_det_f(mesh, u, 2 * mesh.k) > 0.5
+    else:
+        u = rng.uniform(-1, 1, mesh.n_node * ncomp)
+    return u, rng.uniform(-1, 1, mesh.n_node * ncomp)
+
+
+CASES = [(f, 2, k) for f in range(6) for k in range(1, 7)] + \
+        [(f, 3, k) for f in range(6) for k in range(1, 5)]
+STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_ELEMENT),
+          (fx.SCATTER_PATCH, 128, 1, fx.SUM_COLOURED), (fx.SCATTER_COLOUR, 0, 0, 0)]
+STRAT_IDS = ["patch", "patch64e", "patch128c", "colour"]
+
+
+@pytest.mark.parametrize("strategy", STRATS, ids=STRAT_IDS)
+@pytest.mark.parametrize("form,dim,k", CASES)
+def test_curved_action_and_vjp(form, dim, k, strategy):
+    # 2D n=9: 162 cells; 3D n=3: 162 cells -- several patches plus a ragged tail
+    n = 9 if dim == 2 else 3
+    mesh = meshgen.curved(meshgen.make_mesh(dim, n, k, None, np.random.default_rng(300 + k)), 0.08)
+    u, v = inputs(form, mesh, 70 + k)
+    qd = 2 * k
+    say(f"[curved] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd} strat={strategy}")
+    plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    assert plan.geometry == 2
+    plan.set_strategy(*strategy)
+    fam = plan.quad_family_name
+    y = plan.action(gpu(u)).cpu().numpy()
+    ref = oracle.action(form, mesh, u, qd, params_for(form), family=fam)
+    emax, el2 = rel_err(y, ref)
+    assert emax < TOL and el2 < TOL, ("action", emax, el2)
+    g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
+    gref = oracle.vjp(form, mesh, u, v, qd, params_for(form), family=fam)
+    emax, el2 = rel_err(g, gref)
+    assert emax < TOL and el2 < TOL, ("vjp", emax, el2)
+
+
+def test_curved_plan_rejects_lane_splits_and_batches():
+    mesh = meshgen.curved(meshgen.make_mesh(3, 2, 3, None, np.random.default_rng(1)), 0.05)
+    plan = fx.Plan.from_mesh(fx.FORM_ELASTICITY, mesh, 4, LAME)
+    assert plan.strategy()[2] == 1
+    with pytest.raises(fx.FemError):
+        plan.set_strategy(fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT)
+    u = gpu(np.zeros(mesh.n_node * 3))
+    with pytest.raises(fx.FemError):
+        fx.Batch([plan], [u], [torch.empty_like(u)])
+
+
+def test_curved_set_quadrature_and_straight_geometry():
+    # straight P2 geometry through the curved path equals the affine plan (rounding only)
+    m = meshgen.make_mesh(2, 6, 3, None, np.random.default_rng(5))
+    ms = meshgen.curved(m, 0.0)
+    u, _ = inputs(fx.FORM_NEOHOOKEAN, m, 9)
+    pa = fx.Plan.from_mesh(fx.FORM_NEOHOOKEAN, m, 6, NH)
+    pc = fx.Plan.from_mesh(fx.FORM_NEOHOOKEAN, ms, 6, NH)
+    ya, yc = pa.action(gpu(u)).cpu().numpy(), pc.action(gpu(u)).cpu().numpy()
+    assert rel_err(yc, ya)[0] < TOL
+    # switching the rule family rebuilds the geometry part of the tables
+    mc = meshgen.curved(m, 0.08)
+    pc2 = fx.Plan.from_mesh(fx.FORM_NEOHOOKEAN, mc, 6, NH)
+    pc2.set_quadrature(fx.QUAD_CONICAL)
+    y = pc2.action(gpu(u)).cpu().numpy()
+    ref = oracle.action(fx.FORM_NEOHOOKEAN, mc, u, 6, NH, family="conical")
+    assert rel_err(y, ref)[0] < TOL

@@ -265,7 +265,8 @@ def test_single_cell_and_ragged_counts():
         assert rel_err(y, ref)[0] < TOL
 
 
-FULL = ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d", "nh_vjp_p4_2d", "mass_p2_2d_1024", "svk_p4_2d"]
+FULL = ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d", "nh_vjp_p4_2d", "mass_p2_2d_1024", "svk_p4_2d",
+        "nh_p4_2d_curved", "mass_p2_2d_1024_curved"]
 _ref_cache = {}
 
 

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import test_oracle_action as pins
+import test_oracle_curved as curved
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
                    "fem_oracle.c")
@@ -25,12 +26,17 @@ MUTATIONS = {
     "nh_sign_of_cofactor": ("S[i][j] = mu * (F[i][j] - FiT) + lam * lnJ * FiT;",
                             "S[i][j] = mu * (F[i][j] + FiT) + lam * lnJ * FiT;",
                             [lambda: pins.test_hyper_invariances(pins.F_NH, 2, 2)]),
-    "jacobian_transposed": ("J[i][r] = x[r + 1][i] - x[0][i];",
-                            "J[r][i] = x[r + 1][i] - x[0][i];",
+    "jacobian_transposed": ("J[i][r] += x[g][i] * gdq[g * d + r];",
+                            "J[i][r] += x[g][r] * gdq[g * d + i];",
                             [lambda: pins.test_elasticity_equals_exact_assembly(2, 2, 2, pins.LAME)]),
-    "no_abs_det": ("double detJ = fabs(geometry(d, x, J, K));\n        for (int i = 0; i < nloc * ncomp; ++i)",
-                   "double detJ = geometry(d, x, J, K);\n        for (int i = 0; i < nloc * ncomp; ++i)",
+    "no_abs_det": ("double detJ = fabs(geometry(d, ng, x, gdphi + (int64_t)q * ng * d, J, K));\n            const double W = w[q] * detJ;\n            if (form == OR_MASS",
+                   "double detJ = geometry(d, ng, x, gdphi + (int64_t)q * ng * d, J, K);\n            const double W = w[q] * detJ;\n            if (form == OR_MASS",
                    [lambda: pins.test_mass_partition_of_unity(3, 2)]),
+    "curved_geometry_frozen_at_first_point": (
+        "double detJ = fabs(geometry(d, ng, x, gdphi + (int64_t)q * ng * d, J, K));\n            const double W = w[q] * detJ;\n            if (form == OR_MASS",
+        "double detJ = fabs(geometry(d, ng, x, gdphi, J, K));\n            const double W = w[q] * detJ;\n            if (form == OR_MASS",
+        [lambda: curved.test_curved_mass_moments(2, 4),
+         lambda: curved.test_curved_laplace_patch_test(2, 2)]),
     "weight_without_det": ("const double W = w[q] * detJ;\n            if (form == OR_MASS || form == OR_HELMHOLTZ)",
                            "const double W = w[q];\n            if (form == OR_MASS || form == OR_HELMHOLTZ)",
                            [lambda: pins.test_mass_partition_of_unity(2, 2)]),
