@@ -29,13 +29,21 @@ FP64_PEAK_TFLOPS = 78.6
 
 
 # ----------------------------------------------------------------------- cost model
-def flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
-    """Algorithmic FP64 flops of one cell of the plain quadrature loop (FMA = 2)."""
+def cell_geometry_flops(dim: int, nq: int, ng: int) -> float:
+    """J, det J, K = J^-1 and |det J|: once per affine cell, or at each of the nq points of
+    a curved cell from its ng geometry nodes (J = sum_g x_g (x) grad phiG_g, 2 d^2 ng)."""
     d = dim
-    if d == 2:
-        geo = 4 + 3 + 1 + 4 + 1          # J (4 sub), det (3), 1/det, K (4 mul), |det|
-    else:
-        geo = 9 + 17 + 1 + 9 * 5 + 1     # J, det by cofactors, 1/det, adjugate*inv, |det|
+    inv = 3 + 1 + 4 + 1 if d == 2 else 17 + 1 + 45 + 1
+    if ng:
+        return nq * (2 * d * d * ng + inv)
+    return (4 if d == 2 else 9) + inv
+
+
+def flops_per_cell(form: int, dim: int, nloc: int, nq: int, ng: int = 0) -> float:
+    """Algorithmic FP64 flops of one cell of the plain quadrature loop (FMA = 2); ng > 0
+    for curved cells with ng geometry nodes."""
+    d = dim
+    geo = cell_geometry_flops(d, nq, ng)
     if form == 0:                        # mass: eval 2n, weight 2, contraction 2n
         per_q = 2 * nloc + 2 + 2 * nloc
         return geo + nq * per_q
@@ -58,10 +66,10 @@ def flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
     return geo + nq * (ev + ct + geo_q + pw)
 
 
-def vjp_flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
+def vjp_flops_per_cell(form: int, dim: int, nloc: int, nq: int, ng: int = 0) -> float:
     """The tangent contracted with grad v: neo-Hookean (2) or St Venant-Kirchhoff (3)."""
     d = dim
-    geo = 4 + 3 + 1 + 4 + 1 if d == 2 else 9 + 17 + 1 + 45 + 1
+    geo = cell_geometry_flops(d, nq, ng)
     ev = 2 * (2 * d * d * nloc)          # gradients of u and v
     ct = 2 * d * d * nloc
     geo_q = 2 * (2 * d ** 3) + (2 * d ** 3 + d * d) + 1
@@ -74,9 +82,11 @@ def vjp_flops_per_cell(form: int, dim: int, nloc: int, nq: int) -> float:
     return geo + nq * (ev + ct + geo_q + pw)
 
 
-def footprint_bytes(dim, n_vert, n_cell, nloc, n_dof, vectors=2) -> float:
-    """Each DoF, coordinate and map entry counted once."""
-    return 8.0 * n_dof * vectors + 8.0 * dim * n_vert + 4.0 * nloc * n_cell + 4.0 * (dim + 1) * n_cell
+def footprint_bytes(dim, n_vert, n_cell, nloc, n_dof, vectors=2, ng=None) -> float:
+    """Each DoF, coordinate and map entry counted once (ng geometry nodes per cell: the
+    d+1 vertices unless given)."""
+    ng = dim + 1 if ng is None else ng
+    return 8.0 * n_dof * vectors + 8.0 * dim * n_vert + 4.0 * nloc * n_cell + 4.0 * ng * n_cell
 
 
 # ----------------------------------------------------------------------- timing
@@ -208,17 +218,20 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
         ms = np.array([ms])
     kernel_ms = time_kernel(plan, fn, steps)
     st = plan.strategy()
-    nv = w.mesh.n_vert
+    curved = w.mesh.cell_gnodes is not None
+    nv = w.mesh.gcoords.shape[0] if curved else w.mesh.n_vert
+    ng = w.mesh.cell_gnodes.shape[1] if curved else 0
     if vjp and w.form in (2, 3):
-        fl = vjp_flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad)
+        fl = vjp_flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad, ng)
     else:
-        fl = flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad)
+        fl = flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad, ng)
     info = dict(workload=name, vjp=vjp, cold=cold, n_cell=w.mesh.n_cell, n_dof=w.n_dof,
                 n_loc=plan.n_loc, n_quad=plan.n_quad, quad_family=plan.quad_family_name,
                 tuned=tuned,
                 flops_per_cell=fl, flops=fl * w.mesh.n_cell,
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
-                                      3 if vjp and w.form in (2, 3) else 2),
+                                      3 if vjp and w.form in (2, 3) else 2, ng or None),
+                geometry=2 if curved else 1,
                 ms_mean=float(ms.mean()), kernel_ms=kernel_ms, wall_s=wall,
                 launch={"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
                         "lanes_per_cell": st[2],
@@ -516,6 +529,11 @@ def main():
             info, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule="conical")
             extras[args.workload + "_conical"] = info
             note(f"{args.workload} conical rule: {info['ms_mean']:.4f} ms/step")
+        # curved (P2-geometry) cells: J, K and |det J| at every quadrature point
+        for name in ("nh_p4_2d_curved", "mass_p2_2d_1024_curved"):
+            info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
+            extras[name] = info
+            note(f"{name}: {info['ms_mean']:.4f} ms/step")
         for name in ("mass_p2_2d_1024", "nh_p4_2d", "elast_p2_3d"):
             info, _ = run_workload(name, args.steps, args.warmup, cold=True, tune=tune)
             extras[name + "_cold"] = info
@@ -527,11 +545,12 @@ def main():
     # the dominant kernel alone (its own HIP-event duration); the step adds the fixup
     achieved = main_info["kernel_tflops"]
     lanes, mode = main_info["launch"]["lanes_per_cell"], main_info["launch"]["sum_mode"]
+    geo = main_info["geometry"]
     if main_info["launch"]["strategy"] == "patch":
         kname = (f"patch_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {lanes}, "
-                 f"{ {'element': 1, 'coloured': 2}.get(mode, 0) }>")
+                 f"{ {'element': 1, 'coloured': 2}.get(mode, 0) }, {geo}>")
     else:
-        kname = f"colour_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false>"
+        kname = f"colour_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {geo}>"
     out = {
         "metric": "FP64 FE action DoF/s",
         "value": main_info["dof_per_s"],
