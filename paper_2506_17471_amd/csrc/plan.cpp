@@ -499,27 +499,46 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
             auto hi = node_count[nd] == 1 ? nodes.begin() + nint : nodes.end();
             return (int)(std::lower_bound(lo, hi, nd) - nodes.begin());
         };
-        pairs.clear();
+        // sub-colours: greedy first-fit over the patch's cells in Morton order; the cells are
+        // then stably sorted by colour, so that the lanes of a wavefront share one or two
+        // colours and skip the other colours' accumulation phases (the node sums still run
+        // in colour order, so the result does not depend on this permutation)
         used.assign((size_t)U, 0);
         int ncol = 0;
+        int cols[256], perm[256];
+        for (int64_t s = c0; s < c1; ++s) {
+            const int64_t c = L.order[s];
+            uint64_t forbid = 0;
+            int lids[256];
+            for (int a = 0; a < nloc; ++a) {
+                lids[a] = local(cell_nodes[c * nloc + a]);
+                forbid |= used[lids[a]];
+            }
+            if (forbid == ~uint64_t(0)) throw Error(FEM_E_UNSUPPORTED, "a patch needs more than 64 colours");
+            const int col = __builtin_ctzll(~forbid);
+            cols[s - c0] = col;
+            ncol = std::max(ncol, col + 1);
+            for (int a = 0; a < nloc; ++a) used[lids[a]] |= uint64_t(1) << col;
+        }
+        const int n_in = (int)(c1 - c0);
+        for (int i = 0; i < n_in; ++i) perm[i] = i;
+        std::stable_sort(perm, perm + n_in, [&](int x, int y) { return cols[x] < cols[y]; });
+        {
+            int64_t sorted[256];
+            for (int i = 0; i < n_in; ++i) sorted[i] = L.order[c0 + perm[i]];
+            for (int i = 0; i < n_in; ++i) L.order[c0 + i] = sorted[i];
+        }
+        pairs.clear();
         for (int64_t s = c0; s < c1; ++s) {
             const int64_t c = L.order[s];
             const int cl = (int)(s - c0);
             for (int j = 0; j < nv; ++j) L.pverts[(size_t)j * L.stride + s] = cell_verts[c * nv + j];
-            uint64_t forbid = 0;
-            int lids[256];
             for (int a = 0; a < nloc; ++a) {
                 const int l = local(cell_nodes[c * nloc + a]);
-                lids[a] = l;
                 L.lidx[(size_t)a * L.stride + s] = (uint16_t)l;
-                forbid |= used[l];
                 pairs.push_back({((int64_t)l * P + cl) * nloc + a, (a << 8) | cl});
             }
-            if (forbid == ~uint64_t(0)) throw Error(FEM_E_UNSUPPORTED, "a patch needs more than 64 colours");
-            const int col = __builtin_ctzll(~forbid);
-            L.colour[s] = (uint8_t)col;
-            ncol = std::max(ncol, col + 1);
-            for (int a = 0; a < nloc; ++a) used[lids[a]] |= uint64_t(1) << col;
+            L.colour[s] = (uint8_t)cols[perm[cl]];
         }
         L.patch_ncol[pt] = (uint8_t)ncol;
         L.max_colours = std::max(L.max_colours, ncol);
