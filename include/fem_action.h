@@ -259,9 +259,11 @@ int fem_plan_get_quadrature(const fem_plan *plan, int *family, int *n_points);
 
 /*
  * Kernel timing, a measurement aid.  With timing on, every fem_action / fem_action_vjp
- * call on the plan brackets its main kernel launches (the patch kernel, or the run of
- * colour launches) with a pair of HIP events on the caller's stream; the shared-node fixup
- * and the zeroing of untouched nodes fall outside the bracket.  fem_plan_get_timing waits
+ * call on the plan times its main kernel with a pair of HIP events on the caller's stream:
+ * for the patch strategy the events are attached to the patch kernel's dispatch
+ * (hipExtLaunchKernel), so they read the kernel's own start and end; for the colour
+ * strategy they bracket the run of colour launches.  The shared-node fixup and the zeroing
+ * of untouched nodes fall outside.  fem_plan_get_timing waits
  * for the recorded events and returns the summed milliseconds and the number of bracketed
  * calls since timing was last switched on or off (either resets both).  The events are the
  * plan's and are destroyed with it.  Errors: FEM_E_ARG, FEM_E_HIP.

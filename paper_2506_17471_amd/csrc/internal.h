@@ -170,7 +170,9 @@ hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double 
 size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes,
                        int sum_mode);
 size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode);
-hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s);
+// start / stop (optional): events the dispatch itself stamps at the kernel's start and end
+hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s,
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // the hyperelastic forms: nonlinear residuals whose VJP is a tangent action at u
 inline bool nonlinear_form(int form) { return form == FEM_NEOHOOKEAN || form == FEM_SVK; }
 // scalar forms carry one component per node, vector forms dim (host and device)

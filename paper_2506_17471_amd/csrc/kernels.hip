@@ -193,7 +193,8 @@ hipError_t launch_batch_fixup(const FixDesc *fix, int n_mesh, int64_t n, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s)
+hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s,
+                        hipEvent_t start, hipEvent_t stop)
 {
     if (p.lanes < 1 || p.lanes > 3 || (p.sum_mode != SUM_ELEMENT && p.sum_mode != SUM_COLOURED))
         return hipErrorInvalidConfiguration;
@@ -210,6 +211,14 @@ hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStre
     hipError_t e = allow_lds((const void *)fn, lds);
     if (e != hipSuccess) return e;
     if (p.n_patch > 0x7fffffff) return hipErrorInvalidConfiguration;
+    if (start || stop) {
+        // timed: the events are stamped by the dispatch at the kernel's own start and end
+        PatchArgs args = a;
+        int P = p.patch;
+        void *kargs[] = {(void *)&args, (void *)&P};
+        return hipExtLaunchKernel((const void *)fn, dim3((unsigned)p.n_patch), dim3(threads), kargs,
+                                  lds, s, start, stop, 0);
+    }
     hipLaunchKernelGGL(fn, dim3((unsigned)p.n_patch), dim3(threads), lds, s, a, p.patch);
     return hipGetLastError();
 }

@@ -124,9 +124,12 @@ std::pair<hipEvent_t, hipEvent_t> timing_pair(const fem_plan *p)
         p->timing_free.pop_back();
         return ev;
     }
+    // timing-only events: no system-scope fence (cache write-back) when they are recorded,
+    // so they read the kernel's own duration
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    femx::check_hip(hipEventCreate(&ev.first), "hipEventCreate");
-    if (hipEventCreate(&ev.second) != hipSuccess) {
+    femx::check_hip(hipEventCreateWithFlags(&ev.first, hipEventDisableSystemFence),
+                    "hipEventCreateWithFlags");
+    if (hipEventCreateWithFlags(&ev.second, hipEventDisableSystemFence) != hipSuccess) {
         (void)hipEventDestroy(ev.first);
         femx::check_hip(hipErrorOutOfMemory, "hipEventCreate");
     }
@@ -771,15 +774,9 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         a.lam = p->lam;
         a.mu = p->mu;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-        if (p->timing) {
-            ev = timing_pair(p);
-            femx::check_hip(hipEventRecord(ev.first, s), "hipEventRecord");
-        }
-        femx::check_hip(femx::launch_patch(*p, a, nl_vjp, s), "patch launch");
-        if (p->timing) {
-            femx::check_hip(hipEventRecord(ev.second, s), "hipEventRecord");
-            p->timing_pending.push_back(ev);
-        }
+        if (p->timing) ev = timing_pair(p);
+        femx::check_hip(femx::launch_patch(*p, a, nl_vjp, s, ev.first, ev.second), "patch launch");
+        if (p->timing) p->timing_pending.push_back(ev);
         if (p->n_shared > 0)
             femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off,
                                                p->n_shared, p->d_partial, p->ncomp, y, s),
