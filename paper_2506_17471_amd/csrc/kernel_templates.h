@@ -61,6 +61,10 @@ constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc, int geo 
 {
     if (lpc == 3) return 1;
     if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : 4;
+    // affine P1/P2 tetrahedra, linear elasticity: a short loop between long memory and
+    // accumulation phases, where a third wave per SIMD pays (the compiler otherwise takes
+    // 183 VGPRs; the hyperelastic forms would spill at this bound)
+    if (form == FEM_ELASTICITY && !vjp && dim == 3 && k <= 2 && geo == 1) return 3;
     // curved cells hold their geometry nodes through the loop: two waves, not three
     return (!vjp && dim == 2 && k <= 4 && !scalar_form(form)) ? (geo == 2 ? 2 : 3) : 1;
 }
