@@ -110,6 +110,22 @@ def time_steps(fn, steps: int, warmup: int):
     return start.elapsed_time(end) / steps, wall
 
 
+def median_step_ms(fn, steps: int) -> float:
+    """Median of per-step times, each step bracketed by its own pair of HIP events on the
+    current stream (the per-step events add their packets; the mean comes from time_steps)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
 def time_kernel(plan, fn, steps: int):
     """Mean duration of the plan's main kernel (the patch kernel, without the shared-node
     fixup), from HIP events the library records around that launch on the same stream."""
@@ -216,6 +232,7 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
     else:
         ms, wall = time_steps(fn, steps, warmup)
         ms = np.array([ms])
+    ms_median = float(np.median(ms)) if cold else median_step_ms(fn, steps)
     kernel_ms = time_kernel(plan, fn, steps)
     st = plan.strategy()
     curved = w.mesh.cell_gnodes is not None
@@ -232,7 +249,7 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
                                       3 if vjp and w.form in (2, 3) else 2, ng or None),
                 geometry=2 if curved else 1,
-                ms_mean=float(ms.mean()), kernel_ms=kernel_ms, wall_s=wall,
+                ms_mean=float(ms.mean()), ms_median=ms_median, kernel_ms=kernel_ms, wall_s=wall,
                 launch={"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
                         "lanes_per_cell": st[2],
                         "sum_mode": {1: "element", 2: "coloured"}.get(st[3], "-")})
@@ -246,6 +263,34 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
     info["kernel_hbm_frac_footprint"] = info["bytes"] / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS
     del plan
     return info, w
+
+
+def run_autograd(name: str, steps: int, warmup: int) -> dict:
+    """Forward plus backward through the torch.autograd.Function (y = A(u), then
+    (dA/du)^T v as the backward of <y, v>) against the raw forward and VJP calls on the same
+    plan (default launch configuration): the cost of the autograd path itself."""
+    import torch
+    import meshgen
+    import paper_2506_17471_amd as fx
+    w = meshgen.workload(name, with_v=True)
+    plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
+    u = torch.as_tensor(w.u, device="cuda")
+    v = torch.as_tensor(w.v, device="cuda")
+    y, g = torch.empty_like(u), torch.empty_like(u)
+    raw_ms, _ = time_steps(lambda: (plan.action(u, out=y), plan.vjp(u, v, out=g)), steps, warmup)
+    ug = u.clone().requires_grad_(True)
+
+    def step():
+        ug.grad = None
+        fx.FemAction.apply(ug, plan).backward(v)
+
+    ag_ms, _ = time_steps(step, steps, warmup)
+    torch.cuda.synchronize()
+    ref = plan.vjp(u, v)
+    same = bool(torch.equal(ug.grad, ref))
+    del plan
+    return {"workload": name, "raw_forward_plus_vjp_ms": raw_ms, "autograd_forward_backward_ms": ag_ms,
+            "autograd_overhead": ag_ms / raw_ms, "autograd_grad_equals_raw_vjp": same}
 
 
 def run_batch(steps: int, warmup: int, tune: bool = True, n_mesh: int = 64):
@@ -512,6 +557,8 @@ def main():
         extras["vjp"] = vinfo
         extras["adjoint_forward_time_ratio"] = vinfo["ms_mean"] / main_info["ms_mean"]
         note(f"vjp: {vinfo['ms_mean']:.4f} ms/step")
+        extras["autograd"] = run_autograd(args.workload, args.steps, args.warmup)
+        note(f"autograd: {extras['autograd']}")
     if args.all:
         for name in ("mass_p2_2d", "mass_p2_2d_1024", "elast_p2_3d"):
             info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
@@ -559,6 +606,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": main_info["ms_mean"],
+        "ms_per_step_median": main_info["ms_median"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

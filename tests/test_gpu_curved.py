@@ -111,3 +111,30 @@ def test_curved_set_quadrature_and_straight_geometry():
     y = pc2.action(gpu(u)).cpu().numpy()
     ref = oracle.action(fx.FORM_NEOHOOKEAN, mc, u, 6, NH, family="conical")
     assert rel_err(y, ref)[0] < TOL
+
+
+def test_curved_autograd_function_and_tuner():
+    # the autograd Function's backward is the VJP on curved cells too; a tuned plan keeps
+    # parity and its timing reports one call per action
+    m = meshgen.curved(meshgen.make_mesh(2, 16, 4, None, np.random.default_rng(8)), 0.08)
+    u0, v = inputs(fx.FORM_NEOHOOKEAN, m, 12)
+    plan = fx.Plan.from_mesh(fx.FORM_NEOHOOKEAN, m, 8, NH)
+    u = gpu(u0).requires_grad_(True)
+    y = fx.FemAction.apply(u, plan)
+    (y * gpu(v)).sum().backward()
+    fam = plan.quad_family_name
+    ref = oracle.vjp(fx.FORM_NEOHOOKEAN, m, u0, v, 8, NH, family=fam)
+    assert rel_err(u.grad.cpu().numpy(), ref)[0] < TOL
+    yref = oracle.action(fx.FORM_NEOHOOKEAN, m, u0, 8, NH, family=fam)
+    assert rel_err(y.detach().cpu().numpy(), yref)[0] < TOL
+    ud = gpu(u0)
+    out = torch.empty_like(ud)
+    plan.tune(ud, y=out)
+    assert plan.strategy()[2] == 1
+    plan.set_timing(True)
+    for _ in range(3):
+        plan.action(ud, out=out)
+    ms, n = plan.timing()
+    plan.set_timing(False)
+    assert n == 3 and ms > 0
+    assert rel_err(out.cpu().numpy(), yref)[0] < TOL
