@@ -2,12 +2,13 @@
  * femx -- matrix-free finite element actions on AMD Instinct MI355X (gfx950), FP64.
  *
  * C ABI of the library.  The operation is the matrix-free action of a finite element
- * operator on affine simplex meshes (paper Sec. 2.2, the action written as a sum of cell
+ * operator on affine simplex meshes, or on curved cells with a P2 geometry
+ * (fem_plan_create_curved, paper Sec. 2.4) (paper Sec. 2.2, the action written as a sum of cell
  * integrals through the local-to-global maps and the reference-cell substitution, then
  * replaced by quadrature; Sec. 2.3, the generic action kernel: gather, Jacobian and
  * determinant, evaluation at quadrature points, pointwise form, quadrature contraction,
- * scatter-add).  Forms follow App. A: mass, linear elasticity, and the hyperelastic
- * residual with a compressible neo-Hookean energy.
+ * scatter-add).  Forms follow App. A: mass, Laplace, Helmholtz, linear elasticity, and the
+ * hyperelastic residual with a compressible neo-Hookean or St Venant-Kirchhoff energy.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -15,20 +16,22 @@
  *   xi = alpha/k, |alpha| <= k.  Local node order (the columns of cell_nodes): first
  *   coordinate fastest, i.e. 2D  for j in 0..k: for i in 0..k-j: (i, j);
  *   3D  for l: for j: for i (i + j + l <= k).  n_loc = C(k + d, d).
- * - Geometry is affine: J = [x_1 - x_0 | ... | x_d - x_0] from the cell's vertices in
- *   cell_verts order; integrals use |det J| (cells with det J < 0 in 3D are valid).
+ * - Geometry (fem_plan_create) is affine: J = [x_1 - x_0 | ... | x_d - x_0] from the
+ *   cell's vertices in cell_verts order; integrals use |det J| (cells with det J < 0 in 3D
+ *   are valid).  Curved plans evaluate J at every quadrature point instead.
  * - Quadrature: a rule exact to quad_degree on the reference simplex, from one of two
  *   families: FEM_QUAD_CONICAL, the conical-product (collapsed Gauss-Jacobi) rule with
  *   ceil((quad_degree + 1)/2) points per direction (any degree); FEM_QUAD_SYMMETRIC, fully
  *   symmetric rules (points on orbits of the simplex's symmetry group, one weight per
  *   orbit, positive weights, points inside), each an isolated root of its moment
- *   equations solved by Newton's method at plan creation: triangles of degree <= 2, 4, 6,
+ *   equations solved by Gauss-Newton iteration at plan creation: triangles of degree <= 2, 4, 6,
  *   8, 10, 12 (1, 3, 6, 12, 16, 25, 33 points), tetrahedra of degree <= 2, 5, 6, 8 (1, 4,
  *   14, 24, 50 points);
  *   a degree without its own rule takes the next tabulated one.  A plan uses the
  *   symmetric rule when one is built for its degree, else the conical rule
- *   (fem_plan_set_quadrature switches).  The mass and elasticity operators do not depend
- *   on the rule (polynomial integrands); the neo-Hookean operator does.
+ *   (fem_plan_set_quadrature switches).  On affine cells the linear forms' operators do
+ *   not depend on the rule once it integrates their polynomial integrands exactly; the
+ *   hyperelastic operators, and every form on curved cells, do.
  * - Vectors are node-major interleaved: component c of node n at index n * ncomp + c,
  *   ncomp = 1 for the scalar forms (mass, Laplace, Helmholtz) and d for the vector forms
  *   (elasticity, neo-Hookean, St Venant-Kirchhoff).
@@ -239,9 +242,8 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *                   buffer colour by colour (smaller LDS, one barrier per colour).
  *   0 for lanes_per_cell, patch_cells or sum_mode picks the plan's default (three lanes
  *   for 3D vector forms of degree >= 3 when the patch size allows it, one otherwise;
- *   coloured sums in 2D and in 3D from degree 3 on, the element buffer for P1/P2
- *   tetrahedra; 42 cells for lane triples with coloured sums, else the largest patch whose
- *   element buffer fits 64 KB).
+ *   coloured sums; 42 cells for lane triples, else the largest patch whose element buffer
+ *   would fit 64 KB).
  * Rebuilding patches synchronises the device.  Errors: FEM_E_ARG, FEM_E_UNSUPPORTED (a lane
  * split the form lacks, or more than 160 KB of LDS), FEM_E_HIP, FEM_E_NOMEM.
  */

@@ -682,12 +682,13 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
     }
 }
 
-// Sub-colour phases pay one barrier and one masked pass per colour: cheap next to the
-// quadrature work of the 2D forms (about 7 colours) and of 3D cells from P3 on, not next to
-// P1/P2 tetrahedra (about 24 colours), which sum through the element buffer.
-int default_sum_mode(const fem_plan *p)
+// Coloured sums everywhere: with the patch's cells sorted by colour a wavefront runs the
+// adds of one or two colours only, and the smaller LDS need keeps more workgroups resident;
+// measured faster than the element buffer on every 2D case and on P1/P2 tetrahedra for
+// all six forms (about 24 colours there).
+int default_sum_mode(const fem_plan *)
 {
-    return (p->dim == 2 || p->degree >= 3) ? femx::SUM_COLOURED : femx::SUM_ELEMENT;
+    return femx::SUM_COLOURED;
 }
 
 // One lane per cell in 2D: with coloured sums the lane-pair split no longer pays for its
