@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the FP64 matrix-free action on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--all] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--all] [--no-batch] [--no-cpu-baseline]
 
 A step is one full action y = A(u) (gather, geometry, evaluation, pointwise form,
 quadrature, colour-ordered scatter) over the whole mesh, inputs resident in HBM.  The
@@ -505,7 +505,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="nh_p4_2d")
     ap.add_argument("--all", action="store_true", help="also time the other workloads and the batch")
-    ap.add_argument("--batch", action="store_true", help="also time the 64-mesh batch")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-mesh batch (timed by default: the batched speedup)")
+    ap.add_argument("--batch", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-tune", action="store_true", help="use the plans' default launch configuration")
     ap.add_argument("--rule", choices=["default", "conical", "symmetric"], default="default",
                     help="quadrature rule family of the timed workload (default: the plan's)")
@@ -559,8 +561,13 @@ def main():
         note(f"vjp: {vinfo['ms_mean']:.4f} ms/step")
         extras["autograd"] = run_autograd(args.workload, args.steps, args.warmup)
         note(f"autograd: {extras['autograd']}")
+    # the memory-bound form at a size where HBM, not launch latency, binds: its fraction of
+    # the HBM roofline (footprint bytes / time against 8 TB/s)
+    minfo, _ = run_workload("mass_p2_2d_1024", args.steps, args.warmup, tune=tune)
+    extras["mass_p2_2d_1024"] = minfo
+    note(f"mass_p2_2d_1024: {minfo['ms_mean']:.4f} ms/step")
     if args.all:
-        for name in ("mass_p2_2d", "mass_p2_2d_1024", "elast_p2_3d"):
+        for name in ("mass_p2_2d", "elast_p2_3d"):
             info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
             extras[name] = info
             note(f"{name}: {info['ms_mean']:.4f} ms/step")
@@ -585,7 +592,7 @@ def main():
             info, _ = run_workload(name, args.steps, args.warmup, cold=True, tune=tune)
             extras[name + "_cold"] = info
             note(f"{name} cold: {info['ms_mean']:.4f} ms/step")
-    if args.all or args.batch:
+    if not args.no_batch:
         extras["batch"] = run_batch(args.steps, args.warmup, tune=tune)
         note(f"batch: {extras['batch']}")
 
@@ -599,7 +606,7 @@ def main():
     else:
         kname = f"colour_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {geo}>"
     out = {
-        "metric": "FP64 FE action DoF/s",
+        "metric": "FP64 FE action DoF/s + % HBM roofline; adjoint/forward time ratio; batched speedup",
         "value": main_info["dof_per_s"],
         "unit": "DoF/s",
         "n_gpus": 1,
@@ -625,6 +632,19 @@ def main():
                      "avg_step_ms": main_info["ms_mean"],
                      "step_tflops": main_info["tflops"],
                      "footprint_gbs": main_info["hbm_gbs_footprint"]},
+        # the metric's other parts on this run: the fraction of the HBM roofline (footprint
+        # bytes per step against 8 TB/s) of the headline and of the memory-bound mass form,
+        # the adjoint/forward time ratio and the batched speedup
+        "summary": {
+            "dof_per_s": main_info["dof_per_s"],
+            "hbm_roofline_frac": {
+                args.workload: main_info["hbm_frac_footprint"],
+                "mass_p2_2d_1024": minfo["hbm_frac_footprint"],
+                "mass_p2_2d_1024_kernel": minfo["kernel_hbm_frac_footprint"],
+            },
+            "adjoint_forward_time_ratio": extras.get("adjoint_forward_time_ratio"),
+            "batched_speedup": extras["batch"]["speedup_vs_per_mesh"] if "batch" in extras else None,
+        },
         "extras": extras,
     }
     if not args.no_cpu_baseline:
