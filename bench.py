@@ -456,7 +456,13 @@ def spearman(a, b) -> float:
     return float((ra @ rb) / math.sqrt((ra @ ra) * (rb @ rb)))
 
 
-def run_model_eval(tri_cells: float = 5e5, tet_cells: float = 2e5):
+# cases the model's constants were set on, and held-out cases never looked at while setting them
+MODEL_CASES = [(f, 2, k) for f in (0, 1, 2, 4) for k in (2, 4)] + [(f, 3, 2) for f in (0, 1, 2, 4)]
+MODEL_HOLDOUT = [(0, 2, 3), (1, 2, 3), (3, 2, 3), (5, 2, 5), (2, 2, 5), (4, 3, 1), (1, 3, 1),
+                 (5, 3, 2), (3, 3, 2), (1, 3, 3), (0, 3, 4)]
+
+
+def run_model_eval(tri_cells: float = 5e5, tet_cells: float = 2e5, cases=None):
     """The tuner's cost model against the tuner's own measurements (the paper's evaluation
     of its heuristic model): per case the Spearman rank correlation between predicted and
     measured candidate times, and the top-k regret -- the throughput of the best measured
@@ -465,7 +471,7 @@ def run_model_eval(tri_cells: float = 5e5, tet_cells: float = 2e5):
     import meshgen
     import paper_2506_17471_amd as fx
 
-    cases = [(f, 2, k) for f in (0, 1, 2, 4) for k in (2, 4)] + [(f, 3, 2) for f in (0, 1, 2, 4)]
+    cases = MODEL_CASES if cases is None else cases
     out = []
     for form, dim, k in cases:
         rng = np.random.default_rng(7 * dim + k)
@@ -516,6 +522,8 @@ def main():
                     help="only run the degree sweep over every built (form, dim, degree)")
     ap.add_argument("--model-eval", action="store_true",
                     help="only evaluate the tuner's cost model against measured candidates")
+    ap.add_argument("--holdout", action="store_true",
+                    help="with --model-eval: the held-out cases instead of the calibration cases")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
@@ -544,7 +552,7 @@ def main():
         print(json.dumps({"sweep": run_sweep(args.steps, args.warmup)}))
         return
     if args.model_eval:
-        print(json.dumps({"model_eval": run_model_eval()}))
+        print(json.dumps({"model_eval": run_model_eval(cases=MODEL_HOLDOUT if args.holdout else None)}))
         return
 
     def note(msg):

@@ -200,8 +200,9 @@ double flops_per_point(int form, int d, int nloc, bool vjp)
 //   VALU time: FP64 instructions (work / 2, plus what a lane split repeats) at 16 lanes
 //     per SIMD per cycle over 1024 SIMDs, derated when fewer than three waves per SIMD
 //     (set by registers and, for patches, by LDS) are there to hide latency;
-//   memory time: the footprint plus the partial sums of shared nodes (patches) or the
-//     uncoalesced read-add-write scatter (colours) at 4 TB/s;
+//   memory time: the footprint plus the partial sums of shared nodes (patches; plus the slot
+//     lists of the element buffer) or the uncoalesced read-add-write scatter (colours) at
+//     4 TB/s, derated below six resident waves per SIMD;
 //   synchronisation: per workgroup round one barrier per sub-colour (coloured sums) or
 //     three (element buffer), and one launch per colour for the colour strategy.
 double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
@@ -213,8 +214,11 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
     // curved cells: J from the geometry gradients and its inverse at every point
     const int ng = cell_geom_nodes(p->dim, p->geom);
     if (p->geom == 2) instr += (2.0 * d * d * ng + (p->dim == 2 ? 12 : 60)) * p->nq / 2.0 * 1.25;
-    if (c.lanes == 2) instr *= 1.35;                      // pointwise form on both lanes
-    if (c.lanes == 3) instr *= 1.2;                       // shuffles of the gradient rows
+    // lane splits repeat the pointwise form on every lane of a cell and exchange gradient
+    // rows: cheap for elasticity, costly for the hyperelastic forms (inverse, log, stress)
+    const bool hyper = nonlinear_form(p->form);
+    if (c.lanes == 2) instr *= hyper ? 1.6 : 1.35;
+    if (c.lanes == 3) instr *= hyper ? 2.5 : 1.2;
     const int regs = kernel_registers(p->form, p->dim, p->degree, nl,
                                       c.strategy == FEM_SCATTER_COLOUR, c.lanes,
                                       c.strategy == FEM_SCATTER_COLOUR ? 1 : c.sum_mode, p->geom);
@@ -231,8 +235,12 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
         waves = std::min(waves, wgs_lds * wave_per_wg / 4.0);
         const double wg_per_cu = std::max(1.0, waves * 4.0 / wave_per_wg);
         rounds_sync = std::ceil(n / P / (256.0 * wg_per_cu));
-        barriers = c.sum_mode == SUM_COLOURED ? (d == 2 ? 7 : 24) + 3 : 3;
-        extra_bytes = 2.0 * share * vec_bytes * (vjp ? 1.0 : 1.0) * 2.0;
+        // coloured: one barrier per sub-colour (a wavefront skips the other colours' adds);
+        // element buffer: three, plus the buffer's write and slot-ordered read passes
+        barriers = c.sum_mode == SUM_COLOURED ? (d == 2 ? 7 : 24) + 3 : 5;
+        extra_bytes = 2.0 * share * vec_bytes * 2.0;
+        // the element buffer's slot lists: a u16 per (cell, local node), an offset per node
+        if (c.sum_mode == SUM_ELEMENT) extra_bytes += 2.0 * nloc * n + 4.0 * p->n_node * (1.0 + share);
     } else {
         extra_bytes = 2.0 * n * nloc * nc * 8.0;          // gathers and read-add-writes
     }
@@ -240,7 +248,9 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
     const double t_valu = n * instr * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
     const double bytes = vec_bytes * (nl ? 3 : 2) + 8.0 * d * p->n_vert +
                          4.0 * (nloc + ng) * n + extra_bytes;
-    const double t_mem = bytes / 4.0e12;
+    // memory-level parallelism: fewer than six resident waves per SIMD (an LDS-hungry
+    // patch) leave HBM requests unissued
+    const double t_mem = bytes / (4.0e12 * std::min(1.0, waves / 6.0));
     double t = std::max(t_valu, t_mem) + rounds_sync * barriers * 0.4e-6;
     if (c.strategy == FEM_SCATTER_COLOUR) t += p->n_colours * 4.0e-6;
     else t += 4.0e-6;                                     // the fixup launch
