@@ -3,6 +3,9 @@
 // workgroups walk all patches of all its meshes through a device table of per-mesh
 // arguments, and one more launch sums the shared nodes of every mesh.  The sequence is
 // captured once into a HIP graph on a private stream and replayed on the caller's stream.
+// In the graph the groups are parallel branches (they write disjoint meshes), so a
+// memory-bound group's launch overlaps a compute-bound one's and each fills the others' tail;
+// the fixup and the zeroing of untouched nodes join after all of them.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -33,6 +36,8 @@ struct fem_batch {
     int64_t n_fix = 0;
     std::vector<double *> y;              // each mesh's output vector
     hipStream_t capture = nullptr;
+    std::vector<hipStream_t> branch;      // one per group after the first (graph capture)
+    std::vector<hipEvent_t> branch_ev;    // fork event, then one join event per branch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -106,6 +111,8 @@ void free_batch(fem_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (hipStream_t t : b->branch) (void)hipStreamDestroy(t);
+    for (hipEvent_t e : b->branch_ev) (void)hipEventDestroy(e);
     for (auto &g : b->groups) {
         (void)hipFree(g.d_desc);
         (void)hipFree(g.d_patch_mesh);
@@ -147,13 +154,32 @@ void set_vectors(fem_batch *b, const double *const *u, double *const *y)
     b->y.assign(y, y + n);
 }
 
-void enqueue(fem_batch *b, hipStream_t s)
+void launch_group(const fem_batch::Group &g, hipStream_t s)
 {
-    for (auto &g : b->groups)
-        femx::check_hip(femx::launch_batch_patch(g.form, g.dim, g.degree, g.lanes, g.patch,
-                                                 g.sum_mode, g.d_desc, g.d_patch_mesh, g.n_patch,
-                                                 g.lds, s),
-                        "batched patch launch");
+    femx::check_hip(femx::launch_batch_patch(g.form, g.dim, g.degree, g.lanes, g.patch,
+                                             g.sum_mode, g.d_desc, g.d_patch_mesh, g.n_patch,
+                                             g.lds, s),
+                    "batched patch launch");
+}
+
+// parallel: groups after the first on the branch streams, forked from and joined back to s
+// by events (used while capturing the graph, where this becomes parallel graph branches)
+void enqueue(fem_batch *b, hipStream_t s, bool parallel = false)
+{
+    const size_t ng = b->groups.size();
+    if (parallel && ng > 1) {
+        femx::check_hip(hipEventRecord(b->branch_ev[0], s), "fork event");
+        for (size_t i = 1; i < ng; ++i) {
+            femx::check_hip(hipStreamWaitEvent(b->branch[i - 1], b->branch_ev[0], 0), "fork wait");
+            launch_group(b->groups[i], b->branch[i - 1]);
+            femx::check_hip(hipEventRecord(b->branch_ev[i], b->branch[i - 1]), "join event");
+        }
+        launch_group(b->groups[0], s);
+        for (size_t i = 1; i < ng; ++i)
+            femx::check_hip(hipStreamWaitEvent(s, b->branch_ev[i], 0), "join wait");
+    } else {
+        for (auto &g : b->groups) launch_group(g, s);
+    }
     if (b->n_fix > 0)
         femx::check_hip(femx::launch_batch_fixup(b->d_fix, (int)b->fix.size(), b->n_fix, s),
                         "batched fixup launch");
@@ -261,6 +287,17 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
         b->d_fix = upload(b->fix, "batch fixup descriptors");
         femx::check_hip(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking),
                         "capture stream");
+        // branch streams (default priority) and their fork / join events for the graph
+        for (size_t i = 1; i < b->groups.size(); ++i) {
+            hipStream_t t = nullptr;
+            femx::check_hip(hipStreamCreateWithFlags(&t, hipStreamNonBlocking), "branch stream");
+            b->branch.push_back(t);
+        }
+        for (size_t i = 0; i < b->groups.size(); ++i) {
+            hipEvent_t e = nullptr;
+            femx::check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "branch event");
+            b->branch_ev.push_back(e);
+        }
         set_vectors(b, u, y);
     });
     if (st != FEM_OK) {
@@ -297,7 +334,7 @@ int fem_batch_run(fem_batch *batch, void *stream, int use_graph)
             femx::check_hip(hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal),
                             "hipStreamBeginCapture");
             try {
-                enqueue(batch, batch->capture);
+                enqueue(batch, batch->capture, true);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(batch->capture, &g);

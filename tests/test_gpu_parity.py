@@ -399,7 +399,7 @@ def test_batch_matches_oracle_and_per_mesh():
     ys = [torch.full_like(u, 3.0) for u in us]
     b = fx.Batch(plans, us, ys)
     assert b.n_groups == 3
-    for graph in (False, True, True):
+    for graph in (False, True, True, True):
         for y in ys:
             y.fill_(3.0)
         b.run(graph=graph)
