@@ -214,6 +214,8 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
                 if (plans[j] == p) throw Error(FEM_E_ARG, "a plan appears twice in the batch");
             if (p->geom != 1)
                 throw Error(FEM_E_UNSUPPORTED, "batches take plans of affine cells only");
+            if (p->n_cell > 0 && !femx::batch_available(p->form, p->dim, p->degree, 1, femx::SUM_COLOURED))
+                throw Error(FEM_E_UNSUPPORTED, "batch kernels are built up to P6 (2D) / P4 (3D)");
             if (p->n_cell > 0 && (p->strategy != femx::STRAT_PATCH || p->patch == 0))
                 femx::set_strategy(p, FEM_SCATTER_PATCH, 0, 0, 0);
             b->plans.push_back(p);

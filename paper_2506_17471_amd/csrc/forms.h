@@ -600,7 +600,7 @@ __device__ __forceinline__ void cell_quadrature_pair(
         }
         // rows of the reference gradient: this lane's row c and the partner's row 1 - c
         const double o0 = pair_swap(g0), o1 = pair_swap(g1);
-        double gu[2][2], G[2][2], S[2][2], T[2][2];
+        double gu[2][2], G[2][2], H[2][2], S[2][2], T[2][2];
         gu[0][0] = odd ? o0 : g0;
         gu[0][1] = odd ? o1 : g1;
         gu[1][0] = odd ? g0 : o0;
@@ -608,18 +608,14 @@ __device__ __forceinline__ void cell_quadrature_pair(
         to_physical<2>(gu, Kinv, G);
         if constexpr (VJP) {
             const double p0 = pair_swap(h0), p1 = pair_swap(h1);
-            double gv[2][2], H[2][2];
+            double gv[2][2];
             gv[0][0] = odd ? p0 : h0;
             gv[0][1] = odd ? p1 : h1;
             gv[1][0] = odd ? h0 : p0;
             gv[1][1] = odd ? h1 : p1;
             to_physical<2>(gv, Kinv, H);
-            tangent_neohookean<2>(G, H, lam, mu, S);
-        } else if constexpr (FORM == FEM_ELASTICITY) {
-            stress_elasticity<2>(G, lam, mu, S);
-        } else {
-            stress_neohookean<2>(G, lam, mu, S);
         }
+        pointwise<FORM, 2, VJP>(G, H, lam, mu, S);
         pull_back<2>(S, Kinv, t[2 * NLOC] * adet, T);
         const double t0 = odd ? T[1][0] : T[0][0];
         const double t1 = odd ? T[1][1] : T[0][1];

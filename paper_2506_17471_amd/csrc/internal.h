@@ -182,6 +182,8 @@ constexpr bool scalar_form(int form)
 }
 constexpr int ncomp_of(int form, int dim) { return scalar_form(form) ? 1 : dim; }
 bool pair_available(int form, int dim, int degree);
+bool curved_available(int form, int dim, int degree);
+bool batch_available(int form, int dim, int degree, int lanes, int sum_mode);
 bool triple_available(int form, int dim, int degree);
 int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int lanes,
                      int sum_mode, int geom = 1);

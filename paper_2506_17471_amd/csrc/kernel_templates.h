@@ -60,7 +60,7 @@ namespace {
 constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc, int geo = 1)
 {
     if (lpc == 3) return 1;
-    if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : 4;
+    if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : (k <= 6 ? 4 : 1);
     // affine P1/P2 tetrahedra, linear elasticity: a short loop between long memory and
     // accumulation phases, where a third wave per SIMD pays (the compiler otherwise takes
     // 183 VGPRs; the hyperelastic forms would spill at this bound)
@@ -417,26 +417,35 @@ __global__ void __launch_bounds__(kMaxBlock)
     patch_body<FORM, DIM, K, VJP, LPC, SUM, 1>(d.args, b - d.first_patch, P);
 }
 
-template <int FORM, int DIM, int K, bool VJP, int LPC>
+template <int FORM, int DIM, int K, bool VJP, int LPC, bool BATCH>
 void fill_lanes(Kernels &k)
 {
     k.patch[LPC][SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT, 1>;
     k.patch[LPC][SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED, 1>;
-    k.batch[LPC][SUM_ELEMENT] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
-    k.batch[LPC][SUM_COLOURED] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+    if constexpr (BATCH) {
+        k.batch[LPC][SUM_ELEMENT] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
+        k.batch[LPC][SUM_COLOURED] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+    }
 }
+
+// Degrees up to P6 (2D) / P4 (3D) get every variant; the higher ones (the rest of the
+// degree sweep) the single-mesh kernels on affine cells only: no batch, no P2 geometry.
+constexpr bool full_set(int dim, int k) { return dim == 2 ? k <= 6 : k <= 4; }
 
 template <int FORM, int DIM, int K, bool VJP>
 Kernels entry()
 {
+    constexpr bool FULL = full_set(DIM, K);
     Kernels k{};
     k.colour = colour_kernel<FORM, DIM, K, VJP, 1>;
-    fill_lanes<FORM, DIM, K, VJP, 1>(k);
-    k.colour_p2 = colour_kernel<FORM, DIM, K, VJP, 2>;
-    k.patch_p2[SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_ELEMENT, 2>;
-    k.patch_p2[SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_COLOURED, 2>;
-    if constexpr (DIM == 2 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 2>(k);
-    if constexpr (DIM == 3 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 3>(k);
+    fill_lanes<FORM, DIM, K, VJP, 1, FULL>(k);
+    if constexpr (FULL) {
+        k.colour_p2 = colour_kernel<FORM, DIM, K, VJP, 2>;
+        k.patch_p2[SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_ELEMENT, 2>;
+        k.patch_p2[SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_COLOURED, 2>;
+    }
+    if constexpr (DIM == 2 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 2, FULL>(k);
+    if constexpr (DIM == 3 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 3, FULL>(k);
     return k;
 }
 
@@ -461,6 +470,8 @@ Kernels lookup_form(int dim, int degree, bool vjp)
         case 4: return pick<FORM, 2, 4>(vjp);
         case 5: return pick<FORM, 2, 5>(vjp);
         case 6: return pick<FORM, 2, 6>(vjp);
+        case 7: return pick<FORM, 2, 7>(vjp);
+        case 8: return pick<FORM, 2, 8>(vjp);
         default: break;
         }
     } else if (dim == 3) {
@@ -469,6 +480,7 @@ Kernels lookup_form(int dim, int degree, bool vjp)
         case 2: return pick<FORM, 3, 2>(vjp);
         case 3: return pick<FORM, 3, 3>(vjp);
         case 4: return pick<FORM, 3, 4>(vjp);
+        case 5: return pick<FORM, 3, 5>(vjp);
         default: break;
         }
     }

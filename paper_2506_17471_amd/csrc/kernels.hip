@@ -117,6 +117,18 @@ size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int m
            ((b + 7) & ~(size_t)7);
 }
 
+// curved (P2-geometry) and batch kernels exist up to P6 (2D) / P4 (3D)
+bool curved_available(int form, int dim, int degree)
+{
+    return lookup(form, dim, degree, false).colour_p2 != nullptr;
+}
+
+bool batch_available(int form, int dim, int degree, int lanes, int sum_mode)
+{
+    if (lanes < 1 || lanes > 3 || sum_mode < 1 || sum_mode > 2) return false;
+    return lookup(form, dim, degree, false).batch[lanes][sum_mode] != nullptr;
+}
+
 bool pair_available(int form, int dim, int degree)
 {
     return lookup(form, dim, degree, false).patch[2][SUM_ELEMENT] != nullptr;

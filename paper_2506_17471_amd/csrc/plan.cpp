@@ -698,6 +698,9 @@ int default_lanes(const fem_plan *p)
 {
     if (p->geom == 2) return 1;    // curved cells: one-lane kernels only
     if (femx::triple_available(p->form, p->dim, p->degree) && p->degree >= 3) return 3;
+    // 2D vector forms from P7 on: a lane's half of the cell (one component) still fits its
+    // registers, the whole cell spills
+    if (femx::pair_available(p->form, p->dim, p->degree) && p->degree >= 7) return 2;
     return 1;
 }
 
@@ -897,9 +900,13 @@ int create_plan(fem_plan **out, int form, int dim, int degree, int quad_degree, 
         if (!out) throw Error(FEM_E_ARG, "null output pointer");
         if (form < FEM_MASS || form > FEM_HELMHOLTZ) throw Error(FEM_E_UNSUPPORTED, "unknown form");
         if (dim != 2 && dim != 3) throw Error(FEM_E_UNSUPPORTED, "dim must be 2 or 3");
-        if (degree < 1 || degree > (dim == 2 ? 6 : 4) || !femx::kernel_available(form, dim, degree))
+        if (degree < 1 || degree > (dim == 2 ? 8 : 5) || !femx::kernel_available(form, dim, degree))
             throw Error(FEM_E_UNSUPPORTED, "degree " + std::to_string(degree) + " not built for dim " +
                                                std::to_string(dim));
+        if (geom == 2 && !femx::curved_available(form, dim, degree))
+            throw Error(FEM_E_UNSUPPORTED, "curved cells are built up to degree " +
+                                               std::string(dim == 2 ? "6" : "4") + " in " +
+                                               std::to_string(dim) + "D");
         if (quad_degree < 0 || quad_degree > 20) throw Error(FEM_E_UNSUPPORTED, "quad_degree must be 0..20");
         if (n_vert < 0 || n_cell < 0 || n_node < 0) throw Error(FEM_E_ARG, "negative size");
         if (n_node > INT32_MAX || n_vert > INT32_MAX) throw Error(FEM_E_ARG, "more than 2^31 nodes");

@@ -83,13 +83,19 @@ def plan_family(w):
 
 STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_ELEMENT),
           (fx.SCATTER_PATCH, 128, 1, fx.SUM_COLOURED), (fx.SCATTER_COLOUR, 0, 0, 0),
-          (fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 63, 3, fx.SUM_COLOURED)]
-STRAT_IDS = ["patch", "patch64x1e", "patch128x1c", "colour", "patch42x3e", "patch63x3c"]
+          (fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 63, 3, fx.SUM_COLOURED),
+          (fx.SCATTER_PATCH, 64, 2, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 128, 2, fx.SUM_COLOURED)]
+STRAT_IDS = ["patch", "patch64x1e", "patch128x1c", "colour", "patch42x3e", "patch63x3c",
+             "patch64x2e", "patch128x2c"]
 
 
 def apply_strategy(plan, strategy, form, dim):
     if strategy[2] == 3 and (dim != 3 or form in fx.SCALAR_FORMS):
         pytest.skip("three lanes per cell exist for the 3D vector forms only")
+    if strategy[2] == 2 and (dim != 2 or form in fx.SCALAR_FORMS):
+        pytest.skip("two lanes per cell exist for the 2D vector forms only")
+    if strategy[2] > 1 and getattr(plan, "geometry", 1) == 2:
+        pytest.skip("curved cells run one lane per cell")
     plan.set_strategy(*strategy)
 
 
@@ -124,6 +130,34 @@ def test_vjp_small_meshes(form, dim, k, strategy):
     ref = oracle.vjp(form, mesh, u, v, qd, params_for(form), family=plan.quad_family_name)
     emax, el2 = rel_err(g, ref)
     assert emax < TOL and el2 < TOL, (emax, el2)
+
+
+HIGH = [(f, 2, k) for f in range(6) for k in (7, 8)] + [(f, 3, 5) for f in range(6)]
+HIGH_STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_COLOURED),
+               (fx.SCATTER_PATCH, 64, 0, fx.SUM_ELEMENT), (fx.SCATTER_COLOUR, 0, 0, 0)]
+
+
+@pytest.mark.parametrize("strategy", HIGH_STRATS, ids=["patch", "patch64x1c", "patch64e", "colour"])
+@pytest.mark.parametrize("form,dim,k", HIGH)
+def test_high_degrees(form, dim, k, strategy):
+    # the rest of the degree sweep (2D P7, P8; 3D P5): action and VJP, several patches and a
+    # ragged tail (2D n=6: 72 cells; 3D n=2: 48 cells)
+    n = 6 if dim == 2 else 2
+    mesh = meshgen.make_mesh(dim, n, k, None, np.random.default_rng(400 + k))
+    u, v = inputs(form, mesh, 90 + k)
+    qd = qdeg(form, k)
+    say(f"[high] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd} strat={strategy}")
+    plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    apply_strategy(plan, strategy, form, dim)
+    fam = plan.quad_family_name
+    y = plan.action(gpu(u)).cpu().numpy()
+    ref = oracle.action(form, mesh, u, qd, params_for(form), family=fam)
+    emax, el2 = rel_err(y, ref)
+    assert emax < TOL and el2 < TOL, ("action", emax, el2)
+    g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
+    gref = oracle.vjp(form, mesh, u, v, qd, params_for(form), family=fam)
+    emax, el2 = rel_err(g, gref)
+    assert emax < TOL and el2 < TOL, ("vjp", emax, el2)
 
 
 @pytest.mark.parametrize("name", ["mass_p2_2d", "nh_p4_2d", "elast_p2_3d"])
@@ -271,8 +305,9 @@ _ref_cache = {}
 
 
 @pytest.mark.parametrize("strategy", [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 128, 1),
-                                      (fx.SCATTER_COLOUR, 0, 0), (fx.SCATTER_PATCH, 84, 3)],
-                         ids=["patch", "patch128x1", "colour", "patch84x3"])
+                                      (fx.SCATTER_COLOUR, 0, 0), (fx.SCATTER_PATCH, 84, 3),
+                                      (fx.SCATTER_PATCH, 64, 2)],
+                         ids=["patch", "patch128x1", "colour", "patch84x3", "patch64x2"])
 @pytest.mark.parametrize("name", FULL)
 def test_full_size_against_oracle(name, strategy):
     """Every output of the full-size workloads against the oracle (seconds on the host)."""
