@@ -446,7 +446,7 @@ def run_sweep(steps: int, warmup: int, tri_cells: float = 5e5, tet_cells: float 
     import paper_2506_17471_amd as fx
 
     out = []
-    for dim, degrees in ((2, range(1, 9)), (3, range(1, 6))):
+    for dim, degrees in ((2, range(1, 9)), (3, range(1, 7))):
         for k in degrees:
             rng = np.random.default_rng(100 * dim + k)
             if dim == 2:

@@ -96,7 +96,8 @@ typedef struct fem_plan fem_plan;
  *   form         FEM_MASS, FEM_ELASTICITY, FEM_NEOHOOKEAN, FEM_SVK, FEM_LAPLACE or
  *                FEM_HELMHOLTZ
  *   dim          2 (triangles) or 3 (tetrahedra)
- *   degree       polynomial degree k: 1..6 in 2D, 1..4 in 3D
+ *   degree       polynomial degree k: 1..8 in 2D, 1..6 in 3D (batches and curved cells:
+ *                up to 6 in 2D, 4 in 3D)
  *   quad_degree  degree the rule integrates exactly: 0..20
  *   coords       HOST f64 [n_vert][dim]
  *   cell_verts   HOST i32 [n_cell][dim+1]   vertex ids, the affine map's vertex order

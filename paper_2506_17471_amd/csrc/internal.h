@@ -50,7 +50,8 @@ std::vector<double> kernel_table(int form, const RefTables &t, const RefTables *
 struct LaunchArgs {
     const int32_t *verts;     // SoA [(dim+1)][stride] colour-sorted vertex ids
     const int32_t *nodes;     // SoA [nloc][stride]    colour-sorted node ids
-    const uint64_t *first;    // [stride] bit a: this cell is first to write node a
+    const uint64_t *first;    // [(n_loc + 63) / 64][stride]: bit a of word a / 64 set when
+                              // this cell is the first to write its node a
     const double *coords;     // [n_vert][dim]
     const double *tab;        // [nq][record]
     const double *u;

@@ -129,12 +129,16 @@ __global__ void __launch_bounds__(kMaxBlock) colour_kernel(const LaunchArgs a)
         }
     }
     cell_quadrature<FORM, DIM, K, VJP, GEO>(ul, vl, Kinv, adet, gx, a.tab, a.nq, a.lam, a.mu, yl);
-    const uint64_t first = a.first[s];
+    // first-touch bits, one 64-bit word per 64 local nodes ([word][stride])
+    constexpr int NWF = (NLOC + 63) / 64;
+    uint64_t first[NWF];
+#pragma unroll
+    for (int w = 0; w < NWF; ++w) first[w] = a.first[w * a.stride + s];
 #pragma unroll
     for (int n = 0; n < NLOC; ++n) {
         const int64_t nd = a.nodes[n * a.stride + s];
         double *dst = a.y + nd * NC;
-        if ((first >> n) & 1) {
+        if ((first[n >> 6] >> (n & 63)) & 1) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) dst[c] = yl[n][c];
         } else {
@@ -481,6 +485,7 @@ Kernels lookup_form(int dim, int degree, bool vjp)
         case 3: return pick<FORM, 3, 3>(vjp);
         case 4: return pick<FORM, 3, 4>(vjp);
         case 5: return pick<FORM, 3, 5>(vjp);
+        case 6: return pick<FORM, 3, 6>(vjp);
         default: break;
         }
     }

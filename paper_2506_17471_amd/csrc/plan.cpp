@@ -315,21 +315,20 @@ void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
 
     p->stride = std::max<int64_t>(64, (p->n_cell + 63) / 64 * 64);
     std::vector<int32_t> verts((size_t)nv * p->stride, 0), nodes((size_t)nloc * p->stride, 0);
-    std::vector<uint64_t> first((size_t)p->stride, 0);
+    const int nwf = (nloc + 63) / 64;        // first-touch words per cell
+    std::vector<uint64_t> first((size_t)nwf * p->stride, 0);
     std::vector<uint8_t> seen((size_t)p->n_node, 0);
     for (int64_t s = 0; s < p->n_cell; ++s) {
         const int64_t c = perm[s];
         for (int j = 0; j < nv; ++j) verts[(size_t)j * p->stride + s] = cell_verts[c * nv + j];
-        uint64_t m = 0;
         for (int a = 0; a < nloc; ++a) {
             const int32_t nd = cell_nodes[c * nloc + a];
             nodes[(size_t)a * p->stride + s] = nd;
             if (!seen[nd]) {
                 seen[nd] = 1;
-                m |= uint64_t(1) << a;
+                first[(size_t)(a >> 6) * p->stride + s] |= uint64_t(1) << (a & 63);
             }
         }
-        first[s] = m;
     }
     std::vector<int32_t> untouched;
     for (int64_t n = 0; n < p->n_node; ++n)
@@ -900,7 +899,7 @@ int create_plan(fem_plan **out, int form, int dim, int degree, int quad_degree, 
         if (!out) throw Error(FEM_E_ARG, "null output pointer");
         if (form < FEM_MASS || form > FEM_HELMHOLTZ) throw Error(FEM_E_UNSUPPORTED, "unknown form");
         if (dim != 2 && dim != 3) throw Error(FEM_E_UNSUPPORTED, "dim must be 2 or 3");
-        if (degree < 1 || degree > (dim == 2 ? 8 : 5) || !femx::kernel_available(form, dim, degree))
+        if (degree < 1 || degree > (dim == 2 ? 8 : 6) || !femx::kernel_available(form, dim, degree))
             throw Error(FEM_E_UNSUPPORTED, "degree " + std::to_string(degree) + " not built for dim " +
                                                std::to_string(dim));
         if (geom == 2 && !femx::curved_available(form, dim, degree))
@@ -1089,7 +1088,7 @@ int fem_colouring(int64_t n_cell, int n_loc, const int32_t *cell_nodes, int64_t 
 {
     return guarded([&] {
         using femx::Error;
-        if (n_cell < 0 || n_node < 0 || n_loc < 1 || n_loc > 64) throw Error(FEM_E_ARG, "bad size");
+        if (n_cell < 0 || n_node < 0 || n_loc < 1 || n_loc > 255) throw Error(FEM_E_ARG, "bad size");
         if (n_cell > 0 && (!cell_nodes || !colour)) throw Error(FEM_E_ARG, "null array");
         for (int64_t i = 0; i < n_cell * n_loc; ++i)
             if (cell_nodes[i] < 0 || cell_nodes[i] >= n_node)

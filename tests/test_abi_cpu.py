@@ -87,7 +87,7 @@ def test_error_paths_from_host():
     assert _create(form=7)[0] == -2
     assert _create(dim=4)[0] == -2
     assert _create(degree=9)[0] == -2
-    assert _create(dim=3, degree=6, mesh=meshgen.unit_cube(1, 1))[0] == -2
+    assert _create(dim=3, degree=7, mesh=meshgen.unit_cube(1, 1))[0] == -2
     # curved cells and batches are built up to P6 (2D): a curved P7 plan is refused on the host
     mc = meshgen.curved(meshgen.unit_square(2, 7), 0.05)
     assert _create_curved(mc, degree=7, qd=14)[0] == -2
