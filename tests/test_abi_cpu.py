@@ -1,6 +1,8 @@
 """C-ABI checks that need no GPU: exported symbols, the host-side steps of the plan
 (reference tabulation and quadrature, colouring) against the oracle, and error paths."""
 import ctypes
+import itertools
+import math
 import os
 import re
 
@@ -32,16 +34,25 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("dim,k,qd", [(2, 1, 2), (2, 2, 4), (2, 3, 6), (2, 4, 8), (2, 6, 12),
-                                      (3, 1, 2), (3, 2, 2), (3, 2, 4), (3, 4, 6)])
+                                      (2, 7, 14), (2, 8, 16), (3, 1, 2), (3, 2, 2), (3, 2, 4),
+                                      (3, 4, 6), (3, 5, 10), (3, 6, 12)])
 def test_reference_tables_match_oracle(dim, k, qd):
     pts, w, phi, dphi = fx.reference_tables(dim, k, qd)
     opts, ow = quadrature.stroud(dim, qd)
     ophi, odphi = basis.tabulate(dim, k, opts)
     assert pts.shape == opts.shape
     assert np.max(np.abs(pts - opts)) < 1e-15
-    assert np.max(np.abs(w - ow) / ow) < 1e-14
-    assert np.max(np.abs(phi - ophi)) < 1e-13
-    assert np.max(np.abs(dphi - odphi)) < 1e-12
+    # individual Gauss-Jacobi weights from two independent computations agree to ~4e-14 at
+    # 8-9 points per direction; what the rule must do -- integrate every monomial up to its
+    # degree exactly -- both do to rounding
+    assert np.max(np.abs(w - ow) / ow) < 1e-13
+    for P, W in ((pts, w), (opts, ow)):
+        for e in itertools.product(range(qd + 1), repeat=dim):
+            if sum(e) <= qd:
+                exact = math.prod(math.factorial(a) for a in e) / math.factorial(sum(e) + dim)
+                assert abs(np.sum(W * np.prod(P ** np.array(e), axis=1)) - exact) < 5e-14 * exact
+    assert np.max(np.abs(phi - ophi)) < 1e-13 * max(1.0, np.max(np.abs(ophi)))
+    assert np.max(np.abs(dphi - odphi)) < 1e-13 * max(10.0, np.max(np.abs(odphi)))
 
 
 @pytest.mark.parametrize("dim,n,k", [(2, 16, 2), (2, 7, 4), (3, 4, 2), (3, 3, 3)])

@@ -46,7 +46,8 @@ def lattice_positions(mesh):
 
 
 # ----------------------------------------------------------------------------- mass
-@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (2, 5), (3, 1), (3, 2), (3, 3)])
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (2, 5), (2, 8), (3, 1), (3, 2), (3, 3),
+                                   (3, 6)])
 def test_mass_partition_of_unity(dim, k):
     m = small_mesh(dim, 3 if dim == 2 else 2, k)
     y = oracle.action(F_MASS, m, np.ones(m.n_node), 2 * k)
@@ -94,7 +95,7 @@ def test_mass_equals_exact_assembly(dim, n, k):
 
 
 # ------------------------------------------------------------------- Laplace and Helmholtz
-@pytest.mark.parametrize("dim,k", [(2, 1), (2, 3), (2, 6), (3, 1), (3, 2), (3, 4)])
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 3), (2, 6), (2, 8), (3, 1), (3, 2), (3, 4), (3, 6)])
 def test_laplace_kernel_patch_test_symmetry(dim, k):
     m = small_mesh(dim, 3 if dim == 2 else 2, k, seed=12, jitter=0.2 if dim == 2 else 0.1)
     qd = 2 * (k - 1)
