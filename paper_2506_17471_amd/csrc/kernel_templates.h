@@ -60,7 +60,9 @@ namespace {
 constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc, int geo = 1)
 {
     if (lpc == 3) return 1;
-    if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : (k <= 6 ? 4 : 1);
+    // lane pairs, forward: four waves up to P4; three at P5/P6, where four spill ~45
+    // registers (P6 neo-Hookean 412 -> 149 us per 2e5 cells at three)
+    if (lpc == 2) return vjp ? (k <= 4 ? 3 : 1) : (k <= 4 ? 4 : (k <= 6 ? 3 : 1));
     // affine P1/P2 tetrahedra, linear elasticity: a short loop between long memory and
     // accumulation phases, where a third wave per SIMD pays (the compiler otherwise takes
     // 183 VGPRs; the hyperelastic forms would spill at this bound)

@@ -690,16 +690,21 @@ int default_sum_mode(const fem_plan *)
     return femx::SUM_COLOURED;
 }
 
-// One lane per cell in 2D: with coloured sums the lane-pair split no longer pays for its
+// One lane per cell in 2D up to P4: with coloured sums the lane-pair split no longer pays for its
 // shuffles (measured on the P4 neo-Hookean action and VJP); lane triples in 3D from P3 on,
 // where one lane's cell vector would not fit its registers.
 int default_lanes(const fem_plan *p)
 {
     if (p->geom == 2) return 1;    // curved cells: one-lane kernels only
     if (femx::triple_available(p->form, p->dim, p->degree) && p->degree >= 3) return 3;
-    // 2D vector forms from P7 on: a lane's half of the cell (one component) still fits its
-    // registers, the whole cell spills
-    if (femx::pair_available(p->form, p->dim, p->degree) && p->degree >= 7) return 2;
+    // 2D vector forms from P6 on (P5 for elasticity and St Venant-Kirchhoff): a lane's half
+    // of the cell (one component) fits its registers at three waves per SIMD, the whole
+    // cell does not (per 5e5 cells, pairs against one lane: P6 neo-Hookean 362 / 543 us,
+    // SVK 384 / 470, elasticity 298 / 317; P5 elasticity 125 / 161, SVK 180 / 196, but
+    // neo-Hookean 232 / 210; from P7 one lane spills)
+    if (femx::pair_available(p->form, p->dim, p->degree) &&
+        (p->degree >= 6 || (p->degree == 5 && p->form != FEM_NEOHOOKEAN)))
+        return 2;
     return 1;
 }
 
