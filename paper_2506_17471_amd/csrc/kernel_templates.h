@@ -67,6 +67,10 @@ constexpr int waves_target(int form, int dim, int k, bool vjp, int lpc, int geo 
     // accumulation phases, where a third wave per SIMD pays (the compiler otherwise takes
     // 183 VGPRs; the hyperelastic forms would spill at this bound)
     if (form == FEM_ELASTICITY && !vjp && dim == 3 && k <= 2 && geo == 1) return 3;
+    // P4 tetrahedra, scalar forms: 174 VGPRs would leave two waves per SIMD; at three (4
+    // spilled) Laplace 165 -> 114 us and Helmholtz 393 -> 227 us per 2e5 cells (the same
+    // bound on the 2D P8 scalar kernels spills 24-44 registers and doubles their time)
+    if (scalar_form(form) && dim == 3 && k == 4 && geo == 1) return 3;
     // curved cells hold their geometry nodes through the loop: two waves, not three
     return (!vjp && dim == 2 && k <= 4 && !scalar_form(form)) ? (geo == 2 ? 2 : 3) : 1;
 }
