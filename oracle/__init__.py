@@ -11,10 +11,12 @@ Pieces:
 * ``basis.tabulate``     -- Silvester-formula P_k Lagrange values and reference gradients;
 * ``fem_oracle.c``       -- the per-cell loop of the paper's generic action kernel
   (Sec. 2.3) for the mass, Laplace, Helmholtz, linear elasticity, neo-Hookean and
-  St Venant-Kirchhoff forms (App. A), the hyperelastic VJPs written as the literal transpose of the tangent, the
-  discrete energies, and greedy first-fit colouring;
-* ``exact``              -- quadrature-free assembly of mass and elasticity matrices by
-  exact integration of barycentric monomials (the brute-force pin).
+  St Venant-Kirchhoff forms (App. A), the hyperelastic VJPs written as the literal
+  transpose of the tangent, the discrete energies, and greedy first-fit colouring; the
+  Jacobian of the cell map is evaluated at every quadrature point from a geometry basis
+  (P1 on the vertices for affine cells, P2 for curved cells, Sec. 2.4);
+* ``exact``              -- quadrature-free assembly of mass, elasticity and Laplace
+  matrices by exact integration of barycentric monomials (the brute-force pin).
 
 Parity pins: every function here is checked in ``tests/test_oracle_*.py`` against closed
 forms, invariants and brute force; none is pinned by re-running itself.
