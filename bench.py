@@ -570,7 +570,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the action "
-              f"shards by cells across GPUs, which this build does not run)", file=sys.stderr)
+              f"shards by cells across GPUs, which this library does not implement)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
