@@ -246,6 +246,13 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
         comp = lane < 63 ? lane % 3 : 0;
         base = lane < 63 ? lane - comp : 0;
     }
+    // Wave priorities (coloured sums, affine cells): a workgroup's memory phases -- the
+    // staging here, the sums and the write-out after its quadrature loop -- take issue
+    // precedence over the loops of the other workgroups sharing the SIMD, so they overlap
+    // those loops rather than wait behind them.  The curved-cell kernels keep the default
+    // priority (the hints reshuffle their register allocation, already spilling).
+    constexpr bool kPrio = SUM == SUM_COLOURED && GEO == 1;
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(2);
     const int nb = a.patch_off[p];
     const int U = a.patch_off[p + 1] - nb;
     const int nint = a.patch_nint[p];
@@ -298,6 +305,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     }
 
     // 3. the cell's quadrature loop
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
     if (active) {
         if constexpr (LPC == 1) {
             cell_quadrature<FORM, DIM, K, VJP, GEO>(ul, vl, Kinv, adet, gx, a.tab, a.nq, a.lam,
@@ -328,6 +336,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     }
 
     // 4. sum the cell vectors into the patch's nodes
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
     if constexpr (SUM == SUM_ELEMENT) {
         if (active) {
 #pragma unroll
