@@ -51,13 +51,23 @@ def params_for(form):
 HYPERELASTIC = (fx.FORM_NEOHOOKEAN, fx.FORM_SVK)
 
 
+
+def rule_families(dim, quad_degree):
+    """The rule families a plan can run at this degree: conical always, symmetric where
+    one is built."""
+    return ["conical"] + (["symmetric"] if oracle.quadrature.has_symmetric(dim, quad_degree) else [])
+
+
 def inputs(form, mesh, seed):
     rng = np.random.default_rng(seed)
     ncomp = 1 if form in fx.SCALAR_FORMS else mesh.dim
     if form == fx.FORM_NEOHOOKEAN:
         u = meshgen.nh_displacement(rng, mesh, 0.01)
-        # an admissible state: det F > 0 at every quadrature point of the rule used
-        assert oracle.min_det_f(mesh, u, 2 * mesh.k) > 0.5
+        # an admissible state: det F > 0 at every quadrature point of every rule a test
+        # may run at this degree (the plans default to the symmetric rule where one is
+        # built; the conical rule is always available)
+        for fam in rule_families(mesh.dim, 2 * mesh.k):
+            assert oracle.min_det_f(mesh, u, 2 * mesh.k, family=fam) > 0.5
     elif form == fx.FORM_SVK:
         # SVK needs no det F > 0; a larger state exercises its cubic terms
         u = meshgen.nh_displacement(rng, mesh, 0.2)

@@ -14,6 +14,7 @@ import pytest
 import oracle
 import test_oracle_action as pins
 import test_oracle_curved as curved
+import test_oracle_min_det as mindet
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
                    "fem_oracle.c")
@@ -71,6 +72,12 @@ MUTATIONS = {
     "helmholtz_mass_term_dropped": ("if (form == OR_MASS || form == OR_HELMHOLTZ) {\n                double uq",
                                     "if (form == OR_MASS) {\n                double uq",
                                     [lambda: pins.test_laplace_helmholtz_equal_exact_assembly(2, 2, 2)]),
+    "min_det_f_keeps_first_point": ("            if (det < mn)\n                mn = det;",
+                                    "            if (q == 0 && cell == 0)\n                mn = det;",
+                                    [lambda: mindet.test_quadratic_displacement_extreme_point(2, 2, 0, 0.3, "conical")]),
+    "min_det_f_without_identity": ("F[i][j] = (i == j ? 1.0 : 0.0) + G[i][j];\n            double det = inverse(d, F, Fi);",
+                                   "F[i][j] = G[i][j];\n            double det = inverse(d, F, Fi);",
+                                   [lambda: mindet.test_zero_displacement_gives_one(2, 1, "conical")]),
     "colouring_ignores_conflicts": ("if ((masks[nd * nwords + c / 64] >> (c % 64)) & 1u) {",
                                     "if (0) {",
                                     [lambda: pins.test_colouring_valid_and_greedy(2, 6, 1)]),
