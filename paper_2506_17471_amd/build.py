@@ -69,25 +69,9 @@ def build(asm_dir: str | None = None, verbose: bool = False) -> str:
     return LIB
 
 
-PROBE_SRC = os.path.join(CSRC, "probe", "contraction_probe.hip")
-PROBE = os.path.join(HERE, "contraction_probe")
-
-
-def build_probe() -> str:
-    """The stand-alone FP64 matrix-core / vector contraction probe (not part of the library)."""
-    tmp = PROBE + ".tmp"
-    cmd = [_hipcc(), "-x", "hip", *[f for f in HIPFLAGS if f != "-fPIC"], PROBE_SRC, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for the contraction probe:\n{r.stderr}")
-    os.replace(tmp, PROBE)
-    return PROBE
-
-
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--asm", default=None, help="directory to keep gfx950 assembly")
     ap.add_argument("-v", "--verbose", action="store_true")
     args = ap.parse_args()
     print(build(args.asm, args.verbose))
-    print(build_probe())
