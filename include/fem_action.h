@@ -136,9 +136,10 @@ int fem_plan_create_curved(fem_plan **out, int form, int dim, int degree, int qu
                            const int32_t *cell_gnodes, const int32_t *cell_nodes, int64_t n_node,
                            const double *params, int n_params);
 
-/* Release a plan and its device memory (NULL is a no-op).  Synchronises the device
- * before freeing so that no enqueued launch still reads the plan's arrays. */
-void fem_plan_destroy(fem_plan *plan);
+/* Release a plan and its device memory (NULL is a no-op, FEM_OK).  Synchronises the device
+ * before freeing so that no enqueued launch still reads the plan's arrays.  Errors:
+ * FEM_E_ARG, with the plan left intact, while a batch (fem_batch_create) holds it. */
+int fem_plan_destroy(fem_plan *plan);
 
 /*
  * y = A(u): the operator action (paper Sec. 2.3, generic action kernel; App. A forms).
@@ -288,7 +289,8 @@ int fem_plan_get_timing(fem_plan *plan, double *kernel_ms, int64_t *calls);
  *   cache_path  HOST path of a JSON cache to update (NULL: none).  fem_plan_create applies
  *          a cached configuration when the environment variable FEM_TUNE_CACHE names the
  *          file.  Keys: device architecture, form, dimension, degree, quadrature degree
- *          and rule family, round(log2(cell count)).
+ *          and rule family, round(log2(cell count)), and for the hyperelastic forms the
+ *          direction (the VJP's entry is its own; plan creation applies the action's).
  *   results HOST f64 [max_results][6] out: strategy, cells per patch, lanes per cell,
  *          cells per workgroup (colour), sum mode, mean milliseconds; n_results HOST out.
  *   max_timed  0: time every candidate; k > 0: only the cost model's k best
@@ -320,7 +322,9 @@ int fem_tune_predict(const fem_plan *plan, int vjp, double *results, int max_res
  * launch over all patches of its meshes, and one launch sums every mesh's shared nodes.
  *
  * fem_batch_create: plans HOST [n] (each switched to the patch strategy if it is not on
- *   it; the plans must outlive the batch and must not change strategy meanwhile);
+ *   it).  The batch holds its plans until fem_batch_destroy: meanwhile fem_plan_destroy,
+ *   fem_plan_set_strategy, fem_plan_set_quadrature and fem_tune on any of them fail with
+ *   FEM_E_ARG and leave the plan unchanged (the batch keeps pointers to its arrays);
  *   u, y HOST arrays [n] of DEVICE pointers, mesh i reading u[i] and writing y[i] (no two
  *   meshes may share an output).  Synchronous.
  * fem_batch_set_vectors: rebind the vectors (synchronous; the graph is re-recorded at the

@@ -28,6 +28,7 @@ SCALAR_FORMS = (FORM_MASS, FORM_LAPLACE, FORM_HELMHOLTZ)
 QUAD_CONICAL, QUAD_SYMMETRIC = 0, 1
 SCATTER_COLOUR, SCATTER_PATCH = 0, 1
 SUM_ELEMENT, SUM_COLOURED = 1, 2
+OK, E_ARG, E_UNSUPPORTED, E_INDEX, E_INVERTED, E_HIP, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfemx.so")
 
 _STATUS = {0: "FEM_OK", -1: "FEM_E_ARG", -2: "FEM_E_UNSUPPORTED", -3: "FEM_E_INDEX",
@@ -60,7 +61,7 @@ def lib() -> ctypes.CDLL:
     L.fem_plan_create_curved.argtypes = L.fem_plan_create.argtypes
     L.fem_plan_create_curved.restype = i32
     L.fem_plan_destroy.argtypes = [P]
-    L.fem_plan_destroy.restype = None
+    L.fem_plan_destroy.restype = i32
     L.fem_action.argtypes = [P, P, P, P]
     L.fem_action.restype = i32
     L.fem_action_vjp.argtypes = [P, P, P, P, P]
@@ -252,7 +253,7 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None) is not None:
-            lib().fem_plan_destroy(self._h)
+            _check(lib().fem_plan_destroy(self._h))   # refused while a batch holds the plan
             self._h = None
 
     def __del__(self):

@@ -307,6 +307,7 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
         delete b;
         return st;
     }
+    for (fem_plan *p : b->plans) ++p->batch_refs;
     *out = b;
     return FEM_OK;
 }
@@ -371,6 +372,7 @@ void fem_batch_destroy(fem_batch *batch)
 {
     if (!batch) return;
     (void)hipDeviceSynchronize();
+    for (fem_plan *p : batch->plans) --p->batch_refs;
     free_batch(batch);
     delete batch;
 }

@@ -120,6 +120,7 @@ struct fem_plan {
     int n_colours = 0;
     int block = 0;                       // cells per workgroup (0 = default)
     int device = 0;
+    int batch_refs = 0;                  // batches holding this plan's device arrays
     std::vector<int64_t> colour_off;     // [n_colours + 1] in colour-sorted order
     std::vector<int32_t> colour;         // [n_cell] colour of each caller cell
     int64_t stride = 0;                  // padded column length of the SoA maps

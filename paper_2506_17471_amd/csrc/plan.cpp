@@ -738,6 +738,16 @@ void check_plan(const fem_plan *p)
     if (!p) throw femx::Error(FEM_E_ARG, "null plan");
 }
 
+// A batch keeps device pointers into its plans (tables, patch arrays, partial sums) in its
+// descriptors and its recorded graph: calls that replace those arrays are refused while one
+// holds the plan.
+void check_unbatched(const fem_plan *p)
+{
+    check_plan(p);
+    if (p->batch_refs > 0)
+        throw femx::Error(FEM_E_ARG, "the plan is held by a batch; destroy the batch first");
+}
+
 void run(const fem_plan *p, const double *u, const double *v, double *y, void *stream, bool vjp)
 {
     using femx::Error;
@@ -966,12 +976,16 @@ int fem_plan_create_curved(fem_plan **out, int form, int dim, int degree, int qu
                        cell_gnodes, cell_nodes, n_node, params, n_params);
 }
 
-void fem_plan_destroy(fem_plan *plan)
+int fem_plan_destroy(fem_plan *plan)
 {
-    if (!plan) return;
+    if (!plan) return FEM_OK;
+    if (plan->batch_refs > 0)
+        return fail(femx::Error(FEM_E_ARG, "the plan is held by a batch; destroy the batch first"));
     (void)hipDeviceSynchronize();
     free_plan_memory(plan);
     delete plan;
+    femx::last_error().clear();
+    return FEM_OK;
 }
 
 int fem_action_jvp(const fem_plan *plan, const double *u, const double *w, double *out,
@@ -1149,7 +1163,7 @@ int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const 
 int fem_plan_set_quadrature(fem_plan *plan, int family)
 {
     return guarded([&] {
-        check_plan(plan);
+        check_unbatched(plan);
         int nq = 0;
         std::vector<double> tab = plan_tables(plan, family, plan->h_coords.data(),
                                               plan->h_cell_verts.data(), true, &nq);
@@ -1165,7 +1179,10 @@ int fem_plan_set_quadrature(fem_plan *plan, int family)
 int fem_plan_set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_cell,
                           int sum_mode)
 {
-    return guarded([&] { femx::set_strategy(plan, strategy, patch_cells, lanes_per_cell, sum_mode); });
+    return guarded([&] {
+        check_unbatched(plan);
+        femx::set_strategy(plan, strategy, patch_cells, lanes_per_cell, sum_mode);
+    });
 }
 
 int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vjp,
@@ -1173,7 +1190,7 @@ int fem_tune(fem_plan *plan, const double *u, const double *v, double *y, int vj
              int *n_results, int max_timed)
 {
     return guarded([&] {
-        check_plan(plan);
+        check_unbatched(plan);
         if (plan->n_cell == 0) throw femx::Error(FEM_E_ARG, "nothing to tune on an empty mesh");
         if (!u || !y || (vjp && !v)) throw femx::Error(FEM_E_ARG, "null vector");
         if (max_results < 0 || max_timed < 0) throw femx::Error(FEM_E_ARG, "negative count");
@@ -1207,6 +1224,6 @@ int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
 
 const char *fem_last_error(void) { return g_last_error.c_str(); }
 
-int fem_version(void) { return 100; }
+int fem_version(void) { return 200; }
 
 }  // extern "C"

@@ -8,7 +8,8 @@
 // timed with HIP events on the caller's stream using the paper's protocol (Sec. 6.2.1): five warm-up runs, then timed runs until 15 have been collected
 // or 0.2 s has accumulated, the arithmetic mean being the candidate's time.  Results can
 // be kept in a small JSON cache keyed by device architecture, form, dimension, degree,
-// quadrature degree and rule family, and log2 of the cell count, which fem_plan_create consults when the
+// quadrature degree and rule family, log2 of the cell count and direction (action or VJP); fem_plan_create
+// consults the action entries when the
 // environment variable FEM_TUNE_CACHE names the file.
 #include <hip/hip_runtime_api.h>
 
@@ -41,13 +42,16 @@ std::string arch_name()
     return colon == std::string::npos ? s : s.substr(0, colon);
 }
 
-std::string cache_key(const fem_plan *p)
+// one entry per direction: the tangent (VJP) kernels of the hyperelastic forms have their
+// own best configuration; plan creation applies the forward entry
+std::string cache_key(const fem_plan *p, bool vjp = false)
 {
     const int bucket = p->n_cell > 0 ? (int)std::lround(std::log2((double)p->n_cell)) : 0;
     std::ostringstream k;
     k << arch_name() << "/f" << p->form << "/d" << p->dim << "/k" << p->degree << "/q"
       << p->quad_degree << (p->quad_family == FEM_QUAD_SYMMETRIC ? "s" : "c")
-      << (p->geom == 2 ? "/g2" : "") << "/c" << bucket;
+      << (p->geom == 2 ? "/g2" : "") << "/c" << bucket
+      << (vjp && femx::nonlinear_form(p->form) ? "/vjp" : "");
     return k.str();
 }
 
@@ -323,7 +327,7 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
     apply(p, best_c);
     if (cache && *cache) {
         auto c = read_cache(cache);
-        c[cache_key(p)] = {(double)best_c.strategy, (double)best_c.patch, (double)best_c.lanes,
+        c[cache_key(p, vjp)] = {(double)best_c.strategy, (double)best_c.patch, (double)best_c.lanes,
                            (double)best_c.block, (double)best_c.sum_mode, best};
         write_cache(cache, c);
     }

@@ -473,3 +473,33 @@ def test_batch_rebind_vectors():
     torch.cuda.synchronize()
     for p, u, y in zip(plans, us2, ys2):
         assert torch.equal(y, p.action(u))
+
+
+def test_batch_holds_its_plans():
+    """While a batch holds a plan, the calls that would free or replace the arrays its
+    descriptors and graph point at are refused (host-side checks) and leave the plan as it
+    was; after the batch is destroyed they work again."""
+    ws = _batch_meshes(n_mesh=3, seed=13)
+    plans = [fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params) for w in ws]
+    us = [gpu(w.u) for w in ws]
+    ys = [torch.empty_like(u) for u in us]
+    b = fx.Batch(plans, us, ys)
+    b.run()
+    torch.cuda.synchronize()
+    before = [y.clone() for y in ys]
+    p = plans[0]
+    st = p.strategy()
+    L = fx.lib()
+    assert L.fem_plan_set_quadrature(p.handle, fx.QUAD_CONICAL) == fx.E_ARG
+    assert L.fem_plan_set_strategy(p.handle, fx.SCATTER_COLOUR, 0, 0, 0) == fx.E_ARG
+    assert L.fem_plan_destroy(p.handle) == fx.E_ARG
+    assert b"held by a batch" in L.fem_last_error()
+    with pytest.raises(fx.FemError):
+        p.tune(us[0])
+    assert p.strategy() == st
+    b.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, y) for a, y in zip(before, ys))
+    b.close()
+    p.set_strategy(fx.SCATTER_COLOUR)
+    p.close()
