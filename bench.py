@@ -4,9 +4,15 @@
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--all] [--no-batch] [--no-cpu-baseline]
 
 A step is one full action y = A(u) (gather, geometry, evaluation, pointwise form,
-quadrature, colour-ordered scatter) over the whole mesh, inputs resident in HBM.  The
+quadrature, fixed-order scatter) over the whole mesh, inputs resident in HBM.  The
 default workload is the 2D P4 compressible neo-Hookean residual on the 512x512 unit
 square (524288 triangles, 8,396,802 DoFs, quadrature degree 8).  Prints ONE JSON line.
+
+Besides the headline (warm: back-to-back steps) the default line carries its VJP, the
+P2 mass action at 1024^2 and at 64^2, and the 3D P2 elasticity action at 64^3, each warm
+and cold (every step after a read-only pass over 1.25 GiB that evicts L2 and the 256 MB
+memory-side cache), the library's STREAM copy as the achievable bandwidth, the 64-mesh
+batch, and the oracle on the host's CPUs.
 
 Roofline: the kernel is bound by FP64 vector arithmetic (its arithmetic intensity is far
 above the 9.8 flop/byte ridge), so `roofline` reports achieved FP64 flop/s of the
@@ -168,9 +174,20 @@ def recorded_traffic(workload: str, kernel: str):
     return r["fetch_kib"] * 1024 * r["fetch_scale"] + r["write_kib"] * 1024 * r["write_scale"]
 
 
-def cold_flush(buf):
-    """Stream a buffer larger than the 256 MB MALL so that the next step starts cold."""
-    buf.add_(1.0)
+class ColdFlush:
+    """Evict L2 and the 256 MB memory-side cache (MALL) before a cold step: the library's
+    read-only pass over 1.25 GiB (five times the MALL).  Nothing is written but one partial
+    sum per workgroup, so no dirty lines are left to be written back inside the timed step;
+    the previous step's dirty output lines are written back during the pass, outside it."""
+
+    def __init__(self, gib: float = 1.25):
+        import torch
+        self.buf = torch.ones(int(gib * (1 << 30)) // 8, dtype=torch.float64, device="cuda")
+        self.sink = torch.empty(4096, dtype=torch.float64, device="cuda")
+
+    def __call__(self):
+        import paper_2506_17471_amd as fx
+        fx.stream_read(self.buf, self.sink)
 
 
 def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default"):
@@ -199,9 +216,32 @@ def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default"):
     return plan, u, v, y, tuned
 
 
-def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bool = False,
-                 tune: bool = True, rule: str = "default"):
+def cold_steps(fn, steps: int, warmup: int, flush) -> np.ndarray:
+    """Milliseconds of each of `steps` steps, each timed by its own pair of HIP events
+    after a cache-evicting pass and a synchronisation (the pass is outside the events)."""
     import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ms = []
+    for _ in range(steps):
+        flush()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    return np.array(ms)
+
+
+def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bool = False,
+                 tune: bool = True, rule: str = "default", flush=None):
+    """The workload's tuned plan timed warm (back-to-back steps, inputs resident in HBM and
+    whatever of them the caches hold) and, with `cold`, cold (every step after a
+    cache-evicting pass).  Returns (warm info, cold info or None, workload)."""
     import meshgen
 
     w = meshgen.workload(name, with_v=vjp)
@@ -210,30 +250,6 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
         fn = lambda: plan.vjp(u, v, out=y)  # noqa: E731
     else:
         fn = lambda: plan.action(u, out=y)  # noqa: E731
-    if cold:
-        # stream 1.25 GiB (more than the 256 MB last-level cache) before every timed run
-        flush = torch.zeros(160 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        st = torch.cuda.current_stream()
-        ms = []
-        for _ in range(steps):
-            cold_flush(flush)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(st)
-            fn()
-            b.record(st)
-            torch.cuda.synchronize()
-            ms.append(a.elapsed_time(b))
-        ms = np.array(ms)
-        wall = float(ms.sum()) / 1e3
-        del flush
-    else:
-        ms, wall = time_steps(fn, steps, warmup)
-        ms = np.array([ms])
-    ms_median = float(np.median(ms)) if cold else median_step_ms(fn, steps)
-    kernel_ms = time_kernel(plan, fn, steps)
     st = plan.strategy()
     curved = w.mesh.cell_gnodes is not None
     nv = w.mesh.gcoords.shape[0] if curved else w.mesh.n_vert
@@ -242,27 +258,50 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
         fl = vjp_flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad, ng)
     else:
         fl = flops_per_cell(w.form, w.mesh.dim, plan.n_loc, plan.n_quad, ng)
-    info = dict(workload=name, vjp=vjp, cold=cold, n_cell=w.mesh.n_cell, n_dof=w.n_dof,
+    base = dict(workload=name, vjp=vjp, n_cell=w.mesh.n_cell, n_dof=w.n_dof,
                 n_loc=plan.n_loc, n_quad=plan.n_quad, quad_family=plan.quad_family_name,
-                tuned=tuned,
-                flops_per_cell=fl, flops=fl * w.mesh.n_cell,
+                tuned=tuned, flops_per_cell=fl, flops=fl * w.mesh.n_cell,
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
                                       3 if vjp and w.form in (2, 3) else 2, ng or None),
                 geometry=2 if curved else 1,
-                ms_mean=float(ms.mean()), ms_median=ms_median, kernel_ms=kernel_ms, wall_s=wall,
                 launch={"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
                         "lanes_per_cell": st[2],
                         "sum_mode": {1: "element", 2: "coloured"}.get(st[3], "-")})
-    t = info["ms_mean"] / 1e3
-    info["dof_per_s"] = w.n_dof / t
-    info["tflops"] = info["flops"] / t / 1e12
-    info["hbm_gbs_footprint"] = info["bytes"] / t / 1e9
-    info["hbm_frac_footprint"] = info["hbm_gbs_footprint"] / HBM_PEAK_GBS
-    info["fp64_frac"] = info["tflops"] / FP64_PEAK_TFLOPS
-    info["kernel_tflops"] = info["flops"] / (kernel_ms / 1e3) / 1e12
-    info["kernel_hbm_frac_footprint"] = info["bytes"] / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS
+
+    def finish(info, ms_mean, ms_median, kernel_ms):
+        info.update(ms_mean=ms_mean, ms_median=ms_median, kernel_ms=kernel_ms)
+        t = ms_mean / 1e3
+        info["dof_per_s"] = w.n_dof / t
+        info["tflops"] = info["flops"] / t / 1e12
+        info["hbm_gbs_footprint"] = info["bytes"] / t / 1e9
+        info["hbm_frac_footprint"] = info["hbm_gbs_footprint"] / HBM_PEAK_GBS
+        info["fp64_frac"] = info["tflops"] / FP64_PEAK_TFLOPS
+        if kernel_ms:
+            info["kernel_tflops"] = info["flops"] / (kernel_ms / 1e3) / 1e12
+            info["kernel_fp64_frac"] = info["kernel_tflops"] / FP64_PEAK_TFLOPS
+            info["kernel_hbm_frac_footprint"] = info["bytes"] / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS
+        return info
+
+    ms, wall = time_steps(fn, steps, warmup)
+    warm = finish(dict(base, cold=False, wall_s=wall), ms, median_step_ms(fn, steps),
+                  time_kernel(plan, fn, steps))
+    cold_info = None
+    if cold:
+        flush = flush or ColdFlush()
+        cms = cold_steps(fn, steps, warmup, flush)
+        # the kernel alone, cold: the library's events on the patch dispatch of each step
+        plan.set_timing(True)
+        for _ in range(steps):
+            flush()
+            fn()
+        import torch
+        torch.cuda.synchronize()
+        kms, n = plan.timing()
+        plan.set_timing(False)
+        cold_info = finish(dict(base, cold=True, wall_s=float(cms.sum()) / 1e3), float(cms.mean()),
+                           float(np.median(cms)), kms / max(n, 1))
     del plan
-    return info, w
+    return warm, cold_info, w
 
 
 def run_autograd(name: str, steps: int, warmup: int) -> dict:
@@ -382,11 +421,35 @@ def _sample_mesh(m, c0: int, c1: int, u: np.ndarray, ncomp: int):
     return sub, np.ascontiguousarray(u.reshape(-1, ncomp)[nodes].ravel())
 
 
+def host_cpus() -> dict:
+    """The host's processor as the process sees it: logical CPUs, the CPUs this process
+    may run on, and the model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"cpu_count": os.cpu_count(), "affinity": allowed, "model": model}
+
+
+# host threads the CPU baseline may use: the per-GPU CPU share of the MI355X boxes (16),
+# or fewer where the process may run on fewer CPUs
+CPU_SHARE = 16
+
+
 def cpu_baseline(w, family: str, max_cells: int = 65536, seconds: float = 10.0):
     """The oracle on the first `max_cells` cells of the same mesh (a mesh of their own),
-    with the quadrature rule the GPU plan used: on one thread, and on all host threads (up
-    to 16) as independent contiguous chunks of the sample run concurrently (the C oracle
-    releases the GIL)."""
+    with the quadrature rule the GPU plan used: on all the host threads the process may use
+    (up to the per-GPU share), as independent contiguous chunks of the sample run
+    concurrently (the C oracle releases the GIL), and on one thread."""
     import concurrent.futures
     import oracle
     m = w.mesh
@@ -398,11 +461,12 @@ def cpu_baseline(w, family: str, max_cells: int = 65536, seconds: float = 10.0):
     while True:
         oracle.action(w.form, sub, us, w.quad_degree, w.params, family=family)
         reps += 1
-        if time.perf_counter() - t0 > seconds:
+        if time.perf_counter() - t0 > seconds / 2:
             break
     dt = (time.perf_counter() - t0) / reps
     dofs_per_cell = w.n_dof / m.n_cell
-    threads = max(1, min(16, os.cpu_count() or 1))
+    host = host_cpus()
+    threads = max(1, min(CPU_SHARE, host["affinity"]))
     bounds = np.linspace(0, nc, threads + 1).astype(int)
     chunks = [_sample_mesh(m, int(a), int(b), w.u, w.ncomp) for a, b in zip(bounds[:-1], bounds[1:])]
     with concurrent.futures.ThreadPoolExecutor(threads) as ex:
@@ -418,13 +482,32 @@ def cpu_baseline(w, family: str, max_cells: int = 65536, seconds: float = 10.0):
             if time.perf_counter() - t1 > seconds / 2:
                 break
         pdt = (time.perf_counter() - t1) / preps
-    return {"value": nc * dofs_per_cell / dt, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+    return {"value": nc * dofs_per_cell / pdt, "unit": "DoF/s", "cores": threads, "kind": "oracle",
             "sample": f"first {nc} of {m.n_cell} cells of the same mesh as a mesh of their own, "
-                      f"{reps} runs, {dt * 1e3:.1f} ms each; DoF/s scaled by DoFs per cell of the "
-                      f"full mesh",
-            "all_cores": {"value": nc * dofs_per_cell / pdt, "cores": threads,
-                          "sample": f"the same cells in {threads} contiguous chunks run "
-                                    f"concurrently, {preps} runs, {pdt * 1e3:.1f} ms each"}}
+                      f"in {threads} contiguous chunks run concurrently on {threads} threads, "
+                      f"{preps} runs, {pdt * 1e3:.1f} ms each; DoF/s scaled by DoFs per cell of "
+                      f"the full mesh",
+            "host": host,
+            "one_thread": {"value": nc * dofs_per_cell / dt, "cores": 1,
+                           "sample": f"the same {nc} cells on one thread, {reps} runs, "
+                                     f"{dt * 1e3:.1f} ms each"}}
+
+
+def stream_copy_gbs(gib: float = 1.0, steps: int = 20) -> dict:
+    """Achievable HBM bandwidth: the library's STREAM copy of `gib` GiB (read + write
+    counted), mean over back-to-back copies, and the same pass read-only."""
+    import torch
+    import paper_2506_17471_amd as fx
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.empty(fx.STREAM_SINK, dtype=torch.float64, device="cuda")
+    ms, _ = time_steps(lambda: fx.stream_copy(src, dst), steps, 3)
+    rms, _ = time_steps(lambda: fx.stream_read(src, sink), steps, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[-5:], src[-5:])
+    return {"bytes_each_way": n * 8, "copy_ms": ms, "copy_gbs": 2 * n * 8 / (ms / 1e3) / 1e9,
+            "read_ms": rms, "read_gbs": n * 8 / (rms / 1e3) / 1e9}
 
 
 FORM_NAMES = {0: "mass", 1: "elasticity", 2: "neohookean", 3: "svk", 4: "laplace", 5: "helmholtz"}
@@ -577,13 +660,14 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.copy_calibration:
+        import paper_2506_17471_amd as fx
         n = args.copy_calibration * 1024 * 1024 // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
-            dst.copy_(src)
+            fx.stream_copy(src, dst)
         torch.cuda.synchronize()
-        ms, _ = time_steps(lambda: dst.copy_(src), 20, 0)
+        ms, _ = time_steps(lambda: fx.stream_copy(src, dst), 20, 0)
         print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 25,
                           "copy_gbs_read_plus_write": 2 * n * 8 / (ms / 1e3) / 1e9}))
         return
@@ -598,51 +682,53 @@ def main():
     def note(msg):
         print(f"# {msg}", file=sys.stderr, flush=True)
 
-    main_info, w = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule=args.rule)
-    note(f"{args.workload}: {main_info['ms_mean']:.4f} ms/step, tuned {main_info['tuned']}")
-    extras = {}
+    flush = ColdFlush()
+    main_info, main_cold, w = run_workload(args.workload, args.steps, args.warmup, cold=True,
+                                           tune=tune, rule=args.rule, flush=flush)
+    note(f"{args.workload}: {main_info['ms_mean']:.4f} ms/step warm, {main_cold['ms_mean']:.4f} cold, "
+         f"tuned {main_info['tuned']}")
+    extras = {args.workload + "_cold": main_cold}
     if w.form == 2:
-        vinfo, _ = run_workload(args.workload, args.steps, args.warmup, vjp=True, tune=tune,
-                                rule=args.rule)
+        vinfo, vcold, _ = run_workload(args.workload, args.steps, args.warmup, cold=True, vjp=True,
+                                       tune=tune, rule=args.rule, flush=flush)
         extras["vjp"] = vinfo
+        extras["vjp_cold"] = vcold
         extras["adjoint_forward_time_ratio"] = vinfo["ms_mean"] / main_info["ms_mean"]
-        note(f"vjp: {vinfo['ms_mean']:.4f} ms/step")
+        note(f"vjp: {vinfo['ms_mean']:.4f} ms/step warm, {vcold['ms_mean']:.4f} cold")
         extras["autograd"] = run_autograd(args.workload, args.steps, args.warmup)
         note(f"autograd: {extras['autograd']}")
-    # the memory-bound form at a size where HBM, not launch latency, binds: its fraction of
-    # the HBM roofline (footprint bytes / time against 8 TB/s)
-    minfo, _ = run_workload("mass_p2_2d_1024", args.steps, args.warmup, tune=tune)
-    extras["mass_p2_2d_1024"] = minfo
-    note(f"mass_p2_2d_1024: {minfo['ms_mean']:.4f} ms/step")
+    # the memory-bound form at a size where HBM, not launch latency, binds (P2 mass at
+    # 1024^2), the 3D P2 elasticity action and the P2 mass action at its stated 64^2 size:
+    # warm and cold
+    for name in ("mass_p2_2d_1024", "elast_p2_3d", "mass_p2_2d"):
+        info, cinfo, _ = run_workload(name, args.steps, args.warmup, cold=True, tune=tune, flush=flush)
+        extras[name] = info
+        extras[name + "_cold"] = cinfo
+        note(f"{name}: {info['ms_mean']:.4f} ms/step warm, {cinfo['ms_mean']:.4f} cold")
+    extras["stream"] = stream_copy_gbs()
+    note(f"stream: {extras['stream']}")
     if args.all:
-        for name in ("mass_p2_2d", "elast_p2_3d"):
-            info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
-            extras[name] = info
-            note(f"{name}: {info['ms_mean']:.4f} ms/step")
         # the paper's hyperelastic law (St Venant-Kirchhoff): residual and tangent action
-        info, _ = run_workload("svk_p4_2d", args.steps, args.warmup, tune=tune)
+        info, _, _ = run_workload("svk_p4_2d", args.steps, args.warmup, tune=tune)
         extras["svk_p4_2d"] = info
         note(f"svk_p4_2d: {info['ms_mean']:.4f} ms/step")
-        info, _ = run_workload("svk_p4_2d", args.steps, args.warmup, vjp=True, tune=tune)
+        info, _, _ = run_workload("svk_p4_2d", args.steps, args.warmup, vjp=True, tune=tune)
         extras["svk_p4_2d_tangent"] = info
         note(f"svk_p4_2d tangent: {info['ms_mean']:.4f} ms/step")
         if w.form == 2 and args.rule == "default":
             # the same operator family with the conical-product rule (more points)
-            info, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule="conical")
+            info, _, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule="conical")
             extras[args.workload + "_conical"] = info
             note(f"{args.workload} conical rule: {info['ms_mean']:.4f} ms/step")
         # curved (P2-geometry) cells: J, K and |det J| at every quadrature point
         for name in ("nh_p4_2d_curved", "mass_p2_2d_1024_curved"):
-            info, _ = run_workload(name, args.steps, args.warmup, tune=tune)
+            info, _, _ = run_workload(name, args.steps, args.warmup, tune=tune)
             extras[name] = info
             note(f"{name}: {info['ms_mean']:.4f} ms/step")
-        for name in ("mass_p2_2d_1024", "nh_p4_2d", "elast_p2_3d"):
-            info, _ = run_workload(name, args.steps, args.warmup, cold=True, tune=tune)
-            extras[name + "_cold"] = info
-            note(f"{name} cold: {info['ms_mean']:.4f} ms/step")
     if not args.no_batch:
         extras["batch"] = run_batch(args.steps, args.warmup, tune=tune)
         note(f"batch: {extras['batch']}")
+    del flush
 
     # the dominant kernel alone (its own HIP-event duration); the step adds the fixup
     achieved = main_info["kernel_tflops"]
@@ -653,6 +739,13 @@ def main():
                  f"{ {'element': 1, 'coloured': 2}.get(mode, 0) }, {geo}>")
     else:
         kname = f"colour_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {geo}>"
+    stream_gbs = extras["stream"]["copy_gbs"]
+
+    def hbm(info, kernel=False):
+        return info["kernel_hbm_frac_footprint"] if kernel else info["hbm_frac_footprint"]
+
+    mass, mass_c = extras["mass_p2_2d_1024"], extras["mass_p2_2d_1024_cold"]
+    hbm_names = [args.workload, "mass_p2_2d_1024", "elast_p2_3d"]
     out = {
         "metric": "FP64 FE action DoF/s + % HBM roofline; adjoint/forward time ratio; batched speedup",
         "value": main_info["dof_per_s"],
@@ -680,16 +773,32 @@ def main():
                      "avg_step_ms": main_info["ms_mean"],
                      "step_tflops": main_info["tflops"],
                      "footprint_gbs": main_info["hbm_gbs_footprint"]},
-        # the metric's other parts on this run: the fraction of the HBM roofline (footprint
-        # bytes per step against 8 TB/s) of the headline and of the memory-bound mass form,
-        # the adjoint/forward time ratio and the batched speedup
+        # the metric's other parts on this run.  HBM roofline fractions: footprint bytes per
+        # step (each DoF, coordinate and map entry once) against 8 TB/s, cold (every step
+        # after a read-only pass over 1.25 GiB that evicts L2 and the 256 MB MALL) and warm
+        # (back-to-back steps); "kernel" is the main kernel's own time without the fixup.
         "summary": {
             "dof_per_s": main_info["dof_per_s"],
             "hbm_roofline_frac": {
-                args.workload: main_info["hbm_frac_footprint"],
-                "mass_p2_2d_1024": minfo["hbm_frac_footprint"],
-                "mass_p2_2d_1024_kernel": minfo["kernel_hbm_frac_footprint"],
+                "cold": {n: hbm(extras[n + "_cold"]) for n in hbm_names},
+                "cold_kernel": {n: hbm(extras[n + "_cold"], True) for n in hbm_names},
+                "warm": {n: hbm(extras[n] if n != args.workload else main_info) for n in hbm_names},
+                "warm_kernel": {n: hbm(extras[n] if n != args.workload else main_info, True)
+                                for n in hbm_names},
             },
+            "mass_p2_2d_1024_vs_stream_copy": {"cold": mass_c["hbm_gbs_footprint"] / stream_gbs,
+                                               "warm": mass["hbm_gbs_footprint"] / stream_gbs},
+            "stream_copy_gbs": stream_gbs,
+            "fp64_roofline_frac": {
+                args.workload: main_info["fp64_frac"],
+                args.workload + "_kernel": main_info["kernel_fp64_frac"],
+                "elast_p2_3d": extras["elast_p2_3d"]["fp64_frac"],
+                "elast_p2_3d_kernel": extras["elast_p2_3d"]["kernel_fp64_frac"],
+                **({"nh_vjp": extras["vjp"]["fp64_frac"],
+                    "nh_vjp_kernel": extras["vjp"]["kernel_fp64_frac"]} if "vjp" in extras else {}),
+            },
+            "us_per_step": {n: 1e3 * extras[n]["ms_mean"] for n in ("mass_p2_2d", "elast_p2_3d",
+                                                                   "mass_p2_2d_1024")},
             "adjoint_forward_time_ratio": extras.get("adjoint_forward_time_ratio"),
             "batched_speedup": extras["batch"]["speedup_vs_per_mesh"] if "batch" in extras else None,
         },

@@ -235,9 +235,13 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *                       others leave as partial sums that a second, small kernel adds in
  *                       patch order.  The default.
  *   lanes_per_cell  1; 2 (2D vector forms: lane c of a pair owns component c); 3 (3D vector
- *                   forms: lane triples, 21 per wavefront).
+ *                   forms: lane triples, 21 per wavefront); 4 (vector forms on affine
+ *                   cells: the FP64 matrix-core kernel, where both contractions of the
+ *                   quadrature loop run as 16x16x4 MFMA tiles over 16 cells per wavefront
+ *                   and the pointwise form on the vector ALU, each cell's points and nodes
+ *                   spread over four lanes; coloured sums only).
  *   patch_cells     64, 128 or 256 with 1 or 2 lanes (at most 256 lanes per workgroup);
- *                   21, 42, 63 or 84 with 3.
+ *                   21, 42, 63 or 84 with 3; 64 with 4.
  *   sum_mode        FEM_SUM_ELEMENT: every cell vector to an LDS element buffer, each node
  *                   summing its slots in ascending (cell, local node); FEM_SUM_COLOURED:
  *                   cells greedily coloured inside the patch accumulate into an LDS node
@@ -280,7 +284,8 @@ int fem_plan_get_timing(fem_plan *plan, double *kernel_ms, int64_t *calls);
  * the fastest on the plan.  Candidates: the colour strategy with 64/128/256 cells per
  * workgroup; the patch strategy with 64/128/256 cells per patch and one lane per cell,
  * 64/128 with lane pairs (2D vector forms), 42/63/84 with lane triples (3D vector forms),
- * each with both sum modes.  The configuration the plan had on entry is kept unless a
+ * each with both sum modes; and the matrix-core kernel (vector forms on affine cells, 64
+ * cells per patch, coloured sums): the matrix cores on or off.  The configuration the plan had on entry is kept unless a
  * candidate is more than 3% faster.  Timing follows the paper's protocol (Sec. 6.2.1): 5 warm-up runs,
  * then timed runs until 15 are collected or 0.2 s accumulates, arithmetic mean, HIP
  * events on `stream`.  Synchronises; may rebuild the plan's patches (host work).
@@ -360,6 +365,34 @@ void fem_batch_destroy(fem_batch *batch);
 int fem_check_patch_layout(int form, int dim, int degree, int64_t n_vert, const double *coords,
                            int64_t n_cell, const int32_t *cell_verts, const int32_t *cell_nodes,
                            int64_t n_node, int patch_cells, int64_t *stats);
+
+/*
+ * The main kernel the plan's current configuration launches for fem_action (vjp = 0) or
+ * fem_action_vjp (vjp != 0): its registers per lane (hipFuncGetAttributes numRegs), its
+ * scratch (spill) bytes per lane, and 1 if it is the variant with wave-priority hints
+ * around its memory phases.  That variant of a coloured-sum patch kernel on affine cells
+ * runs only where its compiled form uses no scratch memory; the environment variable
+ * FEM_WAVE_PRIORITY=0 turns the hints off everywhere.  All outputs HOST, may be NULL.
+ * Errors: FEM_E_ARG, FEM_E_HIP (no device).
+ */
+int fem_plan_kernel_info(const fem_plan *plan, int vjp, int *regs, int *scratch_bytes,
+                         int *wave_priority);
+
+/*
+ * Measurement aids (the roofline's bandwidth input, paper Sec. 6.1: peak bandwidth is
+ * measured, not assumed).
+ * fem_stream_copy: dst[i] = src[i] for i < n, a STREAM-style copy that reads each byte of
+ *   src once and writes each byte of dst once (16-byte accesses, grid-stride).
+ *   src, dst  DEVICE f64 [n], 16-byte aligned, not overlapping.  Asynchronous on `stream`.
+ * fem_stream_read: reads src[0..n) once and writes one partial sum per workgroup to
+ *   sink[0..FEM_STREAM_SINK): a read-only pass that evicts the caches (L2 and the
+ *   memory-side cache) without leaving dirty lines to be written back later.
+ *   src DEVICE f64 [n], 16-byte aligned; sink DEVICE f64 [n_sink >= FEM_STREAM_SINK].
+ * Errors: FEM_E_ARG (nulls, misalignment, overlap, short sink), FEM_E_HIP.
+ */
+#define FEM_STREAM_SINK 2048
+int fem_stream_copy(const double *src, double *dst, int64_t n, void *stream);
+int fem_stream_read(const double *src, int64_t n, double *sink, int64_t n_sink, void *stream);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *fem_last_error(void);

@@ -112,6 +112,12 @@ def lib() -> ctypes.CDLL:
     L.fem_last_error.restype = ctypes.c_char_p
     L.fem_version.argtypes = []
     L.fem_version.restype = i32
+    L.fem_plan_kernel_info.argtypes = [P, i32, P, P, P]
+    L.fem_plan_kernel_info.restype = i32
+    L.fem_stream_copy.argtypes = [P, P, i64, P]
+    L.fem_stream_copy.restype = i32
+    L.fem_stream_read.argtypes = [P, i64, P, i64, P]
+    L.fem_stream_read.restype = i32
     _lib = L
     return L
 
@@ -184,6 +190,25 @@ def _dev_ptr(t, n: int, name: str) -> int:
     return t.data_ptr()
 
 
+STREAM_SINK = 2048
+
+
+
+def stream_copy(src, dst, stream=None):
+    """dst <- src through the library's STREAM-style copy kernel (float64 CUDA tensors)."""
+    n = src.numel()
+    _check(lib().fem_stream_copy(_dev_ptr(src, n, "src"), _dev_ptr(dst, n, "dst"), n,
+                                 _stream_handle(stream)))
+
+
+def stream_read(src, sink, stream=None):
+    """Read src once (a cache-evicting pass with no dirty lines); per-workgroup sums land
+    in sink (a float64 CUDA tensor of at least STREAM_SINK entries)."""
+    _check(lib().fem_stream_read(_dev_ptr(src, src.numel(), "src"), src.numel(),
+                                 _dev_ptr(sink, sink.numel(), "sink"), sink.numel(),
+                                 _stream_handle(stream)))
+
+
 class Plan:
     """A mesh + form + quadrature, validated, coloured and resident on the current device."""
 
@@ -250,6 +275,14 @@ class Plan:
         if self._h is None:
             raise RuntimeError("plan is closed")
         return self._h
+
+    def kernel_info(self, vjp: bool = False) -> dict:
+        """Registers, scratch bytes per lane and wave-priority flag of the main kernel the
+        current configuration launches."""
+        r, sc, pr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().fem_plan_kernel_info(self.handle, int(vjp), ctypes.byref(r), ctypes.byref(sc),
+                                          ctypes.byref(pr)))
+        return {"registers": r.value, "scratch_bytes": sc.value, "wave_priority": bool(pr.value)}
 
     def close(self):
         if getattr(self, "_h", None) is not None:

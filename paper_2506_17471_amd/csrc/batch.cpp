@@ -97,6 +97,8 @@ femx::PatchArgs patch_args(const fem_plan *p, const double *u, double *y)
     a.v = nullptr;
     a.y = y;
     a.partial = p->d_partial;
+    a.mtab = p->d_mtab;
+    a.nqt = p->nqt;
     a.stride = p->pstride;
     a.n_cell = p->n_cell;
     a.nq = p->nq;
@@ -247,7 +249,7 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             g.desc.push_back(d);
             g.n_patch += p->n_patch;
             g.members_lds_a.push_back(femx::patch_lds_a(p->form, p->dim, p->degree, false, p->patch,
-                                                        p->max_patch_nodes, p->sum_mode));
+                                                        p->max_patch_nodes, p->sum_mode, p->lanes));
             if (p->n_shared > 0) {
                 femx::FixDesc f{};
                 f.fix_node = p->d_fix_node;
@@ -269,7 +271,7 @@ int fem_batch_create(fem_batch **out, int n, fem_plan *const *plans, const doubl
             for (size_t k = 0; k < g.members.size(); ++k) {
                 const fem_plan *p = b->plans[g.members[k]];
                 const size_t bb = femx::patch_lds_bytes(p->form, p->dim, p->degree, false, p->patch,
-                                                        p->max_patch_nodes, p->sum_mode) -
+                                                        p->max_patch_nodes, p->sum_mode, p->lanes) -
                                   8 * g.members_lds_a[k];
                 b_max = std::max(b_max, bb);
                 g.desc[k].args.lds_a = (int)a_max;

@@ -46,6 +46,23 @@ bool has_symmetric_rule(int dim, int quad_degree);
 int table_record(int form, int dim, int nloc, int geom = 1);
 std::vector<double> kernel_table(int form, const RefTables &t, const RefTables *g = nullptr);
 
+// The matrix-core kernels' tabulation, per tile of 16 quadrature points (16 t .. 16 t + 15,
+// zero-padded past nq) in the operand order of v_mfma_f64_16x16x4_f64 (lane l holds
+// A[l % 16][l / 16]; the 16 x 16 result's register k of lane l is row 4 k + l / 16, column
+// l % 16):
+//   evaluation  [r][ks][64]: A[i][kk] = d phi_{4 ks + kk} / d xi_r at point 16 t + i
+//   contraction [k][r][m][64]: A[i][kk] = d phi_{16 m + i} / d xi_r at point 16 t + 4 k + kk
+//   weights [16]: w at point 16 t + i
+// (ks < mfma_ks = ceil(nloc / 4) k-steps of nodes, m < mfma_ma = ceil(nloc / 16) node tiles,
+// phi_a = 0 for a >= nloc).
+constexpr int mfma_ks(int nloc) { return (nloc + 3) / 4; }
+constexpr int mfma_ma(int nloc) { return (nloc + 15) / 16; }
+constexpr int mfma_tile_doubles(int dim, int nloc)
+{
+    return dim * mfma_ks(nloc) * 64 + 4 * dim * mfma_ma(nloc) * 64 + 16;
+}
+std::vector<double> mfma_table(const RefTables &t, int *n_tiles);
+
 // Launch parameters of one colour class.
 struct LaunchArgs {
     const int32_t *verts;     // SoA [(dim+1)][stride] colour-sorted vertex ids
@@ -83,9 +100,11 @@ struct PatchArgs {
     const double *v;
     double *y;
     double *partial;            // [n_partial][ncomp]
+    const double *mtab;         // matrix-core tabulation tiles (mfma_table), or null
     int64_t stride;
     int64_t n_cell;
     int nq;
+    int nqt;                    // point tiles of mtab
     int lds_a;                  // doubles of LDS region A (staging / element buffer)
     double lam, mu;
 };
@@ -129,6 +148,8 @@ struct fem_plan {
     int32_t *d_nodes = nullptr;
     uint64_t *d_first = nullptr;
     double *d_tab = nullptr;
+    double *d_mtab = nullptr;            // matrix-core tabulation (vector forms, affine cells)
+    int nqt = 0;                         // its 16-point tiles
     int32_t *d_untouched = nullptr;      // nodes no cell holds (zeroed separately)
     int64_t n_untouched = 0;
     // patch strategy
@@ -170,8 +191,9 @@ hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double 
 // LDS bytes the patch kernel needs for a patch of `patch` cells with at most
 // `max_nodes` distinct nodes.
 size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes,
-                       int sum_mode);
-size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode);
+                       int sum_mode, int lanes = 1);
+size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode,
+                   int lanes = 1);
 // start / stop (optional): events the dispatch itself stamps at the kernel's start and end
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
@@ -187,8 +209,16 @@ bool pair_available(int form, int dim, int degree);
 bool curved_available(int form, int dim, int degree);
 bool batch_available(int form, int dim, int degree, int lanes, int sum_mode);
 bool triple_available(int form, int dim, int degree);
+// the matrix-core patch kernel ("four lanes per cell": 16 cells per tile, each cell's points
+// and nodes over four lanes) of the vector forms on affine cells
+bool mfma_available(int form, int dim, int degree);
+constexpr int kMfmaLanes = 4;
 int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int lanes,
                      int sum_mode, int geom = 1);
+// registers per lane, scratch bytes per lane and whether the wave-priority variant runs, of
+// the kernel a configuration launches; -1 if that kernel is not built
+int kernel_info(int form, int dim, int degree, bool vjp, bool colour, int lanes, int sum_mode,
+                int geom, int *regs, int *scratch, int *prio);
 // geometry nodes of a cell: the d+1 vertices, or the P2 lattice of a curved cell
 inline int cell_geom_nodes(int dim, int geom) { return geom == 2 ? (dim == 2 ? 6 : 10) : dim + 1; }
 int patch_threads(int P, int lanes);
@@ -205,6 +235,10 @@ void apply_tuning_cache(fem_plan *p);
 int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
          hipStream_t s, double *results, int max_results, int *n_results, int max_timed);
 int tune_predict(const fem_plan *p, bool vjp, double *results, int max_results, int *n_results);
+// measurement aids (kernels.hip): STREAM copy and a read-only pass into per-block sums
+hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, hipStream_t s);
+hipError_t launch_stream_read(const double *src, int64_t n, double *sink, hipStream_t s);
+int stream_sink_size();
 hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off,
                         int64_t n_shared, const double *partial, int ncomp, double *y,
                         hipStream_t s);

@@ -35,8 +35,10 @@ using BatchFn = void (*)(const BatchDesc *, const int32_t *, int);
 
 struct Kernels {
     ColourFn colour;
-    PatchFn patch[4][3];  // [lanes per cell 1..3][sum mode 1..2], null where absent
-    BatchFn batch[4][3];
+    PatchFn patch[5][3];  // [lanes per cell 1..4][sum mode 1..2], null where absent; four
+    BatchFn batch[5][3];  //   lanes: the matrix-core kernel (coloured sums only)
+    PatchFn patch_prio[5];  // coloured sums with wave-priority hints, [lanes per cell]
+    BatchFn batch_prio[5];
     ColourFn colour_p2;   // P2-geometry cells: colour kernel and one-lane patch kernels
     PatchFn patch_p2[3];  // [sum mode 1..2]
 };
@@ -221,7 +223,7 @@ __device__ __forceinline__ void stage_copy(const T *__restrict__ src, int n, int
 // 3 for the 3D vector forms (lane c of a triple owns component c; a wavefront holds 21
 // triples and leaves its last lane idle).  SUM: SUM_ELEMENT (LDS element buffer and fixed-
 // order node sums) or SUM_COLOURED (sub-colour phases accumulating into an LDS node buffer).
-template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM, int GEO>
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM, int GEO, bool PRIO>
 __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
 {
     constexpr int NLOC = nloc_of(DIM, K);
@@ -246,12 +248,13 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
         comp = lane < 63 ? lane % 3 : 0;
         base = lane < 63 ? lane - comp : 0;
     }
-    // Wave priorities (coloured sums, affine cells): a workgroup's memory phases -- the
+    // Wave priorities (PRIO; coloured sums, affine cells): a workgroup's memory phases -- the
     // staging here, the sums and the write-out after its quadrature loop -- take issue
     // precedence over the loops of the other workgroups sharing the SIMD, so they overlap
-    // those loops rather than wait behind them.  The curved-cell kernels keep the default
-    // priority (the hints reshuffle their register allocation, already spilling).
-    constexpr bool kPrio = SUM == SUM_COLOURED && GEO == 1;
+    // those loops rather than wait behind them.  Both variants are built; the launchers run
+    // the hinted one only where the compiled kernel uses no scratch memory (no spills).
+    static_assert(!PRIO || (SUM == SUM_COLOURED && GEO == 1), "hints: coloured affine kernels");
+    constexpr bool kPrio = PRIO;
     if constexpr (kPrio) __builtin_amdgcn_s_setprio(2);
     const int nb = a.patch_off[p];
     const int U = a.patch_off[p + 1] - nb;
@@ -414,17 +417,17 @@ __device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n)
     return x * q + (x < r ? x : r) + i;
 }
 
-template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM, int GEO>
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM, int GEO, bool PRIO = false>
 __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC, GEO))))
     patch_kernel(const PatchArgs a, int P)
 {
-    patch_body<FORM, DIM, K, VJP, LPC, SUM, GEO>(a, xcd_order(blockIdx.x, gridDim.x), P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM, GEO, PRIO>(a, xcd_order(blockIdx.x, gridDim.x), P);
 }
 
 // Many meshes of one kernel variant in one launch: workgroup b works on patch
 // b - desc[m].first_patch of mesh m = patch_mesh[b].
-template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM>
+template <int FORM, int DIM, int K, bool VJP, int LPC, int SUM, bool PRIO = false>
 __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(waves_target(FORM, DIM, K, VJP, LPC))))
     batch_patch_kernel(const BatchDesc *__restrict__ desc, const int32_t *__restrict__ patch_mesh,
@@ -433,17 +436,27 @@ __global__ void __launch_bounds__(kMaxBlock)
     const int64_t b = xcd_order(blockIdx.x, gridDim.x);
     const int m = patch_mesh[b];
     const BatchDesc &d = desc[m];
-    patch_body<FORM, DIM, K, VJP, LPC, SUM, 1>(d.args, b - d.first_patch, P);
+    patch_body<FORM, DIM, K, VJP, LPC, SUM, 1, PRIO>(d.args, b - d.first_patch, P);
 }
+
+}  // namespace
+}  // namespace femx
+
+#include "mfma_patch.h"
+
+namespace femx {
+namespace {
 
 template <int FORM, int DIM, int K, bool VJP, int LPC, bool BATCH>
 void fill_lanes(Kernels &k)
 {
     k.patch[LPC][SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT, 1>;
     k.patch[LPC][SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED, 1>;
+    k.patch_prio[LPC] = patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED, 1, true>;
     if constexpr (BATCH) {
         k.batch[LPC][SUM_ELEMENT] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_ELEMENT>;
         k.batch[LPC][SUM_COLOURED] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED>;
+        k.batch_prio[LPC] = batch_patch_kernel<FORM, DIM, K, VJP, LPC, SUM_COLOURED, true>;
     }
 }
 
@@ -465,6 +478,10 @@ Kernels entry()
     }
     if constexpr (DIM == 2 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 2, FULL>(k);
     if constexpr (DIM == 3 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 3, FULL>(k);
+    if constexpr (!scalar_form(FORM)) {
+        k.patch[kMfmaLanes][SUM_COLOURED] = mfma_patch_kernel<FORM, DIM, K, VJP>;
+        if constexpr (FULL) k.batch[kMfmaLanes][SUM_COLOURED] = mfma_batch_kernel<FORM, DIM, K, VJP>;
+    }
     return k;
 }
 

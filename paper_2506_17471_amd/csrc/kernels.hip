@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
+#include <map>
 #include <mutex>
 #include <set>
 
@@ -60,6 +62,57 @@ __global__ void zero_nodes_kernel(const int32_t *__restrict__ nodes, int64_t n, 
     for (int c = 0; c < ncomp; ++c) y[nd * ncomp + c] = 0.0;
 }
 
+// Measurement aids: the achievable HBM bandwidth (a STREAM-style copy, every byte read
+// once and written once) and a read-only pass (each workgroup's sum of its share written to
+// sink[block]) that evicts the caches without leaving dirty lines behind.  Grid-stride over
+// 16-byte elements, four in flight per lane; the scalar tail (n odd) goes to the last lane.
+constexpr int kStreamBlock = 256;
+
+__global__ void __launch_bounds__(kStreamBlock)
+    stream_copy_kernel(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2,
+                       const double *__restrict__ tail_src, double *__restrict__ tail_dst)
+{
+    const int64_t stride = (int64_t)gridDim.x * kStreamBlock;
+    int64_t i = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+    for (; i + 3 * stride < n2; i += 4 * stride) {
+        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                      d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n2; i += stride) dst[i] = src[i];
+    if (tail_src && blockIdx.x == gridDim.x - 1 && threadIdx.x == kStreamBlock - 1) *tail_dst = *tail_src;
+}
+
+__global__ void __launch_bounds__(kStreamBlock)
+    stream_read_kernel(const double2 *__restrict__ src, int64_t n2, const double *__restrict__ tail,
+                       double *__restrict__ sink)
+{
+    __shared__ double part[kStreamBlock / 64];
+    const int64_t stride = (int64_t)gridDim.x * kStreamBlock;
+    int64_t i = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (; i + 3 * stride < n2; i += 4 * stride) {
+        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                      d = src[i + 3 * stride];
+        acc0 += (a.x + a.y) + (b.x + b.y);
+        acc1 += (c.x + c.y) + (d.x + d.y);
+    }
+    for (; i < n2; i += stride) acc0 += src[i].x + src[i].y;
+    double v = acc0 + acc1;
+    if (tail && blockIdx.x == gridDim.x - 1 && threadIdx.x == kStreamBlock - 1) v += *tail;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kStreamBlock / 64; ++w) t += part[w];
+        sink[blockIdx.x] = t;
+    }
+}
+
 Kernels lookup(int form, int dim, int degree, bool vjp)
 {
     switch (form) {
@@ -74,6 +127,44 @@ Kernels lookup(int form, int dim, int degree, bool vjp)
 }
 
 }  // namespace
+
+// The wave-priority variant of a coloured affine patch kernel runs only where its compiled
+// form uses no scratch memory (spill-free); FEM_WAVE_PRIORITY=0 in the environment turns the
+// hints off everywhere.  Decided once per kernel (function attributes, no launch).
+static bool prio_usable(const void *hinted)
+{
+    if (!hinted) return false;
+    static const bool enabled = [] {
+        const char *e = std::getenv("FEM_WAVE_PRIORITY");
+        return !(e && e[0] == '0');
+    }();
+    if (!enabled) return false;
+    static std::mutex mu;
+    static std::map<const void *, bool> known;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = known.find(hinted);
+    if (it != known.end()) return it->second;
+    hipFuncAttributes attr{};
+    bool ok = false;
+    if (hipFuncGetAttributes(&attr, hinted) == hipSuccess) ok = attr.localSizeBytes == 0;
+    else (void)hipGetLastError();
+    known.emplace(hinted, ok);
+    return ok;
+}
+
+// the patch kernel a plan's configuration launches (geom 2: the one-lane curved kernels)
+static const void *patch_fn(const Kernels &ks, int geom, int lanes, int sum_mode,
+                            bool *prio = nullptr)
+{
+    if (prio) *prio = false;
+    if (lanes < 1 || lanes > kMfmaLanes || sum_mode < 1 || sum_mode > 2) return nullptr;
+    if (geom == 2) return lanes == 1 ? (const void *)ks.patch_p2[sum_mode] : nullptr;
+    if (sum_mode == SUM_COLOURED && prio_usable((const void *)ks.patch_prio[lanes])) {
+        if (prio) *prio = true;
+        return (const void *)ks.patch_prio[lanes];
+    }
+    return (const void *)ks.patch[lanes][sum_mode];
+}
 
 bool kernel_available(int form, int dim, int degree)
 {
@@ -96,11 +187,15 @@ hipError_t launch_action(const fem_plan &p, const LaunchArgs &a, int block, bool
 
 // LDS region A (doubles): the staged nodal values, then the element buffer (SUM_ELEMENT)
 // or the node accumulator (SUM_COLOURED), which fits in the staging space.
-size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode)
+// (the matrix-core kernel reads the staged values through its whole loop and reuses the
+// space for the node accumulator after it: the coloured sums' size)
+size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode,
+                   int lanes)
 {
     const int nloc = nloc_of(dim, degree);
     const int nc = ncomp_of(form, dim);
     const size_t stage = (size_t)max_nodes * nc * (vjp ? 2 : 1);
+    if (lanes == kMfmaLanes) return stage;
     if (sum_mode == SUM_COLOURED) return stage;
     const size_t elem = (size_t)patch * nloc * nc;
     return stage > elem ? stage : elem;
@@ -108,12 +203,12 @@ size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_n
 
 // Region B (bytes): node ids, plus for the element buffer the relative sum offsets and slots.
 size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int max_nodes,
-                       int sum_mode)
+                       int sum_mode, int lanes)
 {
     const int nloc = nloc_of(dim, degree);
     size_t b = 4 * (size_t)max_nodes;
     if (sum_mode == SUM_ELEMENT) b += 4 * ((size_t)max_nodes + 1) + 2 * (size_t)patch * nloc;
-    return 8 * patch_lds_a(form, dim, degree, vjp, patch, max_nodes, sum_mode) +
+    return 8 * patch_lds_a(form, dim, degree, vjp, patch, max_nodes, sum_mode, lanes) +
            ((b + 7) & ~(size_t)7);
 }
 
@@ -134,6 +229,11 @@ bool pair_available(int form, int dim, int degree)
     return lookup(form, dim, degree, false).patch[2][SUM_ELEMENT] != nullptr;
 }
 
+bool mfma_available(int form, int dim, int degree)
+{
+    return lookup(form, dim, degree, false).patch[kMfmaLanes][SUM_COLOURED] != nullptr;
+}
+
 bool triple_available(int form, int dim, int degree)
 {
     return lookup(form, dim, degree, false).patch[3][SUM_ELEMENT] != nullptr;
@@ -145,13 +245,12 @@ int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int l
                      int sum_mode, int geom)
 {
     const Kernels ks = lookup(form, dim, degree, vjp);
-    const bool ok = lanes >= 1 && lanes <= 3 && sum_mode >= 1 && sum_mode <= 2;
+    const bool ok = lanes >= 1 && lanes <= kMfmaLanes && sum_mode >= 1 && sum_mode <= 2;
     const void *fn = nullptr;
-    if (geom == 2)
-        fn = colour ? (const void *)ks.colour_p2
-                    : (ok && lanes == 1 ? (const void *)ks.patch_p2[sum_mode] : nullptr);
-    else
-        fn = colour ? (const void *)ks.colour : (ok ? (const void *)ks.patch[lanes][sum_mode] : nullptr);
+    if (colour)
+        fn = geom == 2 ? (const void *)ks.colour_p2 : (const void *)ks.colour;
+    else if (ok)
+        fn = patch_fn(ks, geom, lanes, sum_mode);
     if (!fn) return 0;
     hipFuncAttributes attr{};
     if (hipFuncGetAttributes(&attr, fn) != hipSuccess) {
@@ -161,7 +260,27 @@ int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int l
     return attr.numRegs;
 }
 
-// threads of a patch workgroup: P * lanes, or 64 per 21 cells for lane triples
+int kernel_info(int form, int dim, int degree, bool vjp, bool colour, int lanes, int sum_mode,
+                int geom, int *regs, int *scratch, int *prio)
+{
+    const Kernels ks = lookup(form, dim, degree, vjp);
+    bool hinted = false;
+    const void *fn = colour ? (geom == 2 ? (const void *)ks.colour_p2 : (const void *)ks.colour)
+                            : patch_fn(ks, geom, lanes, sum_mode, &hinted);
+    if (!fn) return -1;
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, fn) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    if (regs) *regs = attr.numRegs;
+    if (scratch) *scratch = (int)attr.localSizeBytes;
+    if (prio) *prio = hinted ? 1 : 0;
+    return 0;
+}
+
+// threads of a patch workgroup: P * lanes, 64 per 21 cells for lane triples, 256 (16 cells
+// per wavefront) for the matrix-core kernel
 int patch_threads(int P, int lanes)
 {
     return lanes == 3 ? 64 * ((P + 20) / 21) : P * lanes;
@@ -183,10 +302,12 @@ hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patc
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
                               size_t lds, hipStream_t s)
 {
-    if (lanes < 1 || lanes > 3 || (sum_mode != SUM_ELEMENT && sum_mode != SUM_COLOURED))
+    if (lanes < 1 || lanes > kMfmaLanes || (sum_mode != SUM_ELEMENT && sum_mode != SUM_COLOURED))
         return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(form, dim, degree, false);
     BatchFn fn = ks.batch[lanes][sum_mode];
+    if (sum_mode == SUM_COLOURED && prio_usable((const void *)ks.batch_prio[lanes]))
+        fn = ks.batch_prio[lanes];
     if (!fn) return hipErrorInvalidDeviceFunction;
     const int threads = patch_threads(patch, lanes);
     if (patch < 1 || patch > 256 || threads > kMaxBlock || lds > 160 * 1024 || n_patch > 0x7fffffff)
@@ -208,17 +329,19 @@ hipError_t launch_batch_fixup(const FixDesc *fix, int n_mesh, int64_t n, hipStre
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s,
                         hipEvent_t start, hipEvent_t stop)
 {
-    if (p.lanes < 1 || p.lanes > 3 || (p.sum_mode != SUM_ELEMENT && p.sum_mode != SUM_COLOURED))
+    if (p.lanes < 1 || p.lanes > kMfmaLanes ||
+        (p.sum_mode != SUM_ELEMENT && p.sum_mode != SUM_COLOURED))
+        return hipErrorInvalidConfiguration;
+    if (p.lanes == kMfmaLanes && (p.patch != 64 || !a.mtab || a.nqt < 1))
         return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(p.form, p.dim, p.degree, vjp);
     // curved cells run the one-lane kernels only
-    PatchFn fn = p.geom == 2 ? (p.lanes == 1 ? ks.patch_p2[p.sum_mode] : nullptr)
-                             : ks.patch[p.lanes][p.sum_mode];
+    PatchFn fn = (PatchFn)patch_fn(ks, p.geom, p.lanes, p.sum_mode);
     if (!fn) return hipErrorInvalidDeviceFunction;
     const int threads = patch_threads(p.patch, p.lanes);
     if (p.patch < 1 || p.patch > 256 || threads > kMaxBlock) return hipErrorInvalidConfiguration;
     const size_t lds = patch_lds_bytes(p.form, p.dim, p.degree, vjp, p.patch, p.max_patch_nodes,
-                                       p.sum_mode);
+                                       p.sum_mode, p.lanes);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
     hipError_t e = allow_lds((const void *)fn, lds);
     if (e != hipSuccess) return e;
@@ -244,6 +367,30 @@ hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t
                        n_shared, partial, ncomp, y);
     return hipGetLastError();
 }
+
+// 2048 workgroups of 256 lanes: 8 per CU on the 256 CUs, enough loads in flight to cover
+// HBM latency with the loop's four 16-byte loads per lane.
+constexpr int kStreamGrid = 2048;
+
+hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, hipStream_t s)
+{
+    const int64_t n2 = n / 2;
+    const bool odd = n & 1;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(kStreamGrid), dim3(kStreamBlock), 0, s,
+                       (const double2 *)src, (double2 *)dst, n2, odd ? src + n - 1 : nullptr,
+                       odd ? dst + n - 1 : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_read(const double *src, int64_t n, double *sink, hipStream_t s)
+{
+    const int64_t n2 = n / 2;
+    hipLaunchKernelGGL(stream_read_kernel, dim3(kStreamGrid), dim3(kStreamBlock), 0, s,
+                       (const double2 *)src, n2, (n & 1) ? src + n - 1 : nullptr, sink);
+    return hipGetLastError();
+}
+
+int stream_sink_size() { return kStreamGrid; }
 
 hipError_t launch_zero_nodes(const int32_t *nodes, int64_t n, int ncomp, double *y,
                              hipStream_t s)

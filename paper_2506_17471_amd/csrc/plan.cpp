@@ -156,6 +156,7 @@ void free_plan_memory(fem_plan *p)
     (void)hipFree(p->d_nodes);
     (void)hipFree(p->d_first);
     (void)hipFree(p->d_tab);
+    (void)hipFree(p->d_mtab);
     (void)hipFree(p->d_untouched);
     free_patch_memory(p);
 }
@@ -250,6 +251,16 @@ std::vector<double> plan_tables(const fem_plan *p, int family, const double *coo
     return femx::kernel_table(p->form, t, &g);
 }
 
+// The matrix-core kernels' tabulation on the rule of `family` (vector forms on affine cells
+// whose kernel is built; empty otherwise).
+std::vector<double> plan_mfma_table(const fem_plan *p, int family, int *n_tiles)
+{
+    *n_tiles = 0;
+    if (p->geom != 1 || !femx::mfma_available(p->form, p->dim, p->degree)) return {};
+    femx::RefTables t = femx::reference_tables(p->dim, p->degree, p->quad_degree, family);
+    return femx::mfma_table(t, n_tiles);
+}
+
 // Host-side validation of the mesh; runs before any HIP call.
 void validate_mesh(fem_plan *p, const double *coords, const int32_t *cell_verts,
                    const int32_t *cell_nodes, const double *params, int n_params)
@@ -341,6 +352,7 @@ void build_plan(fem_plan *p, const double *coords, const int32_t *cell_verts,
     p->d_nodes = device_upload(nodes, "cell_nodes");
     p->d_first = device_upload(first, "first-touch masks");
     p->d_tab = device_upload(tab, "tables");
+    p->d_mtab = device_upload(plan_mfma_table(p, p->quad_family, &p->nqt), "matrix-core tables");
     p->d_untouched = device_upload(untouched, "untouched nodes");
     p->lanes = default_lanes(p);
     p->sum_mode = default_sum_mode(p);
@@ -713,11 +725,13 @@ int default_lanes(const fem_plan *p)
 bool patch_allowed(int P, int lanes)
 {
     if (lanes == 3) return P == 21 || P == 42 || P == 63 || P == 84;
+    if (lanes == femx::kMfmaLanes) return P == 64;
     return (P == 64 || P == 128 || P == 256) && P * lanes <= 256;
 }
 
 int default_patch_for(const fem_plan *p, int lanes, int sum_mode)
 {
+    if (lanes == femx::kMfmaLanes) return 64;   // four wavefronts of 16 cells
     // lane triples with coloured sums: two wavefronts per patch measured best (P4 elasticity)
     if (lanes == 3 && sum_mode == femx::SUM_COLOURED) return 42;
     // the largest allowed patch whose element buffer (the larger LDS need) fits 64 KB
@@ -748,7 +762,10 @@ void check_unbatched(const fem_plan *p)
         throw femx::Error(FEM_E_ARG, "the plan is held by a batch; destroy the batch first");
 }
 
-void run(const fem_plan *p, const double *u, const double *v, double *y, void *stream, bool vjp)
+// partial: the shared nodes' partial sums (the plan's own buffer unless given); timed: the
+// plan's kernel timing applies (off for the allocation-free entry point)
+void run(const fem_plan *p, const double *u, const double *v, double *y, void *stream, bool vjp,
+         double *partial = nullptr, bool timed = true)
 {
     using femx::Error;
     check_plan(p);
@@ -783,21 +800,24 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         a.u = in;
         a.v = nl_vjp ? v : nullptr;
         a.y = y;
-        a.partial = p->d_partial;
+        a.partial = partial ? partial : p->d_partial;
+        a.mtab = p->d_mtab;
+        a.nqt = p->nqt;
         a.stride = p->pstride;
         a.n_cell = p->n_cell;
         a.nq = p->nq;
         a.lds_a = (int)femx::patch_lds_a(p->form, p->dim, p->degree, nl_vjp, p->patch,
-                                         p->max_patch_nodes, p->sum_mode);
+                                         p->max_patch_nodes, p->sum_mode, p->lanes);
         a.lam = p->lam;
         a.mu = p->mu;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-        if (p->timing) ev = timing_pair(p);
+        const bool timing = timed && p->timing;
+        if (timing) ev = timing_pair(p);
         femx::check_hip(femx::launch_patch(*p, a, nl_vjp, s, ev.first, ev.second), "patch launch");
-        if (p->timing) p->timing_pending.push_back(ev);
+        if (timing) p->timing_pending.push_back(ev);
         if (p->n_shared > 0)
             femx::check_hip(femx::launch_fixup(p->d_fix_node, p->d_fix_off,
-                                               p->n_shared, p->d_partial, p->ncomp, y, s),
+                                               p->n_shared, a.partial, p->ncomp, y, s),
                             "fixup launch");
         return;
     }
@@ -815,7 +835,8 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
     a.u = in;
     a.v = nl_vjp ? v : nullptr;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    if (p->timing) {
+    const bool timing = timed && p->timing;
+    if (timing) {
         ev = timing_pair(p);
         femx::check_hip(hipEventRecord(ev.first, s), "hipEventRecord");
     }
@@ -825,7 +846,7 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
         if (a.count == 0) continue;
         femx::check_hip(femx::launch_action(*p, a, p->block, nl_vjp, s), "action launch");
     }
-    if (p->timing) {
+    if (timing) {
         femx::check_hip(hipEventRecord(ev.second, s), "hipEventRecord");
         p->timing_pending.push_back(ev);
     }
@@ -851,7 +872,12 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
         lanes = default_lanes(plan);
         if (patch_cells != 0 && !patch_allowed(patch_cells, lanes)) lanes = 1;
     }
-    if (lanes < 1 || lanes > 3) throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1, 2 or 3");
+    if (lanes < 1 || lanes > kMfmaLanes)
+        throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1, 2, 3 or 4");
+    if (lanes == kMfmaLanes && (plan->geom != 1 || !mfma_available(plan->form, plan->dim, plan->degree)))
+        throw Error(FEM_E_UNSUPPORTED,
+                    "the matrix-core kernel (four lanes per cell) exists for the vector forms on "
+                    "affine cells only");
     if (lanes > 1 && plan->geom == 2)
         throw Error(FEM_E_UNSUPPORTED, "curved cells run one lane per cell");
     if (lanes == 2 && !pair_available(plan->form, plan->dim, plan->degree))
@@ -860,26 +886,42 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
         throw Error(FEM_E_UNSUPPORTED, "three lanes per cell exist for the 3D vector forms only");
     const int mode = sum_mode == 0 ? default_sum_mode(plan) : sum_mode;
     if (mode != SUM_ELEMENT && mode != SUM_COLOURED) throw Error(FEM_E_ARG, "unknown sum mode");
+    if (lanes == kMfmaLanes && mode != SUM_COLOURED)
+        throw Error(FEM_E_UNSUPPORTED, "the matrix-core kernel sums by sub-colours only");
     const int P = patch_cells == 0 ? default_patch_for(plan, lanes, mode) : patch_cells;
     if (!patch_allowed(P, lanes))
         throw Error(FEM_E_ARG, "patch_cells must be 64, 128 or 256 (at most 256 lanes) for one or "
-                               "two lanes per cell, and 21, 42, 63 or 84 for three");
+                               "two lanes per cell, 21, 42, 63 or 84 for three, and 64 for four");
     const size_t lds = patch_lds_bytes(plan->form, plan->dim, plan->degree,
                                        femx::nonlinear_form(plan->form), P,
-                                       P == plan->patch ? plan->max_patch_nodes : 0, mode);
+                                       P == plan->patch ? plan->max_patch_nodes : 0, mode, lanes);
     if (P == plan->patch && lds > 160 * 1024)
-        throw Error(FEM_E_UNSUPPORTED, "this sum mode needs more than 160 KB of LDS");
+        throw Error(FEM_E_UNSUPPORTED, "this configuration needs more than 160 KB of LDS");
     const int old_mode = plan->sum_mode;
     plan->sum_mode = mode;
     if (P != plan->patch) {
         if (plan->h_cell_verts.empty()) throw Error(FEM_E_ARG, "plan keeps no host mesh");
         check_hip(hipDeviceSynchronize(), "synchronise before rebuilding patches");
+        const int old_patch = plan->patch;
         try {
             build_patches(plan, plan->h_coords.data(), plan->h_cell_verts.data(),
                           plan->h_cell_nodes.data(), P);
         } catch (...) {
             plan->sum_mode = old_mode;
             throw;
+        }
+        // the new layout's largest patch decides the LDS need of this lane split (the
+        // hyperelastic forms' VJP staging two vectors); past 160 KB, back to the old layout
+        const size_t need = patch_lds_bytes(plan->form, plan->dim, plan->degree,
+                                            femx::nonlinear_form(plan->form), P,
+                                            plan->max_patch_nodes, mode, lanes);
+        if (need > 160 * 1024) {
+            plan->sum_mode = old_mode;
+            if (old_patch > 0)
+                build_patches(plan, plan->h_coords.data(), plan->h_cell_verts.data(),
+                              plan->h_cell_nodes.data(), old_patch);
+            throw Error(FEM_E_UNSUPPORTED, "this configuration needs " + std::to_string(need) +
+                                               " bytes of LDS per workgroup, more than 160 KB");
         }
     }
     plan->lanes = lanes;
@@ -1167,11 +1209,23 @@ int fem_plan_set_quadrature(fem_plan *plan, int family)
         int nq = 0;
         std::vector<double> tab = plan_tables(plan, family, plan->h_coords.data(),
                                               plan->h_cell_verts.data(), true, &nq);
+        int nqt = 0;
+        std::vector<double> mtab = plan_mfma_table(plan, family, &nqt);
         double *d = device_upload(tab, "tables");
+        double *dm = nullptr;
+        try {
+            dm = device_upload(mtab, "matrix-core tables");
+        } catch (...) {
+            (void)hipFree(d);
+            throw;
+        }
         femx::check_hip(hipDeviceSynchronize(), "synchronise before replacing tables");
         (void)hipFree(plan->d_tab);
+        (void)hipFree(plan->d_mtab);
         plan->d_tab = d;
+        plan->d_mtab = dm;
         plan->nq = nq;
+        plan->nqt = nqt;
         plan->quad_family = family;
     });
 }
@@ -1219,6 +1273,45 @@ int fem_plan_get_strategy(const fem_plan *plan, int *strategy, int *patch_cells,
         if (patch_cells) *patch_cells = patch ? plan->patch : 0;
         if (lanes_per_cell) *lanes_per_cell = patch ? plan->lanes : 1;
         if (sum_mode) *sum_mode = patch ? plan->sum_mode : 0;
+    });
+}
+
+int fem_plan_kernel_info(const fem_plan *plan, int vjp, int *regs, int *scratch_bytes,
+                         int *wave_priority)
+{
+    return guarded([&] {
+        check_plan(plan);
+        const bool nl_vjp = vjp && femx::nonlinear_form(plan->form);
+        const bool colour = plan->strategy == femx::STRAT_COLOUR || plan->patch == 0;
+        if (femx::kernel_info(plan->form, plan->dim, plan->degree, nl_vjp, colour, plan->lanes,
+                              plan->sum_mode, plan->geom, regs, scratch_bytes, wave_priority) != 0)
+            throw femx::Error(FEM_E_HIP, "kernel attributes unavailable");
+    });
+}
+
+int fem_stream_copy(const double *src, double *dst, int64_t n, void *stream)
+{
+    return guarded([&] {
+        if (n < 0) throw femx::Error(FEM_E_ARG, "negative length");
+        if (n == 0) return;
+        if (!src || !dst) throw femx::Error(FEM_E_ARG, "null buffer");
+        if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+            throw femx::Error(FEM_E_ARG, "buffers must be 16-byte aligned");
+        if (src < dst + n && dst < src + n) throw femx::Error(FEM_E_ARG, "buffers overlap");
+        femx::check_hip(femx::launch_stream_copy(src, dst, n, (hipStream_t)stream), "stream copy");
+    });
+}
+
+int fem_stream_read(const double *src, int64_t n, double *sink, int64_t n_sink, void *stream)
+{
+    return guarded([&] {
+        if (n < 0) throw femx::Error(FEM_E_ARG, "negative length");
+        if (!src || !sink) throw femx::Error(FEM_E_ARG, "null buffer");
+        if (n_sink < femx::stream_sink_size())
+            throw femx::Error(FEM_E_ARG, "the sink needs FEM_STREAM_SINK doubles");
+        if (reinterpret_cast<uintptr_t>(src) & 15)
+            throw femx::Error(FEM_E_ARG, "src must be 16-byte aligned");
+        femx::check_hip(femx::launch_stream_read(src, n, sink, (hipStream_t)stream), "stream read");
     });
 }
 

@@ -560,6 +560,34 @@ std::vector<double> kernel_table(int form, const RefTables &t, const RefTables *
     return out;
 }
 
+std::vector<double> mfma_table(const RefTables &t, int *n_tiles)
+{
+    const int d = t.dim, n = t.nloc, ks = mfma_ks(n), ma = mfma_ma(n);
+    const int nt = (t.nq + 15) / 16, tile = mfma_tile_doubles(d, n);
+    std::vector<double> out((size_t)nt * tile, 0.0);
+    auto dphi = [&](int q, int a, int r) {
+        return (q < t.nq && a < n) ? t.dphi[((size_t)q * n + a) * d + r] : 0.0;
+    };
+    for (int tt = 0; tt < nt; ++tt) {
+        double *o = &out[(size_t)tt * tile];
+        for (int r = 0; r < d; ++r)
+            for (int s = 0; s < ks; ++s)
+                for (int l = 0; l < 64; ++l)
+                    o[(r * ks + s) * 64 + l] = dphi(16 * tt + l % 16, 4 * s + l / 16, r);
+        double *c = o + d * ks * 64;
+        for (int k = 0; k < 4; ++k)
+            for (int r = 0; r < d; ++r)
+                for (int m = 0; m < ma; ++m)
+                    for (int l = 0; l < 64; ++l)
+                        c[((k * d + r) * ma + m) * 64 + l] =
+                            dphi(16 * tt + 4 * k + l / 16, 16 * m + l % 16, r);
+        double *w = c + 4 * d * ma * 64;
+        for (int i = 0; i < 16; ++i) w[i] = 16 * tt + i < t.nq ? t.weights[16 * tt + i] : 0.0;
+    }
+    *n_tiles = nt;
+    return out;
+}
+
 bool has_symmetric_rule(int dim, int quad_degree)
 {
     std::vector<double> p, w;

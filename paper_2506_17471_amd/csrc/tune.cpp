@@ -172,6 +172,9 @@ std::vector<Candidate> candidates(const fem_plan *p)
     for (int P : {64, 128, 256})
         for (int m : {SUM_ELEMENT, SUM_COLOURED}) cands.push_back({FEM_SCATTER_PATCH, P, 1, 0, m});
     if (p->geom == 2) return cands;     // curved cells: one lane per cell
+    // the matrix-core kernel: 64-cell patches, coloured sums
+    if (mfma_available(p->form, p->dim, p->degree) && p->nqt > 0)
+        cands.push_back({FEM_SCATTER_PATCH, 64, kMfmaLanes, 0, SUM_COLOURED});
     if (pair_available(p->form, p->dim, p->degree))
         for (int P : {64, 128})
             for (int m : {SUM_ELEMENT, SUM_COLOURED})
@@ -233,7 +236,8 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
         const double P = c.patch;
         const double share = d == 2 ? 2.5 / std::sqrt(P) : 4.0 / std::cbrt(P);
         const int U = (int)(P * nodes_per_cell * (1.0 + share)) + 8;
-        const size_t lds = patch_lds_bytes(p->form, p->dim, p->degree, nl, c.patch, U, c.sum_mode);
+        const size_t lds = patch_lds_bytes(p->form, p->dim, p->degree, nl, c.patch, U, c.sum_mode,
+                                           c.lanes);
         const double wgs_lds = std::floor(160.0 * 1024 / std::max<size_t>(1, lds));
         const double wave_per_wg = std::ceil(patch_threads(c.patch, c.lanes) / 64.0);
         waves = std::min(waves, wgs_lds * wave_per_wg / 4.0);
@@ -249,7 +253,19 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
         extra_bytes = 2.0 * n * nloc * nc * 8.0;          // gathers and read-add-writes
     }
     const double eta = std::min(1.0, std::max(waves, 0.25) / 3.0);
-    const double t_valu = n * instr * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
+    double t_valu = n * instr * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
+    if (c.lanes == kMfmaLanes) {
+        // matrix cores: per 16 cells and point tile, d^2 k-steps of the evaluation (twice for
+        // the VJP) and 4 d^2 node tiles of the contraction, 64 cycles each on one SIMD; the
+        // pointwise work on the vector ALU at every padded point, half of it overlapped
+        const double ks = mfma_ks(p->nloc), ma = mfma_ma(p->nloc), tiles = p->nqt;
+        const double ops = tiles * (d * d * ks * (nl ? 2 : 1) + 4.0 * d * d * ma);
+        const double t_mfma = n / 16.0 * ops * 64.0 / (1024.0 * 2.4e9) / eta;
+        const double ev = 2 * d * d * nloc * (nl ? 2 : 1), ct = 2 * d * d * nloc;
+        const double pw = flops_per_point(p->form, p->dim, p->nloc, nl) - ev - ct;
+        const double t_pw = n * 16.0 * tiles * pw / 2.0 * 1.25 * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
+        t_valu = t_mfma + 0.5 * t_pw;
+    }
     const double bytes = vec_bytes * (nl ? 3 : 2) + 8.0 * d * p->n_vert +
                          4.0 * (nloc + ng) * n + extra_bytes;
     // memory-level parallelism: fewer than six resident waves per SIMD (an LDS-hungry

@@ -125,6 +125,14 @@ def test_error_paths_from_host():
     assert st1 == -2
     assert L.fem_plan_set_timing(None, 1) == -1
     assert L.fem_plan_get_timing(None, None, None) == -1
+    assert L.fem_plan_destroy(None) == 0
+    # measurement aids: argument checks before any launch
+    assert L.fem_stream_copy(None, None, 4, None) == -1
+    assert L.fem_stream_copy(None, None, 0, None) == 0
+    assert L.fem_stream_copy(16, 24, 4, None) == -1 and "aligned" in L.fem_last_error().decode()
+    assert L.fem_stream_copy(16, 32, 4, None) == -1 and "overlap" in L.fem_last_error().decode()
+    assert L.fem_stream_read(None, 4, None, 0, None) == -1
+    assert L.fem_stream_read(16, 4, 32, fx.STREAM_SINK - 1, None) == -1
 
 
 def _create_curved(mesh, gcoords=None, cell_gnodes=None, form=0, degree=2, qd=4):

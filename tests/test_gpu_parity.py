@@ -94,19 +94,29 @@ def plan_family(w):
 STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_ELEMENT),
           (fx.SCATTER_PATCH, 128, 1, fx.SUM_COLOURED), (fx.SCATTER_COLOUR, 0, 0, 0),
           (fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 63, 3, fx.SUM_COLOURED),
-          (fx.SCATTER_PATCH, 64, 2, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 128, 2, fx.SUM_COLOURED)]
+          (fx.SCATTER_PATCH, 64, 2, fx.SUM_ELEMENT), (fx.SCATTER_PATCH, 128, 2, fx.SUM_COLOURED),
+          (fx.SCATTER_PATCH, 64, 4, fx.SUM_COLOURED)]
 STRAT_IDS = ["patch", "patch64x1e", "patch128x1c", "colour", "patch42x3e", "patch63x3c",
-             "patch64x2e", "patch128x2c"]
+             "patch64x2e", "patch128x2c", "mfma64"]
 
 
 def apply_strategy(plan, strategy, form, dim):
+    if strategy[2] == 4 and form in fx.SCALAR_FORMS:
+        pytest.skip("the matrix-core kernel exists for the vector forms only")
+    if strategy[2] == 4 and getattr(plan, "geometry", 1) == 2:
+        pytest.skip("curved cells run one lane per cell")
     if strategy[2] == 3 and (dim != 3 or form in fx.SCALAR_FORMS):
         pytest.skip("three lanes per cell exist for the 3D vector forms only")
     if strategy[2] == 2 and (dim != 2 or form in fx.SCALAR_FORMS):
         pytest.skip("two lanes per cell exist for the 2D vector forms only")
     if strategy[2] > 1 and getattr(plan, "geometry", 1) == 2:
         pytest.skip("curved cells run one lane per cell")
-    plan.set_strategy(*strategy)
+    try:
+        plan.set_strategy(*strategy)
+    except fx.FemError as e:
+        if e.status == fx.E_UNSUPPORTED and "LDS" in str(e):
+            pytest.skip(f"configuration does not fit the workgroup's LDS: {e}")
+        raise
 
 
 @pytest.mark.parametrize("strategy", STRATS, ids=STRAT_IDS)
@@ -144,10 +154,12 @@ def test_vjp_small_meshes(form, dim, k, strategy):
 
 HIGH = [(f, 2, k) for f in range(6) for k in (7, 8)] + [(f, 3, k) for f in range(6) for k in (5, 6)]
 HIGH_STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_COLOURED),
-               (fx.SCATTER_PATCH, 64, 0, fx.SUM_ELEMENT), (fx.SCATTER_COLOUR, 0, 0, 0)]
+               (fx.SCATTER_PATCH, 64, 0, fx.SUM_ELEMENT), (fx.SCATTER_COLOUR, 0, 0, 0),
+               (fx.SCATTER_PATCH, 64, 4, fx.SUM_COLOURED)]
 
 
-@pytest.mark.parametrize("strategy", HIGH_STRATS, ids=["patch", "patch64x1c", "patch64e", "colour"])
+@pytest.mark.parametrize("strategy", HIGH_STRATS, ids=["patch", "patch64x1c", "patch64e", "colour",
+                                                      "mfma64"])
 @pytest.mark.parametrize("form,dim,k", HIGH)
 def test_high_degrees(form, dim, k, strategy):
     # the rest of the degree sweep (2D P7, P8; 3D P5): action and VJP, several patches and a
@@ -316,8 +328,8 @@ _ref_cache = {}
 
 @pytest.mark.parametrize("strategy", [(fx.SCATTER_PATCH, 0, 0), (fx.SCATTER_PATCH, 128, 1),
                                       (fx.SCATTER_COLOUR, 0, 0), (fx.SCATTER_PATCH, 84, 3),
-                                      (fx.SCATTER_PATCH, 64, 2)],
-                         ids=["patch", "patch128x1", "colour", "patch84x3", "patch64x2"])
+                                      (fx.SCATTER_PATCH, 64, 2), (fx.SCATTER_PATCH, 64, 4)],
+                         ids=["patch", "patch128x1", "colour", "patch84x3", "patch64x2", "mfma64"])
 @pytest.mark.parametrize("name", FULL)
 def test_full_size_against_oracle(name, strategy):
     """Every output of the full-size workloads against the oracle (seconds on the host)."""
@@ -503,3 +515,23 @@ def test_batch_holds_its_plans():
     b.close()
     p.set_strategy(fx.SCATTER_COLOUR)
     p.close()
+
+
+@pytest.mark.parametrize("form,dim,k", CASES)
+def test_wave_priority_only_on_spill_free_kernels(form, dim, k):
+    """The hinted variant of a coloured-sum patch kernel runs only where the compiled kernel
+    has no scratch memory; curved cells and the element-buffer sums never take it."""
+    mesh = meshgen.make_mesh(dim, 2, k, None, np.random.default_rng(7))
+    plan = fx.Plan.from_mesh(form, mesh, qdeg(form, k), params_for(form))
+    lanes = [1] + ([2] if dim == 2 and form not in fx.SCALAR_FORMS else []) + \
+        ([3] if dim == 3 and form not in fx.SCALAR_FORMS else []) + \
+        ([4] if form not in fx.SCALAR_FORMS else [])
+    for ln in lanes:
+        for mode in ((fx.SUM_COLOURED,) if ln == 4 else (fx.SUM_ELEMENT, fx.SUM_COLOURED)):
+            plan.set_strategy(fx.SCATTER_PATCH, 63 if ln == 3 else 64, ln, mode)
+            for vjp in (False, True):
+                info = plan.kernel_info(vjp)
+                say(f"[prio] form={form} dim={dim} k={k} lanes={ln} mode={mode} vjp={vjp} {info}")
+                assert info["registers"] > 0
+                if info["wave_priority"]:
+                    assert info["scratch_bytes"] == 0 and mode == fx.SUM_COLOURED
