@@ -158,7 +158,11 @@ int fem_action(const fem_plan *plan, const double *u, double *y, void *stream);
  * this call).  For the linear forms A is symmetric and independent of u, so g = A v and u
  * is ignored.
  *   u, v  DEVICE f64 [n_node * ncomp] inputs;  g DEVICE f64 [n_node * ncomp] output,
- *   overwritten; g must alias neither u nor v.  Asynchronous.  Errors as fem_action.
+ *   overwritten; g must alias neither u nor v.  Asynchronous.  Errors as fem_action, and
+ *   FEM_E_UNSUPPORTED for a hyperelastic form when the configuration's tangent kernel
+ *   spills registers to scratch memory (such kernels are not run: two heavily spilling
+ *   ones returned wrong values); the plan's default configuration, every configuration the
+ *   tuner keeps and the matrix-core kernel (lanes_per_cell 4) are free of such spills.
  */
 int fem_action_vjp(const fem_plan *plan, const double *u, const double *v, double *g,
                    void *stream);

@@ -219,6 +219,10 @@ int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int l
 // the kernel a configuration launches; -1 if that kernel is not built
 int kernel_info(int form, int dim, int degree, bool vjp, bool colour, int lanes, int sum_mode,
                 int geom, int *regs, int *scratch, int *prio);
+// whether the hyperelastic tangent (VJP) kernel of a configuration uses scratch memory: such
+// kernels are not run (two of them, heavily spilling, returned wrong values)
+bool vjp_kernel_spills(int form, int dim, int degree, bool colour, int lanes, int sum_mode,
+                       int geom);
 // geometry nodes of a cell: the d+1 vertices, or the P2 lattice of a curved cell
 inline int cell_geom_nodes(int dim, int geom) { return geom == 2 ? (dim == 2 ? 6 : 10) : dim + 1; }
 int patch_threads(int P, int lanes);

@@ -260,6 +260,30 @@ int kernel_registers(int form, int dim, int degree, bool vjp, bool colour, int l
     return attr.numRegs;
 }
 
+// scratch bytes per lane of a compiled kernel (function attributes, cached; -1 unknown)
+static int scratch_bytes(const void *fn)
+{
+    static std::mutex mu;
+    static std::map<const void *, int> known;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = known.find(fn);
+    if (it != known.end()) return it->second;
+    hipFuncAttributes attr{};
+    int b = -1;
+    if (hipFuncGetAttributes(&attr, fn) == hipSuccess) b = (int)attr.localSizeBytes;
+    else (void)hipGetLastError();
+    known.emplace(fn, b);
+    return b;
+}
+
+bool vjp_kernel_spills(int form, int dim, int degree, bool colour, int lanes, int sum_mode, int geom)
+{
+    const Kernels ks = lookup(form, dim, degree, true);
+    const void *fn = colour ? (geom == 2 ? (const void *)ks.colour_p2 : (const void *)ks.colour)
+                            : patch_fn(ks, geom, lanes, sum_mode);
+    return fn && scratch_bytes(fn) != 0;
+}
+
 int kernel_info(int form, int dim, int degree, bool vjp, bool colour, int lanes, int sum_mode,
                 int geom, int *regs, int *scratch, int *prio)
 {

@@ -200,6 +200,7 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
                    const int32_t *cell_nodes, int P);
 int default_patch(const fem_plan *p);
 int default_lanes(const fem_plan *p);
+int default_lanes_vector(const fem_plan *p);
 int default_sum_mode(const fem_plan *p);
 
 // Curved cells: det J (J = sum_g x_g (x) grad_xi phiG_g) at every point of the rule must be
@@ -708,6 +709,20 @@ int default_sum_mode(const fem_plan *)
 int default_lanes(const fem_plan *p)
 {
     if (p->geom == 2) return 1;    // curved cells: one-lane kernels only
+    // the hyperelastic forms whose lane kernel's tangent would spill (3D P5/P6 triples): the
+    // matrix-core kernel, which holds the cell in fewer registers
+    if (femx::nonlinear_form(p->form) && femx::mfma_available(p->form, p->dim, p->degree) &&
+        p->nqt > 0) {
+        const int l = default_lanes_vector(p);
+        if (femx::vjp_kernel_spills(p->form, p->dim, p->degree, false, l, femx::SUM_COLOURED, 1))
+            return femx::kMfmaLanes;
+        return l;
+    }
+    return default_lanes_vector(p);
+}
+
+int default_lanes_vector(const fem_plan *p)
+{
     if (femx::triple_available(p->form, p->dim, p->degree) && p->degree >= 3) return 3;
     // 2D vector forms from P6 on (P5 for elasticity and St Venant-Kirchhoff): a lane's half
     // of the cell (one component) fits its registers at three waves per SIMD, the whole
@@ -782,6 +797,13 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
     // the linear forms are symmetric: their VJP is the action applied to v
     const bool nl_vjp = vjp && femx::nonlinear_form(p->form);
     const double *in = (vjp && !nl_vjp) ? v : u;
+    const bool colour = !(p->strategy == femx::STRAT_PATCH && p->patch > 0);
+    if (nl_vjp && femx::vjp_kernel_spills(p->form, p->dim, p->degree, colour, p->lanes,
+                                          p->sum_mode, p->geom))
+        throw Error(FEM_E_UNSUPPORTED,
+                    "the tangent kernel of this configuration spills registers to scratch memory "
+                    "and is not run; use a configuration whose kernel fits its registers (the "
+                    "matrix-core kernel, lanes_per_cell 4, or the lane splits)");
     if (p->strategy == femx::STRAT_PATCH && p->patch > 0) {
         femx::PatchArgs a{};
         a.verts = p->d_pverts;
@@ -870,6 +892,8 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
     int lanes = lanes_per_cell;
     if (lanes == 0) {
         lanes = default_lanes(plan);
+        // the matrix-core kernel sums by sub-colours only: with element sums, the lane split
+        if (lanes == kMfmaLanes && sum_mode == SUM_ELEMENT) lanes = default_lanes_vector(plan);
         if (patch_cells != 0 && !patch_allowed(patch_cells, lanes)) lanes = 1;
     }
     if (lanes < 1 || lanes > kMfmaLanes)

@@ -183,6 +183,17 @@ std::vector<Candidate> candidates(const fem_plan *p)
         for (int P : {42, 63, 84})
             for (int m : {SUM_ELEMENT, SUM_COLOURED})
                 cands.push_back({FEM_SCATTER_PATCH, P, 3, 0, m});
+    // the hyperelastic forms: only configurations whose tangent kernel runs (no scratch), so
+    // a plan tuned on its action can always take its VJP
+    if (nonlinear_form(p->form)) {
+        std::vector<Candidate> ok;
+        for (const Candidate &c : cands)
+            if (!vjp_kernel_spills(p->form, p->dim, p->degree, c.strategy == FEM_SCATTER_COLOUR,
+                                   c.lanes, c.strategy == FEM_SCATTER_COLOUR ? 1 : c.sum_mode,
+                                   p->geom))
+                ok.push_back(c);
+        cands.swap(ok);
+    }
     return cands;
 }
 
