@@ -152,6 +152,25 @@ int fem_plan_destroy(fem_plan *plan);
 int fem_action(const fem_plan *plan, const double *u, double *y, void *stream);
 
 /*
+ * y = A(u) for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result as fem_action, bit for bit, but the shared nodes' partial sums of the patch
+ * strategy go to a static device buffer of FEM_NOALLOC_SCRATCH_DOUBLES doubles (16 MiB)
+ * that the library holds on each device it runs on until the process ends, instead of the
+ * plan's own buffer.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine) and does no kernel timing (fem_plan_set_timing does not apply).  Every
+ * partial slot is written before it is read in each call, so nothing needs clearing.
+ * Every call on one device shares that device's buffer: calls that overlap on one GPU
+ * (concurrent streams, or threads) race and give wrong results; calls ordered on one
+ * stream do not.  Colour-strategy plans and meshes without shared nodes use no scratch.
+ *   u, y as fem_action.
+ * Errors: FEM_E_UNSUPPORTED when the plan's partial sums (its shared partial slots times
+ * ncomp) exceed the buffer; otherwise as fem_action.
+ */
+#define FEM_NOALLOC_SCRATCH_DOUBLES 2097152
+int fem_action_noalloc(const fem_plan *plan, const double *u, double *y, void *stream);
+
+/*
  * g = (dA/du)^T v: vector-Jacobian product of the action at u.  For the hyperelastic forms
  * (FEM_NEOHOOKEAN, FEM_SVK) the tangent of the residual is contracted with grad v at every
  * quadrature point, F being recomputed from u (nothing is stored between the forward and

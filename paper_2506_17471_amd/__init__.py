@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.fem_last_error.restype = ctypes.c_char_p
     L.fem_version.argtypes = []
     L.fem_version.restype = i32
+    L.fem_action_noalloc.argtypes = [P, P, P, P]
+    L.fem_action_noalloc.restype = i32
     L.fem_plan_kernel_info.argtypes = [P, i32, P, P, P]
     L.fem_plan_kernel_info.restype = i32
     L.fem_stream_copy.argtypes = [P, P, i64, P]
@@ -191,7 +193,7 @@ def _dev_ptr(t, n: int, name: str) -> int:
 
 
 STREAM_SINK = 2048
-
+NOALLOC_SCRATCH_DOUBLES = 2097152   # the static buffer behind fem_action_noalloc
 
 
 def stream_copy(src, dst, stream=None):

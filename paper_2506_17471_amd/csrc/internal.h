@@ -239,6 +239,9 @@ void apply_tuning_cache(fem_plan *p);
 int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, const char *cache,
          hipStream_t s, double *results, int max_results, int *n_results, int max_timed);
 int tune_predict(const fem_plan *p, bool vjp, double *results, int max_results, int *n_results);
+// the device address of this device's static scratch array (FEM_NOALLOC_SCRATCH_DOUBLES
+// doubles), looked up once per device with that device current (kernels.hip)
+double *static_scratch(int device);
 // measurement aids (kernels.hip): STREAM copy and a read-only pass into per-block sums
 hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_stream_read(const double *src, int64_t n, double *sink, hipStream_t s);

@@ -392,6 +392,30 @@ hipError_t launch_fixup(const int32_t *fix_node, const int32_t *fix_off, int64_t
     return hipGetLastError();
 }
 
+// Static scratch for fem_action_noalloc: the shared nodes' partial sums of one action, in a
+// file-scope device array (each device holds its own copy, at its own address, until the
+// process ends).  Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): it uses the address hipGetSymbolAddress returns, looked
+// up once per device with that device current.
+static __device__ __align__(256) double scratch[FEM_NOALLOC_SCRATCH_DOUBLES];
+
+double *static_scratch(int device)
+{
+    static std::mutex mu;
+    static std::map<int, double *> ptrs;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = ptrs.find(device);
+    if (it != ptrs.end()) return it->second;
+    int cur = -1;
+    check_hip(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != device) throw Error(FEM_E_ARG, "scratch lookup needs its device current");
+    double *ptr = nullptr;
+    check_hip(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) throw Error(FEM_E_HIP, "null scratch address");
+    ptrs.emplace(device, ptr);
+    return ptr;
+}
+
 // 2048 workgroups of 256 lanes: 8 per CU on the 256 CUs, enough loads in flight to cover
 // HBM latency with the loop's four 16-byte loads per lane.
 constexpr int kStreamGrid = 2048;

@@ -1114,6 +1114,28 @@ int fem_action(const fem_plan *plan, const double *u, double *y, void *stream)
     return guarded([&] { run(plan, u, nullptr, y, stream, false); });
 }
 
+int fem_action_noalloc(const fem_plan *plan, const double *u, double *y, void *stream)
+{
+    return guarded([&] {
+        check_plan(plan);
+        double *partial = nullptr;
+        if (plan->strategy == femx::STRAT_PATCH && plan->patch > 0 && plan->n_shared > 0) {
+            int dev = -1;
+            femx::check_hip(hipGetDevice(&dev), "hipGetDevice");
+            if (dev != plan->device) throw femx::Error(FEM_E_ARG, "plan was built on another device");
+            const size_t need = (size_t)plan->n_partial * plan->ncomp;
+            if (need > (size_t)FEM_NOALLOC_SCRATCH_DOUBLES)
+                throw femx::Error(FEM_E_UNSUPPORTED,
+                                  "the plan's shared-node partial sums need " + std::to_string(need) +
+                                      " doubles, more than the " +
+                                      std::to_string((long long)FEM_NOALLOC_SCRATCH_DOUBLES) +
+                                      " of the static scratch buffer");
+            partial = femx::static_scratch(dev);
+        }
+        run(plan, u, nullptr, y, stream, false, partial, false);
+    });
+}
+
 int fem_action_vjp(const fem_plan *plan, const double *u, const double *v, double *g, void *stream)
 {
     return guarded([&] { run(plan, u, v, g, stream, true); });
