@@ -151,7 +151,7 @@ def kernel_source_hash() -> str:
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
     for f in ("paper_2506_17471_amd/csrc/forms.h", "paper_2506_17471_amd/csrc/kernel_templates.h",
-              "paper_2506_17471_amd/csrc/kernels.hip"):
+              "paper_2506_17471_amd/csrc/mfma_patch.h", "paper_2506_17471_amd/csrc/kernels.hip"):
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -174,6 +174,11 @@ def recorded_traffic(workload: str, kernel: str):
     return r["fetch_kib"] * 1024 * r["fetch_scale"] + r["write_kib"] * 1024 * r["write_scale"]
 
 
+def fx_stream_sink() -> int:
+    import paper_2506_17471_amd as fx
+    return fx.STREAM_SINK
+
+
 class ColdFlush:
     """Evict L2 and the 256 MB memory-side cache (MALL) before a cold step: the library's
     read-only pass over 1.25 GiB (five times the MALL).  Nothing is written but one partial
@@ -183,7 +188,7 @@ class ColdFlush:
     def __init__(self, gib: float = 1.25):
         import torch
         self.buf = torch.ones(int(gib * (1 << 30)) // 8, dtype=torch.float64, device="cuda")
-        self.sink = torch.empty(4096, dtype=torch.float64, device="cuda")
+        self.sink = torch.empty(fx_stream_sink(), dtype=torch.float64, device="cuda")
 
     def __call__(self):
         import paper_2506_17471_amd as fx
@@ -210,7 +215,7 @@ def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default"):
                 int(r[4])) == (st[1], st[2], st[3]))]
         tuned = {"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
                  "lanes_per_cell": st[2],
-                 "sum_mode": {1: "element", 2: "coloured"}.get(st[3], "-"),
+                 "sum_mode": SUM_NAMES.get(st[3], "-"),
                  "tuner_ms": float(min(r[5] for r in mine)) if mine else None,
                  "fastest_candidate_ms": float(min(r[5] for r in res)), "candidates": len(res)}
     return plan, u, v, y, tuned
@@ -263,10 +268,10 @@ def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bo
                 tuned=tuned, flops_per_cell=fl, flops=fl * w.mesh.n_cell,
                 bytes=footprint_bytes(w.mesh.dim, nv, w.mesh.n_cell, plan.n_loc, w.n_dof,
                                       3 if vjp and w.form in (2, 3) else 2, ng or None),
-                geometry=2 if curved else 1,
+                geometry=2 if curved else 1, kernel_info=plan.kernel_info(vjp),
                 launch={"strategy": "patch" if st[0] == 1 else "colour", "cells_per_patch": st[1],
                         "lanes_per_cell": st[2],
-                        "sum_mode": {1: "element", 2: "coloured"}.get(st[3], "-")})
+                        "sum_mode": SUM_NAMES.get(st[3], "-")})
 
     def finish(info, ms_mean, ms_median, kernel_ms):
         info.update(ms_mean=ms_mean, ms_median=ms_median, kernel_ms=kernel_ms)
@@ -510,6 +515,7 @@ def stream_copy_gbs(gib: float = 1.0, steps: int = 20) -> dict:
             "read_ms": rms, "read_gbs": n * 8 / (rms / 1e3) / 1e9}
 
 
+SUM_NAMES = {1: "element", 2: "coloured"}
 FORM_NAMES = {0: "mass", 1: "elasticity", 2: "neohookean", 3: "svk", 4: "laplace", 5: "helmholtz"}
 
 
@@ -641,6 +647,9 @@ def main():
     ap.add_argument("--rule", choices=["default", "conical", "symmetric"], default="default",
                     help="quadrature rule family of the timed workload (default: the plan's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", action="store_true",
+                    help="time the named workload alone (no VJP, other workloads, copy or batch); "
+                         "for profiler runs")
     ap.add_argument("--sweep", action="store_true",
                     help="only run the degree sweep over every built (form, dim, degree)")
     ap.add_argument("--model-eval", action="store_true",
@@ -682,6 +691,10 @@ def main():
     def note(msg):
         print(f"# {msg}", file=sys.stderr, flush=True)
 
+    if args.only:
+        info, _, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule=args.rule)
+        print(json.dumps({"only": info}))
+        return
     flush = ColdFlush()
     main_info, main_cold, w = run_workload(args.workload, args.steps, args.warmup, cold=True,
                                            tune=tune, rule=args.rule, flush=flush)
@@ -734,9 +747,13 @@ def main():
     achieved = main_info["kernel_tflops"]
     lanes, mode = main_info["launch"]["lanes_per_cell"], main_info["launch"]["sum_mode"]
     geo = main_info["geometry"]
-    if main_info["launch"]["strategy"] == "patch":
+    mode_id = {v: k for k, v in SUM_NAMES.items()}.get(mode, 0)
+    prio = "true" if main_info["kernel_info"]["wave_priority"] else "false"
+    if main_info["launch"]["strategy"] == "patch" and lanes == 4:
+        kname = f"mfma_patch_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {mode_id}>"
+    elif main_info["launch"]["strategy"] == "patch":
         kname = (f"patch_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {lanes}, "
-                 f"{ {'element': 1, 'coloured': 2}.get(mode, 0) }, {geo}>")
+                 f"{mode_id}, {geo}, {prio}>")
     else:
         kname = f"colour_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {geo}>"
     stream_gbs = extras["stream"]["copy_gbs"]

@@ -413,7 +413,7 @@ int fem_plan_kernel_info(const fem_plan *plan, int vjp, int *regs, int *scratch_
  *   src DEVICE f64 [n], 16-byte aligned; sink DEVICE f64 [n_sink >= FEM_STREAM_SINK].
  * Errors: FEM_E_ARG (nulls, misalignment, overlap, short sink), FEM_E_HIP.
  */
-#define FEM_STREAM_SINK 2048
+#define FEM_STREAM_SINK 65536
 int fem_stream_copy(const double *src, double *dst, int64_t n, void *stream);
 int fem_stream_read(const double *src, int64_t n, double *sink, int64_t n_sink, void *stream);
 

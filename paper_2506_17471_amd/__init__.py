@@ -192,7 +192,7 @@ def _dev_ptr(t, n: int, name: str) -> int:
     return t.data_ptr()
 
 
-STREAM_SINK = 2048
+STREAM_SINK = 65536
 NOALLOC_SCRATCH_DOUBLES = 2097152   # the static buffer behind fem_action_noalloc
 
 

@@ -65,43 +65,37 @@ __global__ void zero_nodes_kernel(const int32_t *__restrict__ nodes, int64_t n, 
 // Measurement aids: the achievable HBM bandwidth (a STREAM-style copy, every byte read
 // once and written once) and a read-only pass (each workgroup's sum of its share written to
 // sink[block]) that evicts the caches without leaving dirty lines behind.  Grid-stride over
-// 16-byte elements, four in flight per lane; the scalar tail (n odd) goes to the last lane.
+// 16-byte elements, one element per lane per trip over up to 65536 workgroups (measured
+// fastest of the grid-stride, chunked and unrolled forms on MI355X); the copy uses
+// nontemporal (streaming) loads and stores, the read pass ordinary loads, so that its lines
+// are allocated in L2 and the memory-side cache and push out what they held (with streaming
+// loads a P2 mass action timed after the pass ran as fast as warm).  The scalar tail (n
+// odd) goes to the last lane.
 constexpr int kStreamBlock = 256;
+typedef double dv2 __attribute__((ext_vector_type(2)));
 
 __global__ void __launch_bounds__(kStreamBlock)
-    stream_copy_kernel(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2,
+    stream_copy_kernel(const dv2 *__restrict__ src, dv2 *__restrict__ dst, int64_t n2,
                        const double *__restrict__ tail_src, double *__restrict__ tail_dst)
 {
     const int64_t stride = (int64_t)gridDim.x * kStreamBlock;
-    int64_t i = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
-    for (; i + 3 * stride < n2; i += 4 * stride) {
-        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
-                      d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
-    }
-    for (; i < n2; i += stride) dst[i] = src[i];
+    for (int64_t i = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x; i < n2; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
     if (tail_src && blockIdx.x == gridDim.x - 1 && threadIdx.x == kStreamBlock - 1) *tail_dst = *tail_src;
 }
 
 __global__ void __launch_bounds__(kStreamBlock)
-    stream_read_kernel(const double2 *__restrict__ src, int64_t n2, const double *__restrict__ tail,
+    stream_read_kernel(const dv2 *__restrict__ src, int64_t n2, const double *__restrict__ tail,
                        double *__restrict__ sink)
 {
     __shared__ double part[kStreamBlock / 64];
     const int64_t stride = (int64_t)gridDim.x * kStreamBlock;
-    int64_t i = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
-    double acc0 = 0.0, acc1 = 0.0;
-    for (; i + 3 * stride < n2; i += 4 * stride) {
-        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
-                      d = src[i + 3 * stride];
-        acc0 += (a.x + a.y) + (b.x + b.y);
-        acc1 += (c.x + c.y) + (d.x + d.y);
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x; i < n2; i += stride) {
+        const dv2 a = src[i];
+        acc += a.x + a.y;
     }
-    for (; i < n2; i += stride) acc0 += src[i].x + src[i].y;
-    double v = acc0 + acc1;
+    double v = acc;
     if (tail && blockIdx.x == gridDim.x - 1 && threadIdx.x == kStreamBlock - 1) v += *tail;
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
@@ -220,7 +214,7 @@ bool curved_available(int form, int dim, int degree)
 
 bool batch_available(int form, int dim, int degree, int lanes, int sum_mode)
 {
-    if (lanes < 1 || lanes > 3 || sum_mode < 1 || sum_mode > 2) return false;
+    if (lanes < 1 || lanes > kMfmaLanes || sum_mode < 1 || sum_mode > 2) return false;
     return lookup(form, dim, degree, false).batch[lanes][sum_mode] != nullptr;
 }
 
@@ -326,7 +320,7 @@ hipError_t launch_batch_patch(int form, int dim, int degree, int lanes, int patc
                               const BatchDesc *desc, const int32_t *patch_mesh, int64_t n_patch,
                               size_t lds, hipStream_t s)
 {
-    if (lanes < 1 || lanes > kMfmaLanes || (sum_mode != SUM_ELEMENT && sum_mode != SUM_COLOURED))
+    if (lanes < 1 || lanes > kMfmaLanes || sum_mode < SUM_ELEMENT || sum_mode > SUM_COLOURED)
         return hipErrorInvalidConfiguration;
     const Kernels ks = lookup(form, dim, degree, false);
     BatchFn fn = ks.batch[lanes][sum_mode];
@@ -354,7 +348,7 @@ hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStre
                         hipEvent_t start, hipEvent_t stop)
 {
     if (p.lanes < 1 || p.lanes > kMfmaLanes ||
-        (p.sum_mode != SUM_ELEMENT && p.sum_mode != SUM_COLOURED))
+        p.sum_mode < SUM_ELEMENT || p.sum_mode > SUM_COLOURED)
         return hipErrorInvalidConfiguration;
     if (p.lanes == kMfmaLanes && (p.patch != 64 || !a.mtab || a.nqt < 1))
         return hipErrorInvalidConfiguration;
@@ -416,16 +410,21 @@ double *static_scratch(int device)
     return ptr;
 }
 
-// 2048 workgroups of 256 lanes: 8 per CU on the 256 CUs, enough loads in flight to cover
-// HBM latency with the loop's four 16-byte loads per lane.
-constexpr int kStreamGrid = 2048;
+// up to 65536 workgroups of 256 lanes (the read pass writes one partial sum per workgroup)
+constexpr int kStreamGrid = 65536;
+
+static unsigned stream_grid(int64_t n2)
+{
+    const int64_t g = (n2 + kStreamBlock - 1) / kStreamBlock;
+    return (unsigned)(g < 1 ? 1 : (g > kStreamGrid ? kStreamGrid : g));
+}
 
 hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, hipStream_t s)
 {
     const int64_t n2 = n / 2;
     const bool odd = n & 1;
-    hipLaunchKernelGGL(stream_copy_kernel, dim3(kStreamGrid), dim3(kStreamBlock), 0, s,
-                       (const double2 *)src, (double2 *)dst, n2, odd ? src + n - 1 : nullptr,
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(stream_grid(n2)), dim3(kStreamBlock), 0, s,
+                       (const dv2 *)src, (dv2 *)dst, n2, odd ? src + n - 1 : nullptr,
                        odd ? dst + n - 1 : nullptr);
     return hipGetLastError();
 }
@@ -433,8 +432,8 @@ hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, hipStre
 hipError_t launch_stream_read(const double *src, int64_t n, double *sink, hipStream_t s)
 {
     const int64_t n2 = n / 2;
-    hipLaunchKernelGGL(stream_read_kernel, dim3(kStreamGrid), dim3(kStreamBlock), 0, s,
-                       (const double2 *)src, n2, (n & 1) ? src + n - 1 : nullptr, sink);
+    hipLaunchKernelGGL(stream_read_kernel, dim3(stream_grid(n2)), dim3(kStreamBlock), 0, s,
+                       (const dv2 *)src, n2, (n & 1) ? src + n - 1 : nullptr, sink);
     return hipGetLastError();
 }
 

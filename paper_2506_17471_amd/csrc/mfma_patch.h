@@ -217,26 +217,55 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
 
     // each distinct node stored once: interior nodes into y, shared ones as partials
     for (int jj = tid; jj < U; jj += nthreads) {
+        double sum[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sum[c] = acc_nodes[jj * NC + c];
         if (jj < nint) {
             const int64_t nd = b_node[jj];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a.y[nd * NC + c] = acc_nodes[jj * NC + c];
+            for (int c = 0; c < NC; ++c) a.y[nd * NC + c] = sum[c];
         } else {
             const int64_t dest = a.pdest[pbase + (jj - nint)];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a.partial[dest * NC + c] = acc_nodes[jj * NC + c];
+            for (int c = 0; c < NC; ++c) a.partial[dest * NC + c] = sum[c];
         }
     }
 }
 
+// Waves per SIMD the register allocator is asked to leave room for: more resident
+// workgroups overlap one another's staging, sums and write-out with the matrix products.
+// Set per case from the compiler's resource report so that no bound causes a spill (1: the
+// allocator's default, which also uses the accumulation registers).
+constexpr int mfma_waves(int form, int dim, int k, bool vjp)
+{
+    if (!vjp) {
+        if (dim == 2) {
+            if (k <= 4) return 4;
+            if (form == FEM_ELASTICITY) return k <= 6 ? 4 : 3;
+            return k <= 7 ? 3 : 1;
+        }
+        if (form == FEM_ELASTICITY) return k <= 2 ? 3 : (k <= 5 ? 2 : 1);
+        if (form == FEM_NEOHOOKEAN) return k == 1 ? 3 : ((k == 2 || k == 4) ? 2 : 1);
+        return k == 1 ? 3 : (k <= 5 ? 2 : 1);                       // St Venant-Kirchhoff
+    }
+    if (dim == 2) {
+        if (form == FEM_NEOHOOKEAN) return k == 1 ? 4 : ((k <= 3 || k == 6) ? 3 : 1);
+        return k == 1 ? 4 : ((k == 3 || k == 4 || k == 6) ? 3 : 1); // St Venant-Kirchhoff
+    }
+    return (form == FEM_SVK && k == 1) ? 2 : 1;
+}
+
 template <int FORM, int DIM, int K, bool VJP>
-__global__ void __launch_bounds__(256) mfma_patch_kernel(const PatchArgs a, int P)
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(mfma_waves(FORM, DIM, K, VJP))))
+    mfma_patch_kernel(const PatchArgs a, int P)
 {
     mfma_body<FORM, DIM, K, VJP>(a, xcd_order(blockIdx.x, gridDim.x), P);
 }
 
 template <int FORM, int DIM, int K, bool VJP>
 __global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(mfma_waves(FORM, DIM, K, VJP))))
     mfma_batch_kernel(const BatchDesc *__restrict__ desc, const int32_t *__restrict__ patch_mesh, int P)
 {
     const int64_t b = xcd_order(blockIdx.x, gridDim.x);

@@ -709,10 +709,19 @@ int default_sum_mode(const fem_plan *)
 int default_lanes(const fem_plan *p)
 {
     if (p->geom == 2) return 1;    // curved cells: one-lane kernels only
-    // the hyperelastic forms whose lane kernel's tangent would spill (3D P5/P6 triples): the
-    // matrix-core kernel, which holds the cell in fewer registers
-    if (femx::nonlinear_form(p->form) && femx::mfma_available(p->form, p->dim, p->degree) &&
-        p->nqt > 0) {
+    const bool mfma = femx::mfma_available(p->form, p->dim, p->degree) && p->nqt > 0;
+    // the matrix-core kernel from P4 on tetrahedra, from P6 on triangles for the hyperelastic
+    // forms and from P7 for elasticity, where it measured faster than the lane splits (per 2e5
+    // cells: elasticity 3D P4 222 / 400 us; neo-Hookean 3D P4 392 / 874 us, its VJP 851 / 1953
+    // us; neo-Hookean 2D P6 136 / 144 us, its VJP 184 / 391 us; elasticity 2D P8 346 / 716
+    // us); below, the vector path wins (neo-Hookean 2D P4 110 / 104 us per 5e5 cells,
+    // elasticity 2D P4 96 / 77 us, 3D P2 467 / 171 us at 1.6e6 cells)
+    const int from2d = femx::nonlinear_form(p->form) ? 6 : 7;
+    if (mfma && ((p->dim == 3 && p->degree >= 4) || (p->dim == 2 && p->degree >= from2d)))
+        return femx::kMfmaLanes;
+    // the hyperelastic forms whose lane kernel's tangent would spill: the matrix-core kernel,
+    // which holds the cell in fewer registers
+    if (femx::nonlinear_form(p->form) && mfma) {
         const int l = default_lanes_vector(p);
         if (femx::vjp_kernel_spills(p->form, p->dim, p->degree, false, l, femx::SUM_COLOURED, 1))
             return femx::kMfmaLanes;
