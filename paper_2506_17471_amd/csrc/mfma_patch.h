@@ -249,8 +249,8 @@ constexpr int mfma_waves(int form, int dim, int k, bool vjp)
         return k == 1 ? 3 : (k <= 5 ? 2 : 1);                       // St Venant-Kirchhoff
     }
     if (dim == 2) {
-        if (form == FEM_NEOHOOKEAN) return k == 1 ? 4 : ((k <= 3 || k == 6) ? 3 : 1);
-        return k == 1 ? 4 : ((k == 3 || k == 4 || k == 6) ? 3 : 1); // St Venant-Kirchhoff
+        if (form == FEM_NEOHOOKEAN) return (k <= 3 || k == 6) ? 3 : 1;
+        return (k == 1 || k == 3 || k == 4 || k == 6) ? 3 : 1;      // St Venant-Kirchhoff
     }
     return (form == FEM_SVK && k == 1) ? 2 : 1;
 }
