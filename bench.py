@@ -195,7 +195,7 @@ class ColdFlush:
         fx.stream_read(self.buf, self.sink)
 
 
-def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default"):
+def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default", launch=None):
     import torch
     import paper_2506_17471_amd as fx
     plan = fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params)
@@ -208,7 +208,9 @@ def make_plan(w, tune: bool, vjp: bool = False, rule: str = "default"):
         v = torch.as_tensor(w.v if w.v is not None else
                             np.random.default_rng(9).uniform(-1, 1, w.n_dof), device="cuda")
     tuned = None
-    if tune:
+    if launch is not None:
+        plan.set_strategy(*launch)
+    elif tune:
         res = plan.tune(u, y=y, v=v)
         st = plan.strategy()          # what the tuner applied (the entry config wins ties)
         mine = [r for r in res if int(r[0]) == st[0] and (st[0] == 0 or (int(r[1]), int(r[2]),
@@ -243,14 +245,14 @@ def cold_steps(fn, steps: int, warmup: int, flush) -> np.ndarray:
 
 
 def run_workload(name: str, steps: int, warmup: int, cold: bool = False, vjp: bool = False,
-                 tune: bool = True, rule: str = "default", flush=None):
+                 tune: bool = True, rule: str = "default", flush=None, launch=None):
     """The workload's tuned plan timed warm (back-to-back steps, inputs resident in HBM and
     whatever of them the caches hold) and, with `cold`, cold (every step after a
     cache-evicting pass).  Returns (warm info, cold info or None, workload)."""
     import meshgen
 
     w = meshgen.workload(name, with_v=vjp)
-    plan, u, v, y, tuned = make_plan(w, tune, vjp, rule)
+    plan, u, v, y, tuned = make_plan(w, tune, vjp, rule, launch)
     if vjp:
         fn = lambda: plan.vjp(u, v, out=y)  # noqa: E731
     else:
@@ -647,6 +649,10 @@ def main():
     ap.add_argument("--rule", choices=["default", "conical", "symmetric"], default="default",
                     help="quadrature rule family of the timed workload (default: the plan's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default=None, metavar="S,P,L,M",
+                    help="with --only: this launch configuration (strategy, cells per patch, "
+                         "lanes per cell, sum mode, as fem_plan_set_strategy takes them) instead "
+                         "of tuning")
     ap.add_argument("--only", action="store_true",
                     help="time the named workload alone (no VJP, other workloads, copy or batch); "
                          "for profiler runs")
@@ -692,7 +698,9 @@ def main():
         print(f"# {msg}", file=sys.stderr, flush=True)
 
     if args.only:
-        info, _, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule=args.rule)
+        launch = tuple(int(x) for x in args.launch.split(",")) if args.launch else None
+        info, _, _ = run_workload(args.workload, args.steps, args.warmup, tune=tune, rule=args.rule,
+                                  launch=launch)
         print(json.dumps({"only": info}))
         return
     flush = ColdFlush()
@@ -750,7 +758,7 @@ def main():
     mode_id = {v: k for k, v in SUM_NAMES.items()}.get(mode, 0)
     prio = "true" if main_info["kernel_info"]["wave_priority"] else "false"
     if main_info["launch"]["strategy"] == "patch" and lanes == 4:
-        kname = f"mfma_patch_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {mode_id}>"
+        kname = f"mfma_patch_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false>"
     elif main_info["launch"]["strategy"] == "patch":
         kname = (f"patch_kernel<{w.form}, {w.mesh.dim}, {w.mesh.k}, false, {lanes}, "
                  f"{mode_id}, {geo}, {prio}>")

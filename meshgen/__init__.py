@@ -276,6 +276,10 @@ _SPECS = {
     # the meshes above with every cell bent by ``curved(mesh, 0.05)``
     "nh_p4_2d_curved": (FORM_NH, 2, 512, 4, 8, 0.1, 1, (10.0, 1.0)),
     "mass_p2_2d_1024_curved": (FORM_MASS, 2, 1024, 2, 4, 0.1, 0, ()),
+    # high degree at the paper's smaller sizes (about 2e5 cells): 3D P4 elasticity (32^3
+    # cubes x 6 tets, degree 6) and the 2D P6 neo-Hookean residual (316^2 squares, degree 12)
+    "elast_p4_3d": (FORM_ELAST, 3, 32, 4, 6, 0.05, 6, lame_from_young(1.0, 0.3)),
+    "nh_p6_2d": (FORM_NH, 2, 316, 6, 12, 0.1, 7, (10.0, 1.0)),
 }
 _CURVED_AMP = {"nh_p4_2d_curved": 0.05, "mass_p2_2d_1024_curved": 0.05}
 
