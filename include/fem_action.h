@@ -182,6 +182,9 @@ int fem_action_noalloc(const fem_plan *plan, const double *u, double *y, void *s
  *   spills registers to scratch memory (such kernels are not run: two heavily spilling
  *   ones returned wrong values); the plan's default configuration, every configuration the
  *   tuner keeps and the matrix-core kernel (lanes_per_cell 4) are free of such spills.
+ *   Also FEM_E_UNSUPPORTED when the patch kernel's tangent, which stages u and v, needs
+ *   more than 160 KB of LDS per workgroup for the plan's largest patch (plan creation and
+ *   fem_plan_set_strategy check the action's need only): 3D P6 on full-size meshes.
  */
 int fem_action_vjp(const fem_plan *plan, const double *u, const double *v, double *g,
                    void *stream);

@@ -661,8 +661,10 @@ void build_patches(fem_plan *p, const double *coords, const int32_t *cell_verts,
     PatchLayout L = make_patch_layout(p, coords, cell_verts, cell_nodes, P);
     const char *chk = std::getenv("FEM_CHECK");
     if (chk && chk[0] == '1') validate_patch_layout(p, L, cell_nodes);
-    const size_t lds = femx::patch_lds_bytes(p->form, p->dim, p->degree, femx::nonlinear_form(p->form),
-                                             P, L.max_nodes, p->sum_mode);
+    // the action's need decides whether the layout is usable; the hyperelastic VJP, which
+    // stages two vectors, is checked when it is called
+    const size_t lds = femx::patch_lds_bytes(p->form, p->dim, p->degree, false, P, L.max_nodes,
+                                             p->sum_mode);
     if (lds > 160 * 1024)
         throw Error(FEM_E_UNSUPPORTED, "patch of " + std::to_string(P) + " cells needs " +
                                            std::to_string(lds) + " bytes of LDS");
@@ -800,9 +802,6 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
     int dev = -1;
     femx::check_hip(hipGetDevice(&dev), "hipGetDevice");
     if (dev != p->device) throw Error(FEM_E_ARG, "plan was built on another device");
-    if (p->n_untouched > 0)
-        femx::check_hip(femx::launch_zero_nodes(p->d_untouched, p->n_untouched, p->ncomp, y, s),
-                        "zero untouched nodes");
     // the linear forms are symmetric: their VJP is the action applied to v
     const bool nl_vjp = vjp && femx::nonlinear_form(p->form);
     const double *in = (vjp && !nl_vjp) ? v : u;
@@ -813,6 +812,18 @@ void run(const fem_plan *p, const double *u, const double *v, double *y, void *s
                     "the tangent kernel of this configuration spills registers to scratch memory "
                     "and is not run; use a configuration whose kernel fits its registers (the "
                     "matrix-core kernel, lanes_per_cell 4, or the lane splits)");
+    if (nl_vjp && !colour) {
+        const size_t need = femx::patch_lds_bytes(p->form, p->dim, p->degree, true, p->patch,
+                                                  p->max_patch_nodes, p->sum_mode, p->lanes);
+        if (need > 160 * 1024)
+            throw Error(FEM_E_UNSUPPORTED,
+                        "the tangent kernel of this configuration stages u and v and needs " +
+                            std::to_string(need) + " bytes of LDS per workgroup, more than "
+                            "160 KB; a smaller patch may fit");
+    }
+    if (p->n_untouched > 0)
+        femx::check_hip(femx::launch_zero_nodes(p->d_untouched, p->n_untouched, p->ncomp, y, s),
+                        "zero untouched nodes");
     if (p->strategy == femx::STRAT_PATCH && p->patch > 0) {
         femx::PatchArgs a{};
         a.verts = p->d_pverts;
@@ -925,8 +936,7 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
     if (!patch_allowed(P, lanes))
         throw Error(FEM_E_ARG, "patch_cells must be 64, 128 or 256 (at most 256 lanes) for one or "
                                "two lanes per cell, 21, 42, 63 or 84 for three, and 64 for four");
-    const size_t lds = patch_lds_bytes(plan->form, plan->dim, plan->degree,
-                                       femx::nonlinear_form(plan->form), P,
+    const size_t lds = patch_lds_bytes(plan->form, plan->dim, plan->degree, false, P,
                                        P == plan->patch ? plan->max_patch_nodes : 0, mode, lanes);
     if (P == plan->patch && lds > 160 * 1024)
         throw Error(FEM_E_UNSUPPORTED, "this configuration needs more than 160 KB of LDS");
@@ -943,10 +953,9 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
             plan->sum_mode = old_mode;
             throw;
         }
-        // the new layout's largest patch decides the LDS need of this lane split (the
-        // hyperelastic forms' VJP staging two vectors); past 160 KB, back to the old layout
-        const size_t need = patch_lds_bytes(plan->form, plan->dim, plan->degree,
-                                            femx::nonlinear_form(plan->form), P,
+        // the new layout's largest patch decides the action's LDS need of this lane split;
+        // past 160 KB, back to the old layout
+        const size_t need = patch_lds_bytes(plan->form, plan->dim, plan->degree, false, P,
                                             plan->max_patch_nodes, mode, lanes);
         if (need > 160 * 1024) {
             plan->sum_mode = old_mode;

@@ -346,11 +346,18 @@ int tune(fem_plan *p, const double *u, const double *v, double *y, bool vjp, con
             best_c = c;
         }
     }
+    if (n_results) *n_results = nres;
+    if (nres == 0) {
+        // nothing ran (every candidate refused: spilling tangents, LDS): leave the plan as
+        // it came
+        apply(p, entry);
+        throw Error(FEM_E_UNSUPPORTED, std::string("no launch configuration runs this plan's ") +
+                                           (vjp ? "VJP" : "action"));
+    }
     if (entry_ms < 1e300 && best > (1.0 - kMargin) * entry_ms) {
         best_c = entry;
         best = entry_ms;
     }
-    if (n_results) *n_results = nres;
     apply(p, best_c);
     if (cache && *cache) {
         auto c = read_cache(cache);

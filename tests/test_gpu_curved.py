@@ -51,13 +51,15 @@ def rule_families(dim, quad_degree):
 
 
 def vjp_or_skip(plan, u, v):
-    """The VJP, or a skip where the configuration's tangent kernel spills to scratch (the
-    library refuses to run those)."""
+    """The VJP, or a skip where the configuration's tangent kernel spills to scratch or needs
+    more LDS than a workgroup has (the library refuses to run those)."""
     try:
         return plan.vjp(u, v)
     except fx.FemError as e:
         if e.status == fx.E_UNSUPPORTED and "scratch" in str(e):
             pytest.skip(f"tangent kernel spills: {e}")
+        if e.status == fx.E_UNSUPPORTED and "LDS" in str(e):
+            pytest.skip(f"tangent kernel does not fit the workgroup's LDS: {e}")
         raise
 
 

@@ -60,13 +60,15 @@ def rule_families(dim, quad_degree):
 
 
 def vjp_or_skip(plan, u, v):
-    """The VJP, or a skip where the configuration's tangent kernel spills to scratch (the
-    library refuses to run those)."""
+    """The VJP, or a skip where the configuration's tangent kernel spills to scratch or needs
+    more LDS than a workgroup has (the library refuses to run those)."""
     try:
         return plan.vjp(u, v)
     except fx.FemError as e:
         if e.status == fx.E_UNSUPPORTED and "scratch" in str(e):
             pytest.skip(f"tangent kernel spills: {e}")
+        if e.status == fx.E_UNSUPPORTED and "LDS" in str(e):
+            pytest.skip(f"tangent kernel does not fit the workgroup's LDS: {e}")
         raise
 
 
@@ -571,3 +573,30 @@ def test_spilling_tangent_kernels_are_refused():
     g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
     ref = oracle.vjp(fx.FORM_NEOHOOKEAN, mesh, u, v, 8, NH, family=plan.quad_family_name)
     assert rel_err(g, ref)[0] < TOL and rel_err(g_default.cpu().numpy(), ref)[0] < TOL
+
+
+def test_tangent_needing_more_lds_than_a_workgroup_is_refused():
+    """3D P6 neo-Hookean on 64-cell patches of a 3^3-cube mesh: the largest patch holds
+    3231 nodes, so the matrix-core tangent kernel, which stages u and v, would need 168,016
+    bytes of LDS (> 160 KB) while the action (one vector) fits.  The plan is created and its
+    action runs against the oracle; the VJP fails with FEM_E_UNSUPPORTED naming the LDS; a
+    VJP tuning run, in which no configuration runs, fails the same way and leaves the plan's
+    configuration as it was."""
+    mesh = meshgen.unit_cube(3, 6, 0.05, np.random.default_rng(1))
+    st = fx.check_patch_layout(fx.FORM_NEOHOOKEAN, mesh, 64)
+    assert st["lds_bytes"] > 160 * 1024
+    u, v = inputs(fx.FORM_NEOHOOKEAN, mesh, 19)
+    say(f"[lds] nh 3D P6 cells={mesh.n_cell} max_patch_nodes={st['max_patch_nodes']}")
+    plan = fx.Plan.from_mesh(fx.FORM_NEOHOOKEAN, mesh, 12, NH)
+    plan.set_strategy(fx.SCATTER_PATCH, 64, 4, fx.SUM_COLOURED)
+    before = plan.strategy()
+    y = plan.action(gpu(u)).cpu().numpy()
+    assert rel_err(y, oracle.action(fx.FORM_NEOHOOKEAN, mesh, u, 12, NH,
+                                    family=plan.quad_family_name))[0] < TOL
+    with pytest.raises(fx.FemError) as e:
+        plan.vjp(gpu(u), gpu(v))
+    assert e.value.status == fx.E_UNSUPPORTED and "LDS" in str(e.value)
+    with pytest.raises(fx.FemError) as e:
+        plan.tune(gpu(u), v=gpu(v))
+    assert e.value.status == fx.E_UNSUPPORTED
+    assert plan.strategy() == before
