@@ -261,8 +261,8 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *                       others leave as partial sums that a second, small kernel adds in
  *                       patch order.  The default.
  *   lanes_per_cell  1; 2 (2D vector forms: lane c of a pair owns component c); 3 (3D vector
- *                   forms: lane triples, 21 per wavefront); 4 (vector forms on affine
- *                   cells: the FP64 matrix-core kernel, where both contractions of the
+ *                   forms: lane triples, 21 per wavefront); 4 (affine cells, every form:
+ *                   the FP64 matrix-core kernel, where both contractions of the
  *                   quadrature loop run as 16x16x4 MFMA tiles over 16 cells per wavefront
  *                   and the pointwise form on the vector ALU, each cell's points and nodes
  *                   spread over four lanes; coloured sums only).
@@ -310,8 +310,8 @@ int fem_plan_get_timing(fem_plan *plan, double *kernel_ms, int64_t *calls);
  * the fastest on the plan.  Candidates: the colour strategy with 64/128/256 cells per
  * workgroup; the patch strategy with 64/128/256 cells per patch and one lane per cell,
  * 64/128 with lane pairs (2D vector forms), 42/63/84 with lane triples (3D vector forms),
- * each with both sum modes; and the matrix-core kernel (vector forms on affine cells, 64
- * cells per patch, coloured sums): the matrix cores on or off.  The configuration the plan had on entry is kept unless a
+ * each with both sum modes; and the matrix-core kernel (affine cells, 64 cells per patch,
+ * coloured sums): the matrix cores on or off.  The configuration the plan had on entry is kept unless a
  * candidate is more than 3% faster.  Timing follows the paper's protocol (Sec. 6.2.1): 5 warm-up runs,
  * then timed runs until 15 are collected or 0.2 s accumulates, arithmetic mean, HIP
  * events on `stream`.  Synchronises; may rebuild the plan's patches (host work).

@@ -49,19 +49,25 @@ std::vector<double> kernel_table(int form, const RefTables &t, const RefTables *
 // The matrix-core kernels' tabulation, per tile of 16 quadrature points (16 t .. 16 t + 15,
 // zero-padded past nq) in the operand order of v_mfma_f64_16x16x4_f64 (lane l holds
 // A[l % 16][l / 16]; the 16 x 16 result's register k of lane l is row 4 k + l / 16, column
-// l % 16):
-//   evaluation  [r][ks][64]: A[i][kk] = d phi_{4 ks + kk} / d xi_r at point 16 t + i
-//   contraction [k][r][m][64]: A[i][kk] = d phi_{16 m + i} / d xi_r at point 16 t + 4 k + kk
+// l % 16), for the form's rows f_r: the reference derivatives d phi / d xi_r, r < d (vector
+// forms, Laplace), the values phi (mass), or both, derivatives first (Helmholtz: r = d is
+// phi):
+//   evaluation  [r][ks][64]: A[i][kk] = f_r(phi_{4 ks + kk}) at point 16 t + i
+//   contraction [k][r][m][64]: A[i][kk] = f_r(phi_{16 m + i}) at point 16 t + 4 k + kk
 //   weights [16]: w at point 16 t + i
 // (ks < mfma_ks = ceil(nloc / 4) k-steps of nodes, m < mfma_ma = ceil(nloc / 16) node tiles,
 // phi_a = 0 for a >= nloc).
 constexpr int mfma_ks(int nloc) { return (nloc + 3) / 4; }
 constexpr int mfma_ma(int nloc) { return (nloc + 15) / 16; }
-constexpr int mfma_tile_doubles(int dim, int nloc)
+constexpr int mfma_rows(int form, int dim)
 {
-    return dim * mfma_ks(nloc) * 64 + 4 * dim * mfma_ma(nloc) * 64 + 16;
+    return form == FEM_MASS ? 1 : (form == FEM_HELMHOLTZ ? dim + 1 : dim);
 }
-std::vector<double> mfma_table(const RefTables &t, int *n_tiles);
+constexpr int mfma_tile_doubles(int rows, int nloc)
+{
+    return rows * mfma_ks(nloc) * 64 + 4 * rows * mfma_ma(nloc) * 64 + 16;
+}
+std::vector<double> mfma_table(int form, const RefTables &t, int *n_tiles);
 
 // Launch parameters of one colour class.
 struct LaunchArgs {

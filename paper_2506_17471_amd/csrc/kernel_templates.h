@@ -478,10 +478,8 @@ Kernels entry()
     }
     if constexpr (DIM == 2 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 2, FULL>(k);
     if constexpr (DIM == 3 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 3, FULL>(k);
-    if constexpr (!scalar_form(FORM)) {
-        k.patch[kMfmaLanes][SUM_COLOURED] = mfma_patch_kernel<FORM, DIM, K, VJP>;
-        if constexpr (FULL) k.batch[kMfmaLanes][SUM_COLOURED] = mfma_batch_kernel<FORM, DIM, K, VJP>;
-    }
+    k.patch[kMfmaLanes][SUM_COLOURED] = mfma_patch_kernel<FORM, DIM, K, VJP>;
+    if constexpr (FULL) k.batch[kMfmaLanes][SUM_COLOURED] = mfma_batch_kernel<FORM, DIM, K, VJP>;
     return k;
 }
 

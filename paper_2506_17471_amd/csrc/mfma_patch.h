@@ -1,4 +1,4 @@
-// The vector forms' patch kernel on the FP64 matrix cores (included by kernel_templates.h).
+// The patch kernel on the FP64 matrix cores (included by kernel_templates.h).
 //
 // Both contractions of the quadrature loop (paper Sec. 2.3: evaluation of the reference
 // gradients at the points from the nodal values, and the test-function contraction of the
@@ -9,11 +9,14 @@
 // registers) of every 16-row result tile (the instruction's output layout), so each cell
 // is spread over four lanes ("four lanes per cell").
 //
-// Shapes for dimension d, n = n_loc nodes, Q points padded to 16 T point tiles:
-//   evaluation, point tile t, direction r, component c (d^2 products per tile):
+// Shapes for dimension d, n = n_loc nodes, Q points padded to 16 T point tiles, rows D_r of
+// the tabulation (r < R: the d reference derivatives for the vector forms and Laplace, the
+// values for mass, both for Helmholtz) and C components (d, or 1 for the scalar forms):
+//   evaluation, point tile t, row r, component c (R C products per tile and k-step):
 //     G_rc[q][cell] = sum_a D_r[q][a] u_c[a][cell]      16 x 16, k-steps of 4 nodes
-//   pointwise at each of the lane's 4 points of the tile:  T_cr = W P(G K) K^T
-//   contraction, node tile m, component c, direction r:
+//   pointwise at each of the lane's 4 points of the tile:  T_cr = W P(G K) K^T (vector
+//     forms); T_r = W (K K^T G)_r for the derivative rows, W G for the value row (scalar)
+//   contraction, node tile m, component c, row r:
 //     y_c[a][cell] += sum_q D_r[q][a] T_cr[q][cell]     16 x 16, k-steps of 4 points
 // The evaluation's output register k of lane group g (point 16 t + 4 k + g) is exactly the
 // contraction's B operand of k-step (t, k) for that lane (k-step (t, k) sums the points
@@ -38,14 +41,16 @@ template <int FORM, int DIM, int K, bool VJP>
 __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
 {
     constexpr int NLOC = nloc_of(DIM, K);
-    constexpr int NC = DIM;
+    constexpr int NC = ncomp_of(FORM, DIM);
+    constexpr int NR = mfma_rows(FORM, DIM);
     constexpr int KS = mfma_ks(NLOC);
     constexpr int MA = mfma_ma(NLOC);
-    constexpr int TILE = mfma_tile_doubles(DIM, NLOC);
-    static_assert(DIM * DIM * 4 <= 64, "accumulators");
-    constexpr int EVAL = DIM * KS * 64;
-    constexpr int CON = 4 * DIM * MA * 64;
-    static_assert(!scalar_form(FORM), "vector forms");
+    constexpr int TILE = mfma_tile_doubles(NR, NLOC);
+    static_assert(NR * NC * 4 <= 64, "accumulators");
+    constexpr int EVAL = NR * KS * 64;
+    constexpr int CON = 4 * NR * MA * 64;
+    constexpr bool SCALAR = scalar_form(FORM);
+    static_assert(!(SCALAR && VJP), "the scalar forms are linear: their VJP is the action");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
@@ -104,6 +109,20 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
             }
     }
 
+    // the scalar forms' flux map K K^T (the cell's constant; inactive lanes: W = 0)
+    double KKt[SCALAR ? DIM : 1][SCALAR ? DIM : 1];
+    if constexpr (SCALAR) {
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int q2 = 0; q2 < DIM; ++q2) {
+                double s2 = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < DIM; ++jj) s2 = fma(Kinv[r][jj], Kinv[q2][jj], s2);
+                KKt[r][q2] = s2;
+            }
+    }
+
     dvec4 y[NC][MA];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -115,9 +134,9 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
     for (int t = 0; t < a.nqt; ++t) {
         const double *tile = mt + (int64_t)t * TILE;
         // evaluation: G_rc (and the gradient of v for the VJP) on this tile's 16 points
-        dvec4 acc[DIM][NC], accv[VJP ? DIM : 1][NC];
+        dvec4 acc[NR][NC], accv[VJP ? NR : 1][NC];
 #pragma unroll
-        for (int r = 0; r < DIM; ++r)
+        for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 acc[r][c] = dvec4{0.0, 0.0, 0.0, 0.0};
@@ -137,7 +156,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
                 }
             }
 #pragma unroll
-            for (int r = 0; r < DIM; ++r) {
+            for (int r = 0; r < NR; ++r) {
                 const double af = tile[(r * KS + ks) * 64 + lane];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
@@ -149,34 +168,56 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
         }
         // the pointwise form at the lane's four points 16 t + 4 k + g of its cell
         const double *wt = tile + EVAL + CON;
+        if constexpr (SCALAR) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            double gu[DIM][DIM], gv[DIM][DIM], G[DIM][DIM], H[DIM][DIM], S[DIM][DIM], T[DIM][DIM];
+            for (int k = 0; k < 4; ++k) {
+                const double W = wt[4 * k + g] * adet;
+                if constexpr (FORM != FEM_MASS) {
+                    // flux against the reference test derivatives: W K K^T grad_ref u
+                    double gr[DIM];
 #pragma unroll
-            for (int c = 0; c < DIM; ++c)
+                    for (int r = 0; r < DIM; ++r) gr[r] = acc[r][0][k];
 #pragma unroll
-                for (int r = 0; r < DIM; ++r) {
-                    gu[c][r] = acc[r][c][k];
-                    if constexpr (VJP) gv[c][r] = accv[r][c][k];
+                    for (int r = 0; r < DIM; ++r) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int q2 = 0; q2 < DIM; ++q2) s2 = fma(KKt[r][q2], gr[q2], s2);
+                        acc[r][0][k] = W * s2;
+                    }
                 }
-            to_physical<DIM>(gu, Kinv, G);
-            if constexpr (VJP) to_physical<DIM>(gv, Kinv, H);
-            pointwise<FORM, DIM, VJP>(G, H, a.lam, a.mu, S);
-            pull_back<DIM>(S, Kinv, wt[4 * k + g] * adet, T);
+                if constexpr (FORM == FEM_MASS || FORM == FEM_HELMHOLTZ)
+                    acc[NR - 1][0][k] = W * acc[NR - 1][0][k];     // the value row
+            }
+        } else {
 #pragma unroll
-            for (int c = 0; c < DIM; ++c)
+            for (int k = 0; k < 4; ++k) {
+                double gu[DIM][DIM], gv[DIM][DIM], G[DIM][DIM], H[DIM][DIM], S[DIM][DIM], T[DIM][DIM];
 #pragma unroll
-                for (int r = 0; r < DIM; ++r) acc[r][c][k] = T[c][r];
+                for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r) {
+                        gu[c][r] = acc[r][c][k];
+                        if constexpr (VJP) gv[c][r] = accv[r][c][k];
+                    }
+                to_physical<DIM>(gu, Kinv, G);
+                if constexpr (VJP) to_physical<DIM>(gv, Kinv, H);
+                pointwise<FORM, DIM, VJP>(G, H, a.lam, a.mu, S);
+                pull_back<DIM>(S, Kinv, wt[4 * k + g] * adet, T);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r) acc[r][c][k] = T[c][r];
+            }
         }
         // contraction: k-step (t, k) takes register k of every lane as its B operand
         const double *con = tile + EVAL;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int r = 0; r < DIM; ++r)
+            for (int r = 0; r < NR; ++r)
 #pragma unroll
                 for (int m = 0; m < MA; ++m) {
-                    const double af = con[((k * DIM + r) * MA + m) * 64 + lane];
+                    const double af = con[((k * NR + r) * MA + m) * 64 + lane];
 #pragma unroll
                     for (int c = 0; c < NC; ++c)
                         y[c][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, acc[r][c][k], y[c][m], 0, 0, 0);
@@ -238,6 +279,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
 // allocator's default, which also uses the accumulation registers).
 constexpr int mfma_waves(int form, int dim, int k, bool vjp)
 {
+    if (scalar_form(form)) return 1;
     if (!vjp) {
         if (dim == 2) {
             if (k <= 4) return 4;

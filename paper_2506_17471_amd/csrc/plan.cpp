@@ -252,14 +252,14 @@ std::vector<double> plan_tables(const fem_plan *p, int family, const double *coo
     return femx::kernel_table(p->form, t, &g);
 }
 
-// The matrix-core kernels' tabulation on the rule of `family` (vector forms on affine cells
-// whose kernel is built; empty otherwise).
+// The matrix-core kernels' tabulation on the rule of `family` (affine cells whose kernel is
+// built; empty otherwise).
 std::vector<double> plan_mfma_table(const fem_plan *p, int family, int *n_tiles)
 {
     *n_tiles = 0;
     if (p->geom != 1 || !femx::mfma_available(p->form, p->dim, p->degree)) return {};
     femx::RefTables t = femx::reference_tables(p->dim, p->degree, p->quad_degree, family);
-    return femx::mfma_table(t, n_tiles);
+    return femx::mfma_table(p->form, t, n_tiles);
 }
 
 // Host-side validation of the mesh; runs before any HIP call.
@@ -717,9 +717,14 @@ int default_lanes(const fem_plan *p)
     // cells: elasticity 3D P4 222 / 400 us; neo-Hookean 3D P4 392 / 874 us, its VJP 851 / 1953
     // us; neo-Hookean 2D P6 136 / 144 us, its VJP 184 / 391 us; elasticity 2D P8 346 / 716
     // us); below, the vector path wins (neo-Hookean 2D P4 110 / 104 us per 5e5 cells,
-    // elasticity 2D P4 96 / 77 us, 3D P2 467 / 171 us at 1.6e6 cells)
+    // elasticity 2D P4 96 / 77 us, 3D P2 467 / 171 us at 1.6e6 cells).  The scalar forms
+    // from P5 on tetrahedra and P7 on triangles (per 2e5 tets / 5e5 triangles, one lane
+    // against matrix cores: Helmholtz 3D P5 3928 / 769 us, Laplace 3D P5 719 / 377, mass 3D
+    // P6 2537 / 1031, Helmholtz 2D P8 1878 / 1205, mass 2D P7 314 / 264; one lane wins up to
+    // 3D P4 and 2D P6, e.g. mass 3D P4 66 / 99 us, Laplace 2D P6 161 / 183)
     const int from2d = femx::nonlinear_form(p->form) ? 6 : 7;
-    if (mfma && ((p->dim == 3 && p->degree >= 4) || (p->dim == 2 && p->degree >= from2d)))
+    const int from3d = femx::scalar_form(p->form) ? 5 : 4;
+    if (mfma && ((p->dim == 3 && p->degree >= from3d) || (p->dim == 2 && p->degree >= from2d)))
         return femx::kMfmaLanes;
     // the hyperelastic forms whose lane kernel's tangent would spill: the matrix-core kernel,
     // which holds the cell in fewer registers
@@ -920,8 +925,7 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
         throw Error(FEM_E_ARG, "lanes_per_cell must be 0, 1, 2, 3 or 4");
     if (lanes == kMfmaLanes && (plan->geom != 1 || !mfma_available(plan->form, plan->dim, plan->degree)))
         throw Error(FEM_E_UNSUPPORTED,
-                    "the matrix-core kernel (four lanes per cell) exists for the vector forms on "
-                    "affine cells only");
+                    "the matrix-core kernel (four lanes per cell) exists for affine cells only");
     if (lanes > 1 && plan->geom == 2)
         throw Error(FEM_E_UNSUPPORTED, "curved cells run one lane per cell");
     if (lanes == 2 && !pair_available(plan->form, plan->dim, plan->degree))

@@ -560,13 +560,17 @@ std::vector<double> kernel_table(int form, const RefTables &t, const RefTables *
     return out;
 }
 
-std::vector<double> mfma_table(const RefTables &t, int *n_tiles)
+std::vector<double> mfma_table(int form, const RefTables &t, int *n_tiles)
 {
-    const int d = t.dim, n = t.nloc, ks = mfma_ks(n), ma = mfma_ma(n);
+    const int n = t.nloc, ks = mfma_ks(n), ma = mfma_ma(n), d = mfma_rows(form, t.dim);
     const int nt = (t.nq + 15) / 16, tile = mfma_tile_doubles(d, n);
     std::vector<double> out((size_t)nt * tile, 0.0);
+    // row r of the form: a reference derivative, or (mass; Helmholtz's last row) the value
+    const bool value_row = form == FEM_MASS || form == FEM_HELMHOLTZ;
     auto dphi = [&](int q, int a, int r) {
-        return (q < t.nq && a < n) ? t.dphi[((size_t)q * n + a) * d + r] : 0.0;
+        if (q >= t.nq || a >= n) return 0.0;
+        if (value_row && r == d - 1) return t.phi[(size_t)q * n + a];
+        return t.dphi[((size_t)q * n + a) * t.dim + r];
     };
     for (int tt = 0; tt < nt; ++tt) {
         double *o = &out[(size_t)tt * tile];

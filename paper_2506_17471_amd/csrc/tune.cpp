@@ -266,13 +266,16 @@ double predict_ms(const fem_plan *p, const Candidate &c, bool vjp)
     const double eta = std::min(1.0, std::max(waves, 0.25) / 3.0);
     double t_valu = n * instr * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
     if (c.lanes == kMfmaLanes) {
-        // matrix cores: per 16 cells and point tile, d^2 k-steps of the evaluation (twice for
-        // the VJP) and 4 d^2 node tiles of the contraction, 64 cycles each on one SIMD; the
-        // pointwise work on the vector ALU at every padded point, half of it overlapped
+        // matrix cores: per 16 cells and point tile, R C products (tabulation rows R:
+        // d derivatives, values or both; C components) per k-step of the evaluation (twice
+        // for the VJP) and 4 R C per node tile of the contraction, 64 cycles each on one
+        // SIMD; the pointwise work on the vector ALU at every padded point, half of it
+        // overlapped
         const double ks = mfma_ks(p->nloc), ma = mfma_ma(p->nloc), tiles = p->nqt;
-        const double ops = tiles * (d * d * ks * (nl ? 2 : 1) + 4.0 * d * d * ma);
+        const double rc = (double)mfma_rows(p->form, p->dim) * nc;
+        const double ops = tiles * (rc * ks * (nl ? 2 : 1) + 4.0 * rc * ma);
         const double t_mfma = n / 16.0 * ops * 64.0 / (1024.0 * 2.4e9) / eta;
-        const double ev = 2 * d * d * nloc * (nl ? 2 : 1), ct = 2 * d * d * nloc;
+        const double ev = 2 * rc * nloc * (nl ? 2 : 1), ct = 2 * rc * nloc;
         const double pw = flops_per_point(p->form, p->dim, p->nloc, nl) - ev - ct;
         const double t_pw = n * 16.0 * tiles * pw / 2.0 * 1.25 * 4.0 / (64.0 * 1024.0 * 2.4e9) / eta;
         t_valu = t_mfma + 0.5 * t_pw;

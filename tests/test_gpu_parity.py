@@ -115,8 +115,6 @@ STRAT_IDS = ["patch", "patch64x1e", "patch128x1c", "colour", "patch42x3e", "patc
 
 
 def apply_strategy(plan, strategy, form, dim):
-    if strategy[2] == 4 and form in fx.SCALAR_FORMS:
-        pytest.skip("the matrix-core kernel exists for the vector forms only")
     if strategy[2] == 4 and getattr(plan, "geometry", 1) == 2:
         pytest.skip("curved cells run one lane per cell")
     if strategy[2] == 3 and (dim != 3 or form in fx.SCALAR_FORMS):
@@ -538,8 +536,7 @@ def test_wave_priority_only_on_spill_free_kernels(form, dim, k):
     mesh = meshgen.make_mesh(dim, 2, k, None, np.random.default_rng(7))
     plan = fx.Plan.from_mesh(form, mesh, qdeg(form, k), params_for(form))
     lanes = [1] + ([2] if dim == 2 and form not in fx.SCALAR_FORMS else []) + \
-        ([3] if dim == 3 and form not in fx.SCALAR_FORMS else []) + \
-        ([4] if form not in fx.SCALAR_FORMS else [])
+        ([3] if dim == 3 and form not in fx.SCALAR_FORMS else []) + [4]
     for ln in lanes:
         for mode in ((fx.SUM_COLOURED,) if ln == 4 else (fx.SUM_ELEMENT, fx.SUM_COLOURED)):
             plan.set_strategy(fx.SCATTER_PATCH, 63 if ln == 3 else 64, ln, mode)
