@@ -37,6 +37,25 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
+// Scheduling fences between a tile's evaluation products, its pointwise step and its
+// contraction products (the compiler then keeps each phase's instructions together instead
+// of interleaving the pointwise vector work into the matrix products).  Outputs are the
+// same bit for bit; the time is not, and the better schedule depends on the case, so it is
+// chosen per case from an A/B on MI355X (kernel us, fenced against interleaved; per 3e5
+// triangles / 1.5e5 tetrahedra): faster fenced -- mass 3D P6 771 -> 413, Helmholtz 2D P8
+// 746 -> 370, 3D P6 4487 -> 2818, Laplace 3D P6 3283 -> 2157, 2D P7 240 -> 191,
+// neo-Hookean 2D P8 920 -> 541, its VJP 1546 -> 1219, 3D P4 VJP 722 -> 569, St
+// Venant-Kirchhoff alike, elasticity and the hyperelastic forms 3D P5 3-5% -- and slower
+// fenced -- Helmholtz 3D P5 583 -> 1810, elasticity 3D P4 180 -> 193, the hyperelastic
+// forms 2D P6 and 3D P4 (action) 1-9%, their VJP 2D P7 3-4%; within 1% elsewhere.
+constexpr bool mfma_fence(int form, int dim, int k, bool vjp)
+{
+    if (scalar_form(form))
+        return dim == 2 ? k >= 7 : (k >= 5 && !(form == FEM_HELMHOLTZ && k == 5));
+    if (vjp) return (dim == 2 && k == 8) || (dim == 3 && k == 4);
+    return (dim == 2 && k == 8) || (dim == 3 && k == 5);
+}
+
 template <int FORM, int DIM, int K, bool VJP>
 __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
 {
@@ -50,6 +69,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
     constexpr int EVAL = NR * KS * 64;
     constexpr int CON = 4 * NR * MA * 64;
     constexpr bool SCALAR = scalar_form(FORM);
+    constexpr bool FENCE = mfma_fence(FORM, DIM, K, VJP);
     static_assert(!(SCALAR && VJP), "the scalar forms are linear: their VJP is the action");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -132,6 +152,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
     const double *__restrict__ mt = a.mtab;
 #pragma unroll 1
     for (int t = 0; t < a.nqt; ++t) {
+        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
         const double *tile = mt + (int64_t)t * TILE;
         // evaluation: G_rc (and the gradient of v for the VJP) on this tile's 16 points
         dvec4 acc[NR][NC], accv[VJP ? NR : 1][NC];
@@ -167,6 +188,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
             }
         }
         // the pointwise form at the lane's four points 16 t + 4 k + g of its cell
+        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
         const double *wt = tile + EVAL + CON;
         if constexpr (SCALAR) {
 #pragma unroll
@@ -210,6 +232,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
             }
         }
         // contraction: k-step (t, k) takes register k of every lane as its B operand
+        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
         const double *con = tile + EVAL;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -224,6 +247,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
                 }
     }
 
+    if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
     // sum the cell vectors into the patch's nodes, sub-colour by sub-colour (no two cells of
     // a colour share a node, and the four lanes of a cell hold different nodes: one writer
     // per address within a phase, so the order is fixed)
