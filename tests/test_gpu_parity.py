@@ -481,6 +481,39 @@ def test_batch_matches_oracle_and_per_mesh():
     b.close()
 
 
+def test_batch_matrix_core_scalar_forms():
+    """The batch's matrix-core variant for the scalar forms (mass P3 triangles, Helmholtz P2
+    and Laplace P1 tetrahedra, all set to the matrix-core kernel): each mesh against the
+    oracle and bitwise against its own fem_action."""
+    rng = np.random.default_rng(21)
+    meshes = [(fx.FORM_MASS, meshgen.unit_square(7, 3, 0.1, rng)),
+              (fx.FORM_MASS, meshgen.unit_square(4, 3, 0.1, rng)),
+              (fx.FORM_HELMHOLTZ, meshgen.unit_cube(3, 2, 0.05, rng)),
+              (fx.FORM_LAPLACE, meshgen.unit_cube(4, 1, 0.05, rng))]
+    plans, us, ys, refs = [], [], [], []
+    for form, mesh in meshes:
+        qd = qdeg(form, mesh.k)
+        plan = fx.Plan.from_mesh(form, mesh, qd)
+        plan.set_strategy(fx.SCATTER_PATCH, 64, 4, fx.SUM_COLOURED)
+        u = rng.uniform(-1, 1, mesh.n_node)
+        plans.append(plan)
+        us.append(gpu(u))
+        ys.append(torch.full_like(us[-1], 3.0))
+        refs.append(oracle.action(form, mesh, u, qd, family=plan.quad_family_name))
+    say("[batch mfma scalar] " + ", ".join(f"{f}:{m.n_cell}" for f, m in meshes))
+    b = fx.Batch(plans, us, ys)
+    assert b.n_groups == 3
+    for graph in (False, True, True):
+        for y in ys:
+            y.fill_(3.0)
+        b.run(graph=graph)
+        torch.cuda.synchronize()
+        for p, u, y, ref in zip(plans, us, ys, refs):
+            assert rel_err(y.cpu().numpy(), ref)[0] < TOL
+            assert torch.equal(y, p.action(u))
+    b.close()
+
+
 def test_batch_rebind_vectors():
     ws = _batch_meshes(n_mesh=4, seed=12)
     plans = [fx.Plan.from_mesh(w.form, w.mesh, w.quad_degree, w.params) for w in ws]
