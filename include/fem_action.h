@@ -128,8 +128,8 @@ int fem_plan_create(fem_plan **out, int form, int dim, int degree, int quad_degr
  *   geometry degree: isoparametric for degree 2, sub- or super-parametric otherwise).
  * det J is checked at every point of the rule (FEM_E_INVERTED where it is zero, not
  * finite, changes sign within a cell, or is negative in 2D); between the points the map is
- * not checked.  Curved plans run one lane per cell (FEM_E_UNSUPPORTED for lane splits) and
- * cannot join a batch.  Errors as fem_plan_create.
+ * not checked.  Curved plans run one lane per cell, or lane triples for the 3D vector forms
+ * (FEM_E_UNSUPPORTED for the other lane splits), and cannot join a batch.  Errors as fem_plan_create.
  */
 int fem_plan_create_curved(fem_plan **out, int form, int dim, int degree, int quad_degree,
                            int64_t n_gnode, const double *gcoords, int64_t n_cell,

@@ -627,15 +627,20 @@ __device__ __forceinline__ void cell_quadrature_pair(
 // The 3D vector forms with the three components of a cell on a lane triple (lanes 3g,
 // 3g+1, 3g+2 of a wavefront; `base` = 3g): lane c holds component c, evaluates row c of the
 // reference gradient, gathers the three rows from the triple by lane shuffles, evaluates
-// the (whole) pointwise form and accumulates row c of the stress.
-template <int FORM, int K, bool VJP>
+// the (whole) pointwise form and accumulates row c of the stress.  Curved cells (GEO = 2):
+// lane c holds coordinate c of the ten geometry nodes (gxc) and evaluates row c of J at each
+// point, the triple exchanging the rows as it does the gradient's; K and |det J| then come
+// per point from the whole J on every lane.
+template <int FORM, int K, bool VJP, int GEO = 1>
 __device__ __forceinline__ void cell_quadrature_triple(
     const double (&ul)[nloc_of(3, K)], const double (&vl)[VJP ? nloc_of(3, K) : 1], int c,
-    int base, const double (&Kinv)[3][3], double adet, const double *table, int nq, double lam,
-    double mu, double (&yl)[nloc_of(3, K)])
+    int base, const double (&Kinv)[3][3], double adet,
+    const double (&gxc)[GEO == 2 ? geom_nodes(3, 2) : 1], const double *table, int nq,
+    double lam, double mu, double (&yl)[nloc_of(3, K)])
 {
     constexpr int NLOC = nloc_of(3, K);
-    constexpr int REC = record_of(FORM, 3, NLOC);
+    constexpr int REC = record_of(FORM, 3, NLOC, GEO);
+    constexpr int GOFF = record_base(FORM, 3, NLOC);      // geometry gradients (GEO = 2)
     const FEMX_CONSTANT double *tab = (const FEMX_CONSTANT double *)table;
 #pragma unroll
     for (int n = 0; n < NLOC; ++n) yl[n] = 0.0;
@@ -658,11 +663,35 @@ __device__ __forceinline__ void cell_quadrature_triple(
                 gu[row][r] = __shfl(g[r], base + row);
                 if constexpr (VJP) gv[row][r] = __shfl(h[r], base + row);
             }
-        to_physical<3>(gu, Kinv, G);
+        double Kq[3][3], adq = adet;
+        if constexpr (GEO == 2) {
+            constexpr int NG = geom_nodes(3, 2);
+            const FEMX_CONSTANT double *tg = t + GOFF;
+            double jr[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int gn = 0; gn < NG; ++gn) acc = fma(gxc[gn], tg[r * NG + gn], acc);
+                jr[r] = acc;
+            }
+            double J[3][3];
+#pragma unroll
+            for (int row = 0; row < 3; ++row)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) J[row][r] = __shfl(jr[r], base + row);
+            adq = jacobian_inverse<3>(J, Kq);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) Kq[i][j] = Kinv[i][j];
+        }
+        to_physical<3>(gu, Kq, G);
         double H[3][3];
-        if constexpr (VJP) to_physical<3>(gv, Kinv, H);
+        if constexpr (VJP) to_physical<3>(gv, Kq, H);
         pointwise<FORM, 3, VJP>(G, H, lam, mu, S);
-        pull_back<3>(S, Kinv, t[3 * NLOC] * adet, T);
+        pull_back<3>(S, Kq, t[3 * NLOC] * adq, T);
         double tc[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) tc[r] = c == 0 ? T[0][r] : (c == 1 ? T[1][r] : T[2][r]);

@@ -215,6 +215,8 @@ bool pair_available(int form, int dim, int degree);
 bool curved_available(int form, int dim, int degree);
 bool batch_available(int form, int dim, int degree, int lanes, int sum_mode);
 bool triple_available(int form, int dim, int degree);
+// lane triples on P2-geometry cells (3D vector forms up to P4)
+bool curved_triple_available(int form, int dim, int degree);
 // the matrix-core patch kernel ("four lanes per cell": 16 cells per tile, each cell's points
 // and nodes over four lanes) of the vector forms on affine cells
 bool mfma_available(int form, int dim, int degree);

@@ -41,6 +41,7 @@ struct Kernels {
     BatchFn batch_prio[5];
     ColourFn colour_p2;   // P2-geometry cells: colour kernel and one-lane patch kernels
     PatchFn patch_p2[3];  // [sum mode 1..2]
+    PatchFn patch_p2_3[3];  // P2-geometry lane triples (3D vector forms), [sum mode 1..2]
 };
 
 // one per form, each in its own translation unit (they compile in parallel)
@@ -231,7 +232,8 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     static_assert(LPC == 1 || (LPC == 2 && DIM == 2 && !scalar_form(FORM)) ||
                       (LPC == 3 && DIM == 3 && !scalar_form(FORM)),
                   "lane split");
-    static_assert(GEO == 1 || LPC == 1, "P2-geometry cells run one lane per cell");
+    static_assert(GEO == 1 || LPC == 1 || LPC == 3,
+                  "P2-geometry cells run one lane per cell, or lane triples (3D vector forms)");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
@@ -267,10 +269,19 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
     const int64_t s = p * P + cl;
     const bool active = cl < P && s < a.n_cell;
     constexpr int CW = LPC == 1 ? NC : 1;     // components a lane holds
-    double Kinv[DIM][DIM], adet = 0.0, gx[geom_nodes(DIM, GEO)][DIM];
+    // curved lane triples: lane c keeps coordinate c of the geometry nodes only
+    constexpr bool TRI_GEO = LPC == 3 && GEO == 2;
+    double Kinv[DIM][DIM], adet = 0.0, gx[TRI_GEO ? 1 : geom_nodes(DIM, GEO)][DIM];
+    double gxc[TRI_GEO ? geom_nodes(DIM, GEO) : 1];
     int lid[NLOC];
     if (active) {
-        adet = gather_cell_geometry<DIM, GEO>(a.verts, a.stride, s, a.coords, Kinv, gx);
+        if constexpr (TRI_GEO) {
+#pragma unroll
+            for (int g = 0; g < geom_nodes(DIM, GEO); ++g)
+                gxc[g] = a.coords[(int64_t)a.verts[g * a.stride + s] * DIM + comp];
+        } else {
+            adet = gather_cell_geometry<DIM, GEO>(a.verts, a.stride, s, a.coords, Kinv, gx);
+        }
 #pragma unroll
         for (int n = 0; n < NLOC; ++n) lid[n] = a.lidx[n * a.stride + s];
     }
@@ -320,8 +331,8 @@ __device__ __forceinline__ void patch_body(const PatchArgs &a, int64_t p, int P)
                 u1[n] = ul[n][0];
                 if constexpr (VJP) v1[n] = vl[n][0];
             }
-            cell_quadrature_triple<FORM, K, VJP>(u1, v1, comp, base, Kinv, adet, a.tab, a.nq,
-                                                 a.lam, a.mu, y1);
+            cell_quadrature_triple<FORM, K, VJP, GEO>(u1, v1, comp, base, Kinv, adet, gxc, a.tab,
+                                                      a.nq, a.lam, a.mu, y1);
 #pragma unroll
             for (int n = 0; n < NLOC; ++n) yl[n][0] = y1[n];
         } else {
@@ -475,6 +486,10 @@ Kernels entry()
         k.colour_p2 = colour_kernel<FORM, DIM, K, VJP, 2>;
         k.patch_p2[SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_ELEMENT, 2>;
         k.patch_p2[SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, 1, SUM_COLOURED, 2>;
+        if constexpr (DIM == 3 && !scalar_form(FORM)) {
+            k.patch_p2_3[SUM_ELEMENT] = patch_kernel<FORM, DIM, K, VJP, 3, SUM_ELEMENT, 2>;
+            k.patch_p2_3[SUM_COLOURED] = patch_kernel<FORM, DIM, K, VJP, 3, SUM_COLOURED, 2>;
+        }
     }
     if constexpr (DIM == 2 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 2, FULL>(k);
     if constexpr (DIM == 3 && !scalar_form(FORM)) fill_lanes<FORM, DIM, K, VJP, 3, FULL>(k);

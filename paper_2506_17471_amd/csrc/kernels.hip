@@ -152,7 +152,9 @@ static const void *patch_fn(const Kernels &ks, int geom, int lanes, int sum_mode
 {
     if (prio) *prio = false;
     if (lanes < 1 || lanes > kMfmaLanes || sum_mode < 1 || sum_mode > 2) return nullptr;
-    if (geom == 2) return lanes == 1 ? (const void *)ks.patch_p2[sum_mode] : nullptr;
+    if (geom == 2)
+        return lanes == 1 ? (const void *)ks.patch_p2[sum_mode]
+                          : (lanes == 3 ? (const void *)ks.patch_p2_3[sum_mode] : nullptr);
     if (sum_mode == SUM_COLOURED && prio_usable((const void *)ks.patch_prio[lanes])) {
         if (prio) *prio = true;
         return (const void *)ks.patch_prio[lanes];
@@ -226,6 +228,11 @@ bool pair_available(int form, int dim, int degree)
 bool mfma_available(int form, int dim, int degree)
 {
     return lookup(form, dim, degree, false).patch[kMfmaLanes][SUM_COLOURED] != nullptr;
+}
+
+bool curved_triple_available(int form, int dim, int degree)
+{
+    return lookup(form, dim, degree, false).patch_p2_3[SUM_COLOURED] != nullptr;
 }
 
 bool triple_available(int form, int dim, int degree)

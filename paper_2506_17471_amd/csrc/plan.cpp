@@ -710,7 +710,19 @@ int default_sum_mode(const fem_plan *)
 // where one lane's cell vector would not fit its registers.
 int default_lanes(const fem_plan *p)
 {
-    if (p->geom == 2) return 1;    // curved cells: one-lane kernels only
+    if (p->geom == 2) {
+        // curved cells: one lane, or lane triples (3D vector forms) -- for elasticity from P4,
+        // where one lane spills (per 1.6e5 curved tetrahedra: 552 against 807 us), and for the
+        // hyperelastic forms where one lane's tangent spills (P3, P4), so that the default
+        // can take its VJP (their action is slower on triples there: neo-Hookean P3 322
+        // against 246 us, St Venant-Kirchhoff P4 1068 against 984)
+        if (!femx::curved_triple_available(p->form, p->dim, p->degree)) return 1;
+        if (p->form == FEM_ELASTICITY) return p->degree >= 4 ? 3 : 1;
+        if (femx::nonlinear_form(p->form) &&
+            femx::vjp_kernel_spills(p->form, p->dim, p->degree, false, 1, femx::SUM_COLOURED, 2))
+            return 3;
+        return 1;
+    }
     const bool mfma = femx::mfma_available(p->form, p->dim, p->degree) && p->nqt > 0;
     // the matrix-core kernel from P4 on tetrahedra, from P6 on triangles for the hyperelastic
     // forms and from P7 for elasticity, where it measured faster than the lane splits (per 2e5
@@ -926,8 +938,10 @@ void set_strategy(fem_plan *plan, int strategy, int patch_cells, int lanes_per_c
     if (lanes == kMfmaLanes && (plan->geom != 1 || !mfma_available(plan->form, plan->dim, plan->degree)))
         throw Error(FEM_E_UNSUPPORTED,
                     "the matrix-core kernel (four lanes per cell) exists for affine cells only");
-    if (lanes > 1 && plan->geom == 2)
-        throw Error(FEM_E_UNSUPPORTED, "curved cells run one lane per cell");
+    if (lanes > 1 && plan->geom == 2 &&
+        !(lanes == 3 && curved_triple_available(plan->form, plan->dim, plan->degree)))
+        throw Error(FEM_E_UNSUPPORTED, "curved cells run one lane per cell, or lane triples for "
+                                       "the 3D vector forms");
     if (lanes == 2 && !pair_available(plan->form, plan->dim, plan->degree))
         throw Error(FEM_E_UNSUPPORTED, "two lanes per cell exist for the 2D vector forms only");
     if (lanes == 3 && !triple_available(plan->form, plan->dim, plan->degree))

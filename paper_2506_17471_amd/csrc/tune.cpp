@@ -171,7 +171,22 @@ std::vector<Candidate> candidates(const fem_plan *p)
     // patch sizes grouped so that one layout build serves both sum modes
     for (int P : {64, 128, 256})
         for (int m : {SUM_ELEMENT, SUM_COLOURED}) cands.push_back({FEM_SCATTER_PATCH, P, 1, 0, m});
-    if (p->geom == 2) return cands;     // curved cells: one lane per cell
+    if (p->geom == 2) {
+        // curved cells: one lane per cell, or lane triples (3D vector forms); for the
+        // hyperelastic forms only the configurations whose tangent runs, where any does
+        if (curved_triple_available(p->form, p->dim, p->degree))
+            for (int P : {42, 63, 84})
+                for (int m : {SUM_ELEMENT, SUM_COLOURED}) cands.push_back({FEM_SCATTER_PATCH, P, 3, 0, m});
+        if (nonlinear_form(p->form)) {
+            std::vector<Candidate> ok;
+            for (const Candidate &c : cands)
+                if (!vjp_kernel_spills(p->form, p->dim, p->degree, c.strategy == FEM_SCATTER_COLOUR,
+                                       c.lanes, c.strategy == FEM_SCATTER_COLOUR ? 1 : c.sum_mode, 2))
+                    ok.push_back(c);
+            if (!ok.empty()) cands.swap(ok);
+        }
+        return cands;
+    }
     // the matrix-core kernel: 64-cell patches, coloured sums
     if (mfma_available(p->form, p->dim, p->degree) && p->nqt > 0)
         cands.push_back({FEM_SCATTER_PATCH, 64, kMfmaLanes, 0, SUM_COLOURED});

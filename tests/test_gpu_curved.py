@@ -80,8 +80,9 @@ def inputs(form, mesh, seed):
 CASES = [(f, 2, k) for f in range(6) for k in range(1, 7)] + \
         [(f, 3, k) for f in range(6) for k in range(1, 5)]
 STRATS = [(fx.SCATTER_PATCH, 0, 0, 0), (fx.SCATTER_PATCH, 64, 1, fx.SUM_ELEMENT),
-          (fx.SCATTER_PATCH, 128, 1, fx.SUM_COLOURED), (fx.SCATTER_COLOUR, 0, 0, 0)]
-STRAT_IDS = ["patch", "patch64e", "patch128c", "colour"]
+          (fx.SCATTER_PATCH, 128, 1, fx.SUM_COLOURED), (fx.SCATTER_COLOUR, 0, 0, 0),
+          (fx.SCATTER_PATCH, 42, 3, fx.SUM_COLOURED), (fx.SCATTER_PATCH, 63, 3, fx.SUM_ELEMENT)]
+STRAT_IDS = ["patch", "patch64e", "patch128c", "colour", "triple42c", "triple63e"]
 
 
 @pytest.mark.parametrize("strategy", STRATS, ids=STRAT_IDS)
@@ -93,6 +94,8 @@ def test_curved_action_and_vjp(form, dim, k, strategy):
     u, v = inputs(form, mesh, 70 + k)
     qd = 2 * k
     say(f"[curved] form={form} dim={dim} k={k} n={n} cells={mesh.n_cell} qd={qd} strat={strategy}")
+    if strategy[2] == 3 and (dim != 3 or form in fx.SCALAR_FORMS):
+        pytest.skip("lane triples exist for the 3D vector forms only")
     plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
     assert plan.geometry == 2
     plan.set_strategy(*strategy)
@@ -107,15 +110,25 @@ def test_curved_action_and_vjp(form, dim, k, strategy):
     assert emax < TOL and el2 < TOL, ("vjp", emax, el2)
 
 
-def test_curved_plan_rejects_lane_splits_and_batches():
+def test_curved_plan_lane_splits_and_batches():
+    """Curved cells run one lane per cell or (3D vector forms) lane triples; lane pairs, the
+    matrix-core kernel and batches are refused."""
     mesh = meshgen.curved(meshgen.make_mesh(3, 2, 3, None, np.random.default_rng(1)), 0.05)
     plan = fx.Plan.from_mesh(fx.FORM_ELASTICITY, mesh, 4, LAME)
-    assert plan.strategy()[2] == 1
+    plan.set_strategy(fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT)
+    assert plan.strategy()[2] == 3
     with pytest.raises(fx.FemError):
-        plan.set_strategy(fx.SCATTER_PATCH, 42, 3, fx.SUM_ELEMENT)
+        plan.set_strategy(fx.SCATTER_PATCH, 64, 4, fx.SUM_COLOURED)
     u = gpu(np.zeros(mesh.n_node * 3))
     with pytest.raises(fx.FemError):
         fx.Batch([plan], [u], [torch.empty_like(u)])
+    m2 = meshgen.curved(meshgen.make_mesh(2, 3, 3, None, np.random.default_rng(2)), 0.05)
+    p2 = fx.Plan.from_mesh(fx.FORM_ELASTICITY, m2, 4, LAME)
+    with pytest.raises(fx.FemError):
+        p2.set_strategy(fx.SCATTER_PATCH, 64, 2, fx.SUM_ELEMENT)
+    mass = fx.Plan.from_mesh(fx.FORM_MASS, mesh, 6)
+    with pytest.raises(fx.FemError):
+        mass.set_strategy(fx.SCATTER_PATCH, 42, 3, fx.SUM_COLOURED)
 
 
 def test_curved_set_quadrature_and_straight_geometry():
@@ -161,3 +174,27 @@ def test_curved_autograd_function_and_tuner():
     plan.set_timing(False)
     assert n == 3 and ms > 0
     assert rel_err(out.cpu().numpy(), yref)[0] < TOL
+
+
+@pytest.mark.parametrize("form,k", [(fx.FORM_NEOHOOKEAN, 3), (fx.FORM_SVK, 4), (fx.FORM_ELASTICITY, 4)])
+def test_curved_3d_default_takes_its_vjp(form, k):
+    """Curved 3D P3/P4 vector forms default to lane triples where one lane's tangent spills
+    (hyperelastic) or one lane spills (elasticity P4): the default configuration's tangent
+    runs (no scratch) and its action and VJP match the oracle; a tuned plan keeps a runnable
+    tangent."""
+    mesh = meshgen.curved(meshgen.make_mesh(3, 2, k, None, np.random.default_rng(60 + k)), 0.06)
+    u, v = inputs(form, mesh, 80 + k)
+    qd = 2 * k
+    plan = fx.Plan.from_mesh(form, mesh, qd, params_for(form))
+    assert plan.strategy()[2] == 3
+    assert plan.kernel_info(vjp=True)["scratch_bytes"] == 0
+    fam = plan.quad_family_name
+    y = plan.action(gpu(u)).cpu().numpy()
+    assert rel_err(y, oracle.action(form, mesh, u, qd, params_for(form), family=fam))[0] < TOL
+    g = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
+    assert rel_err(g, oracle.vjp(form, mesh, u, v, qd, params_for(form), family=fam))[0] < TOL
+    if form != fx.FORM_ELASTICITY:
+        plan.tune(gpu(u))
+        assert plan.kernel_info(vjp=True)["scratch_bytes"] == 0
+        g2 = plan.vjp(gpu(u), gpu(v)).cpu().numpy()
+        assert rel_err(g2, oracle.vjp(form, mesh, u, v, qd, params_for(form), family=fam))[0] < TOL
