@@ -70,6 +70,9 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
     constexpr int CON = 4 * NR * MA * 64;
     constexpr bool SCALAR = scalar_form(FORM);
     constexpr bool FENCE = mfma_fence(FORM, DIM, K, VJP);
+    // the contraction's fragments one k-step ahead, fenced: the 3D vector forms from P5 (NH
+    // P5 2224 -> 1510 us, elasticity P5 527 -> 445 per 1.5e5 tetrahedra; at P4 2-6% slower)
+    constexpr bool CPF = !SCALAR && DIM == 3 && K >= 5;
     static_assert(!(SCALAR && VJP), "the scalar forms are linear: their VJP is the action");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -163,22 +166,41 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
                 acc[r][c] = dvec4{0.0, 0.0, 0.0, 0.0};
                 if constexpr (VJP) accv[r][c] = dvec4{0.0, 0.0, 0.0, 0.0};
             }
+        // the next k-step's operands are loaded before this one's products (the vector forms:
+        // a fence keeps them there, nine products ahead of their use instead of the few the
+        // compiler leaves; measured 5-23% faster there, bitwise the same; the scalar forms,
+        // with one to four products per k-step, keep the compiler's order)
+        double afn[NR], b0n[NC], b1n[VJP ? NC : 1];
+        auto load_step = [&](int ks) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            double b0[NC], b1[VJP ? NC : 1];
+            for (int r = 0; r < NR; ++r) afn[r] = tile[(r * KS + ks) * 64 + lane];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if constexpr (HOLD) {
-                    b0[c] = bu[ks][c];
-                    if constexpr (VJP) b1[c] = bv[ks][c];
+                    b0n[c] = bu[ks][c];
+                    if constexpr (VJP) b1n[c] = bv[ks][c];
                 } else {
-                    b0[c] = gather(ks, c, false);
-                    if constexpr (VJP) b1[c] = gather(ks, c, true);
+                    b0n[c] = gather(ks, c, false);
+                    if constexpr (VJP) b1n[c] = gather(ks, c, true);
                 }
             }
+        };
+        load_step(0);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            double b0[NC], b1[VJP ? NC : 1], afc[NR];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                b0[c] = b0n[c];
+                if constexpr (VJP) b1[c] = b1n[c];
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) afc[r] = afn[r];
+            if (ks + 1 < KS) load_step(ks + 1);
+            if constexpr (!SCALAR) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const double af = tile[(r * KS + ks) * 64 + lane];
+                const double af = afc[r];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, b0[c], acc[r][c], 0, 0, 0);
@@ -234,17 +256,51 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
         // contraction: k-step (t, k) takes register k of every lane as its B operand
         if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
         const double *con = tile + EVAL;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
+        if constexpr (CPF) {
+            // the next k-step's fragments loaded before this one's products (fenced)
+            double cfn[NR][MA];
 #pragma unroll
             for (int r = 0; r < NR; ++r)
 #pragma unroll
-                for (int m = 0; m < MA; ++m) {
-                    const double af = con[((k * NR + r) * MA + m) * 64 + lane];
+                for (int m = 0; m < MA; ++m) cfn[r][m] = con[(r * MA + m) * 64 + lane];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c)
-                        y[c][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, acc[r][c][k], y[c][m], 0, 0, 0);
+            for (int k = 0; k < 4; ++k) {
+                double cf[NR][MA];
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+#pragma unroll
+                    for (int m = 0; m < MA; ++m) cf[r][m] = cfn[r][m];
+                if (k + 1 < 4) {
+#pragma unroll
+                    for (int r = 0; r < NR; ++r)
+#pragma unroll
+                        for (int m = 0; m < MA; ++m)
+                            cfn[r][m] = con[(((k + 1) * NR + r) * MA + m) * 64 + lane];
                 }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+#pragma unroll
+                    for (int m = 0; m < MA; ++m)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            y[c][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[r][m], acc[r][c][k],
+                                                                           y[c][m], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+#pragma unroll
+                    for (int m = 0; m < MA; ++m) {
+                        const double af = con[((k * NR + r) * MA + m) * 64 + lane];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            y[c][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, acc[r][c][k], y[c][m],
+                                                                           0, 0, 0);
+                    }
+        }
     }
 
     if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
