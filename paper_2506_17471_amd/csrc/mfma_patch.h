@@ -72,7 +72,10 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
     constexpr bool FENCE = mfma_fence(FORM, DIM, K, VJP);
     // the contraction's fragments one k-step ahead, fenced: the 3D vector forms from P5 (NH
     // P5 2224 -> 1510 us, elasticity P5 527 -> 445 per 1.5e5 tetrahedra; at P4 2-6% slower)
-    constexpr bool CPF = !SCALAR && DIM == 3 && K >= 5;
+    constexpr bool CPF = !SCALAR && DIM == 3 && K >= 5 && !(VJP && K >= 6);
+    // the evaluation's operand prefetch (below): every vector form but the tangents where the
+    // extra registers would spill (2D P3/P4 St Venant-Kirchhoff, 3D P6 hyperelastic)
+    constexpr bool EPF = !SCALAR && !(VJP && ((DIM == 2 && K <= 4) || (DIM == 3 && K >= 6)));
     static_assert(!(SCALAR && VJP), "the scalar forms are linear: their VJP is the action");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -166,10 +169,10 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
                 acc[r][c] = dvec4{0.0, 0.0, 0.0, 0.0};
                 if constexpr (VJP) accv[r][c] = dvec4{0.0, 0.0, 0.0, 0.0};
             }
-        // the next k-step's operands are loaded before this one's products (the vector forms:
-        // a fence keeps them there, nine products ahead of their use instead of the few the
-        // compiler leaves; measured 5-23% faster there, bitwise the same; the scalar forms,
-        // with one to four products per k-step, keep the compiler's order)
+        // the next k-step's operands are loaded before this one's products (EPF: a fence
+        // keeps them there, nine products ahead of their use instead of the few the compiler
+        // leaves; measured 5-23% faster for the vector forms, bitwise the same; the scalar
+        // forms, with one to four products per k-step, keep the compiler's order)
         double afn[NR], b0n[NC], b1n[VJP ? NC : 1];
         auto load_step = [&](int ks) {
 #pragma unroll
@@ -197,7 +200,7 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
 #pragma unroll
             for (int r = 0; r < NR; ++r) afc[r] = afn[r];
             if (ks + 1 < KS) load_step(ks + 1);
-            if constexpr (!SCALAR) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (EPF) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const double af = afc[r];
