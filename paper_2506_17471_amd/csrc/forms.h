@@ -549,8 +549,11 @@ __device__ __forceinline__ void cell_quadrature(
         // Two points per trip give the scheduler two independent pointwise chains (the
         // log and reciprocal sequences are long serial dependences) where the cell's
         // values and outputs leave room: affine forward actions with at most 42 of them.
-        // Larger cells, curved cells and the VJP run one point per trip.
-        if constexpr (!VJP && GEO == 1 && NLOC * DIM <= 42) {
+        // Larger cells, curved cells and the VJP run one point per trip, and so does P2
+        // tetrahedral elasticity: its linear law is a short chain, and the second point's
+        // registers would spill under that kernel's three-wave bound (28 bytes per lane).
+        if constexpr (!VJP && GEO == 1 && NLOC * DIM <= 42 &&
+                      !(FORM == FEM_ELASTICITY && DIM == 3 && K == 2)) {
 #pragma unroll 2
             for (int q = 0; q < nq; ++q) point(q);
         } else {
