@@ -71,10 +71,12 @@ __device__ __forceinline__ void mfma_body(const PatchArgs &a, int64_t p, int P)
     constexpr bool SCALAR = scalar_form(FORM);
     constexpr bool FENCE = mfma_fence(FORM, DIM, K, VJP);
     // the contraction's fragments one k-step ahead, fenced: the 3D vector forms from P5 (NH
-    // P5 2224 -> 1510 us, elasticity P5 527 -> 445 per 1.5e5 tetrahedra; at P4 2-6% slower)
+    // P5 2224 -> 1510 us, elasticity P5 527 -> 445 per 1.5e5 tetrahedra; at P4 2-6% slower),
+    // but not the 3D P6 tangents, which it would make spill
     constexpr bool CPF = !SCALAR && DIM == 3 && K >= 5 && !(VJP && K >= 6);
-    // the evaluation's operand prefetch (below): every vector form but the tangents where the
-    // extra registers would spill (2D P3/P4 St Venant-Kirchhoff, 3D P6 hyperelastic)
+    // the evaluation's operand prefetch (below): every vector form but the 2D tangents up to
+    // P4 (St Venant-Kirchhoff's spilled with it at P3/P4; the vector kernels are the default
+    // there) and the 3D P6 tangents, which it would make spill
     constexpr bool EPF = !SCALAR && !(VJP && ((DIM == 2 && K <= 4) || (DIM == 3 && K >= 6)));
     static_assert(!(SCALAR && VJP), "the scalar forms are linear: their VJP is the action");
     extern __shared__ double lds[];
