@@ -437,6 +437,48 @@ struct PatchLayout {
     std::vector<uint8_t> colour, patch_ncol;
 };
 
+// DSatur colouring (Brelaz 1979) of the n <= 256 cells of one patch, two cells conflicting
+// when they share one of the U local nodes (node(i, a): local node a of cell i): the next cell
+// is the uncoloured one whose neighbours hold the most distinct colours (ties: more
+// neighbours, then the earlier cell), given the smallest colour its neighbours leave free.
+// Returns the number of colours, or 65 when 64 do not suffice.
+template <class NodeOf>
+int dsatur_colours(int n, int U, int nloc, NodeOf node, int *cols)
+{
+    constexpr int W = 4;                              // 256 cells as four 64-bit words
+    std::vector<uint64_t> at((size_t)U * W, 0);       // cells holding each local node
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < nloc; ++a) at[(size_t)node(i, a) * W + (i >> 6)] |= uint64_t(1) << (i & 63);
+    std::vector<uint64_t> adj((size_t)n * W, 0);
+    std::vector<int> deg((size_t)n, 0);
+    for (int i = 0; i < n; ++i) {
+        uint64_t *r = &adj[(size_t)i * W];
+        for (int a = 0; a < nloc; ++a)
+            for (int w = 0; w < W; ++w) r[w] |= at[(size_t)node(i, a) * W + w];
+        r[i >> 6] &= ~(uint64_t(1) << (i & 63));
+        for (int w = 0; w < W; ++w) deg[i] += __builtin_popcountll(r[w]);
+    }
+    std::vector<uint64_t> sat((size_t)n, 0);          // colours held by a cell's neighbours
+    for (int i = 0; i < n; ++i) cols[i] = -1;
+    int ncol = 0;
+    for (int step = 0; step < n; ++step) {
+        int best = -1, bs = -1, bd = -1;
+        for (int i = 0; i < n; ++i) {
+            if (cols[i] >= 0) continue;
+            const int si = __builtin_popcountll(sat[i]);
+            if (si > bs || (si == bs && deg[i] > bd)) { best = i; bs = si; bd = deg[i]; }
+        }
+        if (sat[best] == ~uint64_t(0)) return 65;
+        const int c = __builtin_ctzll(~sat[best]);
+        cols[best] = c;
+        ncol = std::max(ncol, c + 1);
+        const uint64_t *r = &adj[(size_t)best * W];
+        for (int w = 0; w < W; ++w)
+            for (uint64_t m = r[w]; m; m &= m - 1) sat[(w << 6) + __builtin_ctzll(m)] |= uint64_t(1) << c;
+    }
+    return ncol;
+}
+
 PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int32_t *cell_verts,
                               const int32_t *cell_nodes, int P)
 {
@@ -514,14 +556,21 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
             auto hi = node_count[nd] == 1 ? nodes.begin() + nint : nodes.end();
             return (int)(std::lower_bound(lo, hi, nd) - nodes.begin());
         };
-        // sub-colours: greedy first-fit over the patch's cells in Morton order; the cells are
-        // then stably sorted by colour, so that the lanes of a wavefront share one or two
-        // colours and skip the other colours' accumulation phases (the node sums still run
-        // in colour order, so the result does not depend on this permutation)
+        // sub-colours: greedy first-fit over the patch's cells in Morton order, replaced by
+        // DSatur's colouring of the same cells where that needs at least two colours fewer.
+        // Each colour is a barrier-separated accumulation phase; on the 256-cell patches of
+        // the structured tetrahedral meshes first-fit takes 26-31 colours and DSatur the 24
+        // that the 24 cells around a vertex force, while a saving of one colour measured
+        // neutral. The cells are then stably sorted by colour, so that the lanes of a
+        // wavefront share one or two colours and skip the other colours' accumulation
+        // phases (the node sums still run in colour order, so the result does not depend
+        // on this permutation)
         used.assign((size_t)U, 0);
         int ncol = 0;
         int cols[256], perm[256];
-        for (int64_t s = c0; s < c1; ++s) {
+        const int n_in = (int)(c1 - c0);
+        bool ff_ok = true;
+        for (int64_t s = c0; s < c1 && ff_ok; ++s) {
             const int64_t c = L.order[s];
             uint64_t forbid = 0;
             int lids[256];
@@ -529,13 +578,24 @@ PatchLayout make_patch_layout(const fem_plan *p, const double *coords, const int
                 lids[a] = local(cell_nodes[c * nloc + a]);
                 forbid |= used[lids[a]];
             }
-            if (forbid == ~uint64_t(0)) throw Error(FEM_E_UNSUPPORTED, "a patch needs more than 64 colours");
+            if (forbid == ~uint64_t(0)) { ff_ok = false; break; }
             const int col = __builtin_ctzll(~forbid);
             cols[s - c0] = col;
             ncol = std::max(ncol, col + 1);
             for (int a = 0; a < nloc; ++a) used[lids[a]] |= uint64_t(1) << col;
         }
-        const int n_in = (int)(c1 - c0);
+        {
+            int dcols[256];
+            const int dn = dsatur_colours(n_in, U, nloc, [&](int i, int a) {
+                return local(cell_nodes[L.order[c0 + i] * nloc + a]);
+            }, dcols);
+            if (dn <= 64 && (!ff_ok || dn + 2 <= ncol)) {
+                ncol = dn;
+                for (int i = 0; i < n_in; ++i) cols[i] = dcols[i];
+                ff_ok = true;
+            }
+        }
+        if (!ff_ok) throw Error(FEM_E_UNSUPPORTED, "a patch needs more than 64 colours");
         for (int i = 0; i < n_in; ++i) perm[i] = i;
         std::stable_sort(perm, perm + n_in, [&](int x, int y) { return cols[x] < cols[y]; });
         {
