@@ -197,6 +197,16 @@ def test_patch_layout_valid(form, dim, n, k, P):
     assert st["patch_node_pairs"] == m.n_node + st["partial_slots"] - st["shared_nodes"]
 
 
+def test_tetrahedral_patch_sub_colours_near_vertex_bound():
+    # the 24 tetrahedra around an interior vertex of the structured cube mesh need 24 colours;
+    # first-fit in Morton order takes up to 31 on 256-cell patches, and with DSatur's colouring
+    # kept where it saves two or more no patch of this mesh needs more than 26; the layout
+    # check also validates the colouring (no node twice within a colour)
+    m = meshgen.make_mesh(3, 16, 2, None, np.random.default_rng(16))
+    st = fx.check_patch_layout(1, m, 256)
+    assert 24 <= st["max_colours"] <= 26
+
+
 def test_patch_layout_rejects_bad_size():
     m = meshgen.unit_square(4, 2)
     with pytest.raises(fx.FemError):
