@@ -201,6 +201,10 @@ size_t patch_lds_bytes(int form, int dim, int degree, bool vjp, int patch, int m
 size_t patch_lds_a(int form, int dim, int degree, bool vjp, int patch, int max_nodes, int sum_mode,
                    int lanes = 1);
 // start / stop (optional): events the dispatch itself stamps at the kernel's start and end
+// The pipelined mass patch kernel runs this plan's action (launch_patch takes it), and
+// its compiled registers and scratch bytes.
+bool mass_pipe_used(const fem_plan &p, bool vjp);
+int mass_pipe_info(const fem_plan &p, int *regs, int *scratch);
 hipError_t launch_patch(const fem_plan &p, const PatchArgs &a, bool vjp, hipStream_t s,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // the hyperelastic forms: nonlinear residuals whose VJP is a tangent action at u

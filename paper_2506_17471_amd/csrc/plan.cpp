@@ -1425,6 +1425,12 @@ int fem_plan_kernel_info(const fem_plan *plan, int vjp, int *regs, int *scratch_
         check_plan(plan);
         const bool nl_vjp = vjp && femx::nonlinear_form(plan->form);
         const bool colour = plan->strategy == femx::STRAT_COLOUR || plan->patch == 0;
+        if (!colour && femx::mass_pipe_used(*plan, nl_vjp)) {
+            if (femx::mass_pipe_info(*plan, regs, scratch_bytes) != 0)
+                throw femx::Error(FEM_E_HIP, "kernel attributes unavailable");
+            if (wave_priority) *wave_priority = 0;
+            return;
+        }
         if (femx::kernel_info(plan->form, plan->dim, plan->degree, nl_vjp, colour, plan->lanes,
                               plan->sum_mode, plan->geom, regs, scratch_bytes, wave_priority) != 0)
             throw femx::Error(FEM_E_HIP, "kernel attributes unavailable");
