@@ -259,7 +259,10 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *                       nodal values in LDS and sums its cells' vectors into the patch's
  *                       nodes in a fixed order; nodes no other patch holds are stored, the
  *                       others leave as partial sums that a second, small kernel adds in
- *                       patch order.  The default.
+ *                       patch order.  The default.  The P2 mass form on triangles with
+ *                       256-cell coloured patches runs a pipelined variant: as many
+ *                       workgroups as stay resident take the patches in turn, the next
+ *                       patch's loads in flight during this one's work (same results).
  *   lanes_per_cell  1; 2 (2D vector forms: lane c of a pair owns component c); 3 (3D vector
  *                   forms: lane triples, 21 per wavefront); 4 (affine cells, every form:
  *                   the FP64 matrix-core kernel, where both contractions of the
@@ -270,8 +273,9 @@ int fem_plan_set_block(fem_plan *plan, int cells_per_block);
  *                   21, 42, 63 or 84 with 3; 64 with 4.
  *   sum_mode        FEM_SUM_ELEMENT: every cell vector to an LDS element buffer, each node
  *                   summing its slots in ascending (cell, local node); FEM_SUM_COLOURED:
- *                   cells greedily coloured inside the patch accumulate into an LDS node
- *                   buffer colour by colour (smaller LDS, one barrier per colour).
+ *                   cells coloured inside the patch (first-fit, or DSatur where that
+ *                   needs two colours fewer) accumulate into an LDS node buffer colour by
+ *                   colour (smaller LDS, one barrier per colour).
  *   0 for lanes_per_cell, patch_cells or sum_mode picks the plan's default (three lanes
  *   for 3D vector forms of degree >= 3 when the patch size allows it, one otherwise;
  *   coloured sums; 42 cells for lane triples, else the largest patch whose element buffer
